@@ -1,0 +1,126 @@
+"""Derivatives, pseudo-time step and monitors (oracle; test infrastructure).
+
+* ``jvp``: J_U v + J_b dbr, the exact directional derivative of the residual
+  (forward-mode automatic differentiation of ``mhd.residual``).  Branches
+  (min/max picks, |v_n|, the clamp under the square root) follow the values.
+* ``vjp``: J_U^T w and J_b^T w by reverse mode on the same function.
+* ``local_dt``: the backward-Euler diagonal V_c/dt_c = sum_f s_f |S_f| / CFL,
+  i.e. dt_c = CFL V_c / sum_f s_f |S_f| with s_f the Rusanov speed.
+* ``eq2``: the residual monitor of Eq. 2, log10 sqrt(sum_i (a_i^t - a_i^{t+1})^2),
+  per variable.
+* ``gmres``: unrestarted GMRES(m), x0 = 0, modified Gram-Schmidt, Givens
+  least squares, for the implicit step (D + J) x = -R (Section 2.1: backward
+  Euler with large CFL).
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import mhd
+from .grid import Grid
+
+DT = torch.float64
+
+
+def jvp(grid: Grid, U, br, prm, v, dbr=None, cells=None):
+    if dbr is None:
+        dbr = torch.zeros_like(br)
+
+    def f(U_, br_):
+        return mhd.residual(grid, U_, br_, prm, cells)
+
+    R, Jv = torch.func.jvp(f, (U, br), (v, dbr))
+    return Jv, R
+
+
+def vjp(grid: Grid, U, br, prm, w, cells=None):
+    """Returns (gU (9, ncells), gbr (6N^2,)) = (J_U^T w, J_b^T w).
+
+    With ``cells``, w holds the weights of those cells only (9, len(cells))."""
+    U_ = U.detach().clone().requires_grad_(True)
+    b_ = br.detach().clone().requires_grad_(True)
+    R = mhd.residual(grid, U_, b_, prm, cells)
+    gU, gb = torch.autograd.grad((R * w).sum(), (U_, b_), allow_unused=True)
+    if gb is None:
+        gb = torch.zeros_like(br)
+    return gU, gb
+
+
+def face_speeds(grid: Grid, U, br, prm, cells=None):
+    """Per target cell: Rusanov speeds s (n, 6) and face areas |S| (n, 6)."""
+    _, (s, area) = mhd.residual(grid, U, br, prm, cells, return_speeds=True)
+    return s, area
+
+
+def local_dt_diag(grid: Grid, U, br, prm, cfl, cells=None):
+    """V_c / dt_c = (sum over faces of s_f |S_f|) / CFL."""
+    s, area = face_speeds(grid, U, br, prm, cells)
+    return (s * area).sum(1) / cfl
+
+
+def eq2(a, b):
+    """Eq. 2 per variable: log10 of the 2-norm of a - b over cells."""
+    d = (a - b)
+    return torch.log10(torch.sqrt((d * d).sum(-1)))
+
+
+def gmres(matvec, rhs, m: int = 30, tol: float = 0.0):
+    """Unrestarted GMRES(m) from x0 = 0 with modified Gram-Schmidt.
+
+    Returns x and the list of relative residual norms |r_j| / |rhs| after
+    each iteration j = 1..m (from the Givens-rotated least-squares system)."""
+    beta = torch.linalg.norm(rhs)
+    Vs = [rhs / beta]
+    H = torch.zeros(m + 1, m, dtype=DT)
+    cs = torch.zeros(m, dtype=DT)
+    sn = torch.zeros(m, dtype=DT)
+    gvec = torch.zeros(m + 1, dtype=DT)
+    gvec[0] = beta
+    hist = []
+    k_done = 0
+    for j in range(m):
+        w = matvec(Vs[j])
+        for i in range(j + 1):
+            H[i, j] = (w * Vs[i]).sum()
+            w = w - H[i, j] * Vs[i]
+        H[j + 1, j] = torch.linalg.norm(w)
+        for i in range(j):
+            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+            H[i, j] = t
+        den = math.hypot(float(H[j, j]), float(H[j + 1, j]))
+        cs[j] = H[j, j] / den
+        sn[j] = H[j + 1, j] / den
+        H[j, j] = den
+        H[j + 1, j] = 0.0
+        gvec[j + 1] = -sn[j] * gvec[j]
+        gvec[j] = cs[j] * gvec[j]
+        hist.append(float(abs(gvec[j + 1]) / beta))
+        k_done = j + 1
+        if float(H[j + 1, j]) == 0.0 and j + 1 < m:
+            pass
+        nrm = torch.linalg.norm(w)
+        if nrm == 0 or hist[-1] <= tol:
+            break
+        Vs.append(w / nrm)
+    y = torch.linalg.solve_triangular(H[:k_done, :k_done], gvec[:k_done, None], upper=True)[:, 0]
+    x = torch.zeros_like(rhs)
+    for i in range(k_done):
+        x = x + y[i] * Vs[i]
+    return x, hist
+
+
+def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None):
+    """One backward-Euler pseudo-time step: (D + J) x = -R, U <- U + x."""
+    R = mhd.residual(grid, U, br, prm)
+    if diag is None:
+        diag = local_dt_diag(grid, U, br, prm, cfl)
+
+    def A(x):
+        Jx, _ = jvp(grid, U, br, prm, x)
+        return diag[None, :] * x + Jx
+
+    x, hist = gmres(A, -R, m)
+    return U + x, hist, R
