@@ -141,7 +141,9 @@ class Grid:
         xc, _, xf, S = self.cell_geometry(cells)
         nhat = S / torch.linalg.norm(S, dim=-1, keepdim=True)
         h = ((xf - xc[:, None]) * nhat).sum(-1, keepdim=True)
-        y = xf + 0.5 * h * nhat                                  # just outside
+        # a point just across the face: the offset is tiny so that it stays in
+        # the adjacent cell however thick the cells are
+        y = xf + 1e-6 * h * nhat
         p, a, b = locate_panel(y)
         step = (math.pi / 2) / N
         i = torch.floor((torch.atan(a) + math.pi / 4) / step).long().clamp(0, N - 1)
