@@ -1,0 +1,128 @@
+/*
+ * cfv.h -- C ABI of the MI355X coronal finite-volume MHD library.
+ *
+ * The library evaluates, on one GPU and in FP64, the finite-volume residual
+ * of ideal MHD with hyperbolic divergence cleaning on a spherical shell (the
+ * discretisation of Brchnelova et al., "To E or not to E", Section 2.1 and
+ * Eqs. 14-17), with the paper's low-E inner boundary (Section 3.2, Eq. 25)
+ * and the Table 2 outer ghost laws (Section 4.1), its exact Jacobian-vector
+ * product and its adjoint (vector-Jacobian product), and the pieces of the
+ * implicit backward-Euler pseudo-time step (Section 2.1).
+ *
+ * Conventions
+ *  - Every function returns cfv_status (0 = CFV_OK).  On failure
+ *    cfv_last_error() returns a thread-local message.  No C++ exception
+ *    crosses this boundary.
+ *  - Device buffers are owned by the caller and passed as plain pointers to
+ *    FP64 data on the current device.  The library owns its grid tables, the
+ *    B_r map copy and its workspaces (allocated at cfv_ctx_create).
+ *  - All device work is enqueued asynchronously on the hipStream_t given;
+ *    only the *_to_host functions synchronise.
+ *  - State layout (SoA): U[v*ncells + c] with v = 0..8 the conservative
+ *    variables (rho, rho vx, rho vy, rho vz, Bx, By, Bz, E, psi), nondimensional
+ *    (rho_ref, B_ref of Eq. 1, V_ref = B_ref/sqrt(mu0 rho_ref), lengths in R_sun).
+ *  - Cell order c = ((p*Nr + k)*N + j)*N + i over 6 cubed-sphere panels p,
+ *    radial layers k and angular indices j, i.  The B_r map has 6N^2 values in
+ *    the order (p*N + j)*N + i (one per inner boundary face).
+ *  - Residual R is the integrated form: R_c = sum over faces of the outward
+ *    numerical flux times the face area minus V_c S(U_c), so dU/dt = -R/V.
+ */
+#ifndef CFV_H
+#define CFV_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cfv_status;
+enum {
+  CFV_OK = 0,
+  CFV_ERR_ARG = 1,          /* null pointer, bad size or bad parameter */
+  CFV_ERR_SIZE = 2,         /* a length does not match the grid */
+  CFV_ERR_HIP = 3,          /* a HIP runtime call failed */
+  CFV_ERR_NONPHYSICAL = 4,  /* non-positive density or pressure met */
+  CFV_ERR_NOT_CONVERGED = 5,
+  CFV_ERR_ALLOC = 6         /* device or host allocation failed */
+};
+
+typedef struct cfv_grid cfv_grid;
+typedef struct cfv_ctx cfv_ctx;
+
+/* Physical and numerical parameters (nondimensional). */
+typedef struct {
+  double gamma;      /* polytropic index */
+  double c_h;        /* divergence-cleaning speed (Section 3.3: 1) */
+  double G;          /* GM_sun/(R_sun V_ref^2): gravity g = -G x/|x|^3 */
+  double vr_star;    /* inner radial outflow, Eq. 22: 1935.07 m/s / V_ref */
+  double rho_b;      /* inner boundary density */
+  double T_b;        /* inner boundary temperature as p/rho */
+  int32_t limiter;   /* 0: none, 1: Barth-Jespersen */
+  int32_t inner_mode;/* 0: low-E inner boundary (Section 3.2, Eq. 25) */
+  double outer_exp[8]; /* outer ghost powers e in G = I (r_I/r_G)^e for
+                          rho, B_r, B_theta, B_phi, V_r, V_theta, V_phi, p (Table 2) */
+  int32_t outer_vr_mass;  /* 1: V_r r^2 rho = const instead of outer_exp[4] */
+  int32_t outer_psi_zero; /* 1: psi_b = 0 (G = -I); 0: zero gradient (G = I) */
+} cfv_params;
+
+/* Thread-local message of the last failure (empty string if none). */
+const char* cfv_last_error(void);
+
+/* ----------------------------------------------------------------- grid --
+ * Cubed-sphere shell with 6 N x N panels and Nr radial layers between the
+ * Nr+1 strictly increasing radii r_nodes (host array, copied).  Host only:
+ * builds topology (closed-form panel-edge table) and the corner directions. */
+cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_grid** out);
+void cfv_grid_destroy(cfv_grid* g);
+/* ncells = 6N^2 Nr; nfaces = 6N^2(Nr+1) + 12N^2 Nr; nbnd = 6N^2 per boundary. */
+cfv_status cfv_grid_sizes(const cfv_grid* g, int64_t* ncells, int64_t* nfaces, int64_t* nbnd);
+/* Canonical face list (host arrays of length nfaces): cells in increasing
+ * order, local faces (r-, r+, xi-, xi+, eta-, eta+); a face is listed by the
+ * cell whose neighbour is a ghost or has a larger index.  R of a boundary
+ * face is a ghost id: ncells + col (inner) or ncells + 6N^2 + col (outer).
+ * kind: 0 interior, 1 inner boundary, 2 outer boundary. */
+cfv_status cfv_grid_faces_to_host(const cfv_grid* g, int64_t* L, int64_t* R, int8_t* kind);
+
+/* ------------------------------------------------------------- context --
+ * Binds a grid and parameters to the current HIP device: uploads the grid
+ * tables and allocates the workspaces.  The grid must outlive the context. */
+cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** out);
+void cfv_ctx_destroy(cfv_ctx* ctx);
+/* Copy the inner-boundary B_r map (device array of n = 6N^2 values). */
+cfv_status cfv_set_inner_br(cfv_ctx* ctx, const double* br_dev, int64_t n, hipStream_t s);
+
+/* Geometry as the kernels see it (device outputs): cell centroids xc[3c+d],
+ * volumes vol[c], and per (cell, local face) the face centroid xf[(6c+f)*3+d]
+ * and the vector area S outward from the cell (the face owner's numbers). */
+cfv_status cfv_geometry(cfv_ctx* ctx, double* xc, double* vol, double* xf, double* S, hipStream_t s);
+
+/* ----------------------------------------------------------- hot path --
+ * R = R(U, B_r): ghost fill, reconstruction, Rusanov flux, gravity. */
+cfv_status cfv_residual(cfv_ctx* ctx, const double* U, double* R, hipStream_t s);
+/* Jv = J_U v + J_b dbr (dbr may be NULL: no map direction); when R is not
+ * NULL the residual is written too.  Exact forward linearisation; branches
+ * follow the primal values. */
+cfv_status cfv_jvp(cfv_ctx* ctx, const double* U, const double* v, const double* dbr, double* Jv, double* R,
+                   hipStream_t s);
+/* gU = J_U^T w and (when gbr is not NULL) gbr = J_b^T w (6N^2 values).
+ * Deterministic: no floating-point atomics. */
+cfv_status cfv_vjp(cfv_ctx* ctx, const double* U, const double* w, double* gU, double* gbr, hipStream_t s);
+/* Backward-Euler diagonal V_c/dt_c = sum_f s_f |S_f| / cfl (s_f Rusanov speed). */
+cfv_status cfv_local_dt(cfv_ctx* ctx, const double* U, double cfl, double* diag, hipStream_t s);
+
+/* --------------------------------------------------------- reductions --
+ * out9[v] = sqrt(sum_c (a - b)^2) per variable (b may be NULL): the Eq. 2
+ * monitor before the log10.  Fixed reduction order (deterministic). */
+cfv_status cfv_norms(cfv_ctx* ctx, const double* a, const double* b, double* out9_dev, hipStream_t s);
+/* out[i] = <V_i, w> for k vectors V_i stored back to back (9*ncells each). */
+cfv_status cfv_dots(cfv_ctx* ctx, const double* V, int32_t k, const double* w, double* out_dev, hipStream_t s);
+/* y = a*x + b*y over n values (a, b scalars from the host). */
+cfv_status cfv_axpby(cfv_ctx* ctx, int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFV_H */

@@ -1,0 +1,204 @@
+"""ctypes binding of libcfv.so with the C ABI's names (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts torch
+tensors to device pointers and streams.  There is no fallback: if the built
+library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .params import Params
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfv.so")
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class CfvParams(ctypes.Structure):
+    _fields_ = [("gamma", c_double), ("c_h", c_double), ("G", c_double), ("vr_star", c_double),
+                ("rho_b", c_double), ("T_b", c_double), ("limiter", c_int32), ("inner_mode", c_int32),
+                ("outer_exp", c_double * 8), ("outer_vr_mass", c_int32), ("outer_psi_zero", c_int32)]
+
+
+class CfvError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libcfv.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CfvError(f"{LIB_PATH} is missing: build it with `python -m paper_2209_04481_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "cfv_last_error": ([], ctypes.c_char_p),
+        "cfv_grid_create": ([c_int32, c_int32, P, ctypes.POINTER(P)], c_int32),
+        "cfv_grid_destroy": ([P], None),
+        "cfv_grid_sizes": ([P, P, P, P], c_int32),
+        "cfv_grid_faces_to_host": ([P, P, P, P], c_int32),
+        "cfv_ctx_create": ([P, ctypes.POINTER(CfvParams), ctypes.POINTER(P)], c_int32),
+        "cfv_ctx_destroy": ([P], None),
+        "cfv_set_inner_br": ([P, P, c_int64, P], c_int32),
+        "cfv_geometry": ([P, P, P, P, P, P], c_int32),
+        "cfv_residual": ([P, P, P, P], c_int32),
+        "cfv_jvp": ([P, P, P, P, P, P, P], c_int32),
+        "cfv_vjp": ([P, P, P, P, P, P], c_int32),
+        "cfv_local_dt": ([P, P, c_double, P, P], c_int32),
+        "cfv_norms": ([P, P, P, P, P], c_int32),
+        "cfv_dots": ([P, P, c_int32, P, P, P], c_int32),
+        "cfv_axpby": ([P, c_int64, c_double, P, c_double, P, P], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != 0:
+        raise CfvError(f"cfv status {status}: {lib().cfv_last_error().decode()}")
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise CfvError("expected a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise CfvError("expected a contiguous float64 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Grid:
+    """Cubed-sphere shell grid (host topology): cfv_grid_*."""
+
+    def __init__(self, N: int, Nr: int, r_nodes):
+        r = np.ascontiguousarray(np.asarray(r_nodes, dtype=np.float64))
+        if r.size != Nr + 1:
+            raise CfvError("r_nodes must have Nr + 1 entries")
+        self.N, self.Nr = int(N), int(Nr)
+        self.r_nodes = r
+        h = c_void_p()
+        check(lib().cfv_grid_create(self.N, self.Nr, r.ctypes.data_as(c_void_p), ctypes.byref(h)))
+        self._h = h
+        nc, nf, nb = c_int64(), c_int64(), c_int64()
+        check(lib().cfv_grid_sizes(h, ctypes.byref(nc), ctypes.byref(nf), ctypes.byref(nb)))
+        self.ncells, self.nfaces, self.nb = nc.value, nf.value, nb.value
+
+    def faces(self):
+        L = np.empty(self.nfaces, np.int64)
+        R = np.empty(self.nfaces, np.int64)
+        K = np.empty(self.nfaces, np.int8)
+        check(lib().cfv_grid_faces_to_host(self._h, L.ctypes.data_as(c_void_p), R.ctypes.data_as(c_void_p),
+                                           K.ctypes.data_as(c_void_p)))
+        return L, R, K
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cfv_grid_destroy(h)
+            self._h = None
+
+
+class Context:
+    """A grid and parameters bound to the current GPU: cfv_ctx_* and the
+    stream-ordered entry points.  Tensors are float64 CUDA tensors in the
+    SoA layout [9, ncells]."""
+
+    def __init__(self, grid: Grid, params: Params | None = None):
+        self.grid = grid
+        self.params = params or Params()
+        p = self.params
+        cp = CfvParams(p.gamma, p.c_h, p.G, p.vr_star, p.rho_b, p.T_b, int(p.limiter), int(p.inner_mode),
+                       (c_double * 8)(*[float(x) for x in p.outer_exp]), int(bool(p.outer_vr_mass)),
+                       int(bool(p.outer_psi_zero)))
+        h = c_void_p()
+        check(lib().cfv_ctx_create(grid._h, ctypes.byref(cp), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cfv_ctx_destroy(h)
+            self._h = None
+
+    # ---- helpers
+    def _new(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device="cuda")
+
+    def _state(self, t, name):
+        if tuple(t.shape) != (9, self.grid.ncells):
+            raise CfvError(f"{name} must have shape (9, {self.grid.ncells})")
+        return _ptr(t)
+
+    # ---- entry points
+    def set_inner_br(self, br, stream=None):
+        check(lib().cfv_set_inner_br(self._h, _ptr(br), br.numel(), _stream(stream)))
+
+    def geometry(self, stream=None):
+        nc = self.grid.ncells
+        xc, vol, xf, S = self._new(nc, 3), self._new(nc), self._new(nc, 6, 3), self._new(nc, 6, 3)
+        check(lib().cfv_geometry(self._h, _ptr(xc), _ptr(vol), _ptr(xf), _ptr(S), _stream(stream)))
+        return xc, vol, xf, S
+
+    def residual(self, U, out=None, stream=None):
+        R = out if out is not None else self._new(9, self.grid.ncells)
+        check(lib().cfv_residual(self._h, self._state(U, "U"), self._state(R, "R"), _stream(stream)))
+        return R
+
+    def jvp(self, U, v, dbr=None, out=None, R=None, stream=None):
+        Jv = out if out is not None else self._new(9, self.grid.ncells)
+        check(lib().cfv_jvp(self._h, self._state(U, "U"), self._state(v, "v"), _ptr(dbr), self._state(Jv, "Jv"),
+                            None if R is None else self._state(R, "R"), _stream(stream)))
+        return Jv
+
+    def vjp(self, U, w, out=None, gbr=None, want_br=True, stream=None):
+        gU = out if out is not None else self._new(9, self.grid.ncells)
+        if gbr is None and want_br:
+            gbr = self._new(self.grid.nb)
+        check(lib().cfv_vjp(self._h, self._state(U, "U"), self._state(w, "w"), self._state(gU, "gU"),
+                            _ptr(gbr), _stream(stream)))
+        return gU, gbr
+
+    def local_dt(self, U, cfl, out=None, stream=None):
+        d = out if out is not None else self._new(self.grid.ncells)
+        check(lib().cfv_local_dt(self._h, self._state(U, "U"), float(cfl), _ptr(d), _stream(stream)))
+        return d
+
+    def norms(self, a, b=None, out=None, stream=None):
+        o = out if out is not None else self._new(9)
+        check(lib().cfv_norms(self._h, self._state(a, "a"), None if b is None else self._state(b, "b"), _ptr(o),
+                              _stream(stream)))
+        return o
+
+    def dots(self, V, w, k=None, out=None, stream=None):
+        k = V.shape[0] if k is None else k
+        o = out if out is not None else self._new(k)
+        check(lib().cfv_dots(self._h, _ptr(V), int(k), _ptr(w), _ptr(o), _stream(stream)))
+        return o
+
+    def axpby(self, a, x, b, y, stream=None):
+        check(lib().cfv_axpby(self._h, y.numel(), float(a), _ptr(x), float(b), _ptr(y), _stream(stream)))
+        return y

@@ -1,0 +1,285 @@
+// C ABI of the coronal finite-volume MHD library: grid construction on the
+// host, device contexts, and the stream-ordered entry points declared in
+// include/cfv.h.
+#include "../../include/cfv.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cfv_kernels.hpp"
+
+namespace cfv {
+int reduce_partials_per_vector();
+hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s);
+hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
+                      double* A, hipStream_t s);
+int64_t vjp_workspace_doubles(const Shape& g);
+}  // namespace cfv
+
+struct cfv_grid {
+  cfv::Shape g;
+  std::vector<double> r;  // Nr + 1
+  std::vector<double> D;  // 6 (N+1)^2 3 unit corner directions
+};
+
+struct cfv_ctx {
+  const cfv_grid* grid = nullptr;
+  int device = 0;
+  cfv::Params pr{};
+  double* dD = nullptr;
+  double* dr = nullptr;
+  double* dbr = nullptr;
+  double* W = nullptr;     // 36 ncells: primitives + limited gradients
+  double* Wd = nullptr;    // 36 ncells: their tangents
+  double* A = nullptr;     // adjoint workspace
+  double* part = nullptr;  // reduction partials
+  int part_vectors = 0;
+  cfv::DevGrid dev() const {
+    cfv::DevGrid d;
+    d.g = grid->g;
+    d.G.D = dD;
+    d.G.r = dr;
+    d.pr = pr;
+    d.br = dbr;
+    return d;
+  }
+};
+
+namespace {
+thread_local std::string g_err;
+
+cfv_status fail(cfv_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+cfv_status hip_fail(hipError_t e, const char* where) {
+  return fail(CFV_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CFV_HIP(call)                                        \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);        \
+  } while (0)
+
+const double kPi = 3.14159265358979323846;
+
+cfv_status check_ctx(const cfv_ctx* c) {
+  if (!c || !c->grid) return fail(CFV_ERR_ARG, "null context");
+  return CFV_OK;
+}
+
+template <class T>
+cfv_status dmalloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+  if (e != hipSuccess) return fail(CFV_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return CFV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* cfv_last_error(void) { return g_err.c_str(); }
+
+cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_grid** out) {
+  g_err.clear();
+  if (!out || !r_nodes) return fail(CFV_ERR_ARG, "null argument");
+  if (N < 2 || Nr < 1) return fail(CFV_ERR_ARG, "need N >= 2 and Nr >= 1");
+  for (int k = 0; k < Nr; ++k)
+    if (!(r_nodes[k + 1] > r_nodes[k]) || !(r_nodes[k] > 0.0))
+      return fail(CFV_ERR_ARG, "r_nodes must be positive and strictly increasing");
+  cfv_grid* g = new (std::nothrow) cfv_grid;
+  if (!g) return fail(CFV_ERR_ALLOC, "host allocation");
+  g->g.N = N;
+  g->g.Nr = Nr;
+  g->g.nb = 6LL * N * N;
+  g->g.ncells = g->g.nb * Nr;
+  g->r.assign(r_nodes, r_nodes + Nr + 1);
+  const int n1 = N + 1;
+  g->D.resize(size_t(6) * n1 * n1 * 3);
+  std::vector<double> t(n1);
+  for (int q = 0; q <= N; ++q) t[q] = std::tan(-kPi / 4 + q * (kPi / 2) / N);
+  for (int p = 0; p < 6; ++p)
+    for (int jj = 0; jj <= N; ++jj)
+      for (int ii = 0; ii <= N; ++ii) {
+        const double a = t[ii], b = t[jj];
+        double x, y, z;
+        switch (p) {
+          case 0: x = 1; y = a; z = b; break;
+          case 1: x = -a; y = 1; z = b; break;
+          case 2: x = -1; y = -a; z = b; break;
+          case 3: x = a; y = -1; z = b; break;
+          case 4: x = -b; y = a; z = 1; break;
+          default: x = b; y = a; z = -1; break;
+        }
+        const double nrm = std::sqrt(x * x + y * y + z * z);
+        double* d = &g->D[((size_t(p) * n1 + jj) * n1 + ii) * 3];
+        d[0] = x / nrm;
+        d[1] = y / nrm;
+        d[2] = z / nrm;
+      }
+  *out = g;
+  return CFV_OK;
+}
+
+void cfv_grid_destroy(cfv_grid* g) { delete g; }
+
+cfv_status cfv_grid_sizes(const cfv_grid* g, int64_t* ncells, int64_t* nfaces, int64_t* nbnd) {
+  if (!g) return fail(CFV_ERR_ARG, "null grid");
+  const int64_t n2 = int64_t(g->g.N) * g->g.N;
+  if (ncells) *ncells = g->g.ncells;
+  if (nfaces) *nfaces = 6 * n2 * (g->g.Nr + 1) + 12 * n2 * g->g.Nr;
+  if (nbnd) *nbnd = g->g.nb;
+  return CFV_OK;
+}
+
+cfv_status cfv_grid_faces_to_host(const cfv_grid* g, int64_t* L, int64_t* R, int8_t* kind) {
+  if (!g || !L || !R || !kind) return fail(CFV_ERR_ARG, "null argument");
+  const cfv::Shape& s = g->g;
+  int64_t f = 0;
+  for (int64_t c = 0; c < s.ncells; ++c) {
+    int p, k, j, i;
+    cfv::decode(s, c, p, k, j, i);
+    for (int lf = 0; lf < 6; ++lf) {
+      cfv::Nbr nb = cfv::neighbour(s, p, k, j, i, lf);
+      if (nb.id >= s.ncells || nb.id > c) {
+        L[f] = c;
+        R[f] = nb.id;
+        kind[f] = nb.id >= s.ncells + s.nb ? 2 : (nb.id >= s.ncells ? 1 : 0);
+        ++f;
+      }
+    }
+  }
+  return CFV_OK;
+}
+
+cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** out) {
+  g_err.clear();
+  if (!g || !prm || !out) return fail(CFV_ERR_ARG, "null argument");
+  if (!(prm->gamma > 1.0) || !(prm->c_h > 0.0) || prm->G < 0.0 || !(prm->rho_b > 0.0) || !(prm->T_b > 0.0))
+    return fail(CFV_ERR_ARG, "need gamma > 1, c_h > 0, G >= 0, rho_b > 0, T_b > 0");
+  if (prm->limiter != 0 && prm->limiter != 1) return fail(CFV_ERR_ARG, "limiter must be 0 or 1");
+  if (prm->inner_mode != 0) return fail(CFV_ERR_ARG, "inner_mode: only the low-E boundary (0) is provided");
+  cfv_ctx* c = new (std::nothrow) cfv_ctx;
+  if (!c) return fail(CFV_ERR_ALLOC, "host allocation");
+  c->grid = g;
+  CFV_HIP(hipGetDevice(&c->device));
+  c->pr.gamma = prm->gamma;
+  c->pr.c_h = prm->c_h;
+  c->pr.G = prm->G;
+  c->pr.vr_star = prm->vr_star;
+  c->pr.rho_b = prm->rho_b;
+  c->pr.T_b = prm->T_b;
+  c->pr.limiter = prm->limiter;
+  c->pr.inner_mode = prm->inner_mode;
+  for (int q = 0; q < 8; ++q) c->pr.outer_exp[q] = prm->outer_exp[q];
+  c->pr.outer_vr_mass = prm->outer_vr_mass;
+  c->pr.outer_psi_zero = prm->outer_psi_zero;
+  const int64_t nc = g->g.ncells;
+  cfv_status st;
+  c->part_vectors = 32;
+  if ((st = dmalloc(&c->dD, g->D.size())) || (st = dmalloc(&c->dr, g->r.size())) ||
+      (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->W, size_t(36) * nc)) ||
+      (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
+      (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
+      (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector()))) {
+    cfv_ctx_destroy(c);
+    return st;
+  }
+  hipError_t e = hipMemcpy(c->dD, g->D.data(), g->D.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->dr, g->r.data(), g->r.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->dbr, 0, size_t(g->g.nb) * sizeof(double));
+  if (e != hipSuccess) {
+    cfv_ctx_destroy(c);
+    return hip_fail(e, "uploading grid tables");
+  }
+  *out = c;
+  return CFV_OK;
+}
+
+void cfv_ctx_destroy(cfv_ctx* c) {
+  if (!c) return;
+  double* bufs[] = {c->dD, c->dr, c->dbr, c->W, c->Wd, c->A, c->part};
+  for (double* b : bufs)
+    if (b) (void)hipFree(b);
+  delete c;
+}
+
+cfv_status cfv_set_inner_br(cfv_ctx* c, const double* br, int64_t n, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!br) return fail(CFV_ERR_ARG, "null B_r map");
+  if (n != c->grid->g.nb) return fail(CFV_ERR_SIZE, "B_r map length must be 6 N^2");
+  CFV_HIP(hipMemcpyAsync(c->dbr, br, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_geometry(cfv_ctx* c, double* xc, double* vol, double* xf, double* S, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!xc || !vol || !xf || !S) return fail(CFV_ERR_ARG, "null output");
+  CFV_HIP(cfv::launch_geometry(c->dev(), xc, vol, xf, S, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
+  CFV_HIP(cfv::launch_residual(c->dev(), U, R, c->W, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* dbr, double* Jv, double* R,
+                   hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
+  CFV_HIP(cfv::launch_jvp(c->dev(), U, v, dbr, Jv, R, c->W, c->Wd, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_local_dt(cfv_ctx* c, const double* U, double cfl, double* diag, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !diag) return fail(CFV_ERR_ARG, "null state or output");
+  if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
+  CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, diag, c->W, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_norms(cfv_ctx* c, const double* a, const double* b, double* out9, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!a || !out9) return fail(CFV_ERR_ARG, "null input or output");
+  CFV_HIP(cfv::launch_norms(c->grid->g.ncells, a, b, out9, c->part, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_dots(cfv_ctx* c, const double* V, int32_t k, const double* w, double* out, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!V || !w || !out) return fail(CFV_ERR_ARG, "null input or output");
+  if (k < 1 || k > c->part_vectors) return fail(CFV_ERR_ARG, "k must be in 1..32");
+  CFV_HIP(cfv::launch_dots(9 * c->grid->g.ncells, V, k, w, out, c->part, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_axpby(cfv_ctx* c, int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!x || !y || n < 0) return fail(CFV_ERR_ARG, "bad vector arguments");
+  CFV_HIP(cfv::launch_axpby(n, a, x, b, y, s));
+  return CFV_OK;
+}
+
+}  // extern "C"

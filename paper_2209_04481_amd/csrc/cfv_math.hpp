@@ -1,0 +1,246 @@
+// Device-side physics of the coronal finite-volume MHD residual.
+//
+// Everything state-dependent is templated on the scalar type T: T = double
+// gives the residual, T = Dual (value + one tangent) gives the exact forward
+// derivative (JVP) from the same source.  Geometry is always plain double.
+// Branches (min/max picks, |v_n|, the clamp under the square root) are taken
+// on primal values, so the tangent follows the active branch.
+//
+// Physics (paper Section 2.1, Eqs. 14-17; boundary laws Sections 3.2, 4.1):
+//   conservative U = (rho, rho v, B, E, psi), E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
+//   primitive    P = (rho, v, B, p, psi)
+//   normal flux  (rho v_n, rho v v_n + p_T n - B B_n, v_n B - B_n v + psi n,
+//                 (E + p_T) v_n - B_n (v.B), c_h^2 B_n),  p_T = p + |B|^2/2
+//   Rusanov      F = ((F_L + F_R)/2 - s/2 (U_R - U_L)) |S|,
+//                s = max(|v_n,L| + c_f,L, |v_n,R| + c_f,R, c_h)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cfv {
+
+// ---------------------------------------------------------------- dual number
+struct Dual {
+  double v, d;
+  __host__ __device__ Dual() : v(0.0), d(0.0) {}
+  __host__ __device__ Dual(double a) : v(a), d(0.0) {}
+  __host__ __device__ Dual(double a, double b) : v(a), d(b) {}
+};
+__host__ __device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__host__ __device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__host__ __device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__host__ __device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__host__ __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+__host__ __device__ __forceinline__ Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+__host__ __device__ __forceinline__ Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+__host__ __device__ __forceinline__ Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+__host__ __device__ __forceinline__ Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+__host__ __device__ __forceinline__ Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+__host__ __device__ __forceinline__ Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+__host__ __device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+__host__ __device__ __forceinline__ Dual operator/(double a, Dual b) {
+  double q = a / b.v;
+  return Dual(q, -q * b.d / b.v);
+}
+__host__ __device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+__host__ __device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+__host__ __device__ __forceinline__ Dual sqrt(Dual a) {
+  double s = ::sqrt(a.v);
+  return Dual(s, a.d / (2.0 * s));
+}
+
+__host__ __device__ __forceinline__ double val(double a) { return a; }
+__host__ __device__ __forceinline__ double val(Dual a) { return a.v; }
+__host__ __device__ __forceinline__ double dsqrt(double a) { return ::sqrt(a); }
+__host__ __device__ __forceinline__ Dual dsqrt(Dual a) { return sqrt(a); }
+template <class T> __host__ __device__ __forceinline__ T tabs(T a) { return val(a) < 0.0 ? -a : a; }
+// min/max that keep the first argument on ties; the pick follows the values
+template <class T> __host__ __device__ __forceinline__ T pick_min(T a, T b) { return val(a) <= val(b) ? a : b; }
+template <class T> __host__ __device__ __forceinline__ T pick_max(T a, T b) { return val(a) >= val(b) ? a : b; }
+__host__ __device__ __forceinline__ Dual powd(Dual a, double e) {
+  double p = ::pow(a.v, e);
+  return Dual(p, e == 0.0 ? 0.0 : e * ::pow(a.v, e - 1.0) * a.d);
+}
+__host__ __device__ __forceinline__ double powd(double a, double e) { return ::pow(a, e); }
+
+// ------------------------------------------------------------------- vectors
+struct V3 {
+  double x, y, z;
+};
+__host__ __device__ __forceinline__ V3 mk(double x, double y, double z) { return V3{x, y, z}; }
+__host__ __device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__host__ __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__host__ __device__ __forceinline__ V3 operator*(double s, V3 a) { return V3{s * a.x, s * a.y, s * a.z}; }
+__host__ __device__ __forceinline__ double dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ __forceinline__ V3 cross3(V3 a, V3 b) {
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ __forceinline__ double norm3(V3 a) { return ::sqrt(dot3(a, a)); }
+
+// --------------------------------------------------------------- parameters
+struct Params {
+  double gamma, c_h, G, vr_star, rho_b, T_b;
+  int limiter;
+  int inner_mode;
+  double outer_exp[8];  // rho, B_r, B_theta, B_phi, V_r, V_theta, V_phi, p
+  int outer_vr_mass;
+  int outer_psi_zero;
+};
+
+// ------------------------------------------------------------ state algebra
+// prim[] = (rho, vx, vy, vz, Bx, By, Bz, p, psi)
+template <class T>
+__host__ __device__ __forceinline__ void cons_to_prim(const T u[9], T q[9], double gamma) {
+  T rho = u[0];
+  T vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
+  T v2 = vx * vx + vy * vy + vz * vz;
+  T B2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+  q[0] = rho; q[1] = vx; q[2] = vy; q[3] = vz;
+  q[4] = u[4]; q[5] = u[5]; q[6] = u[6];
+  q[7] = (gamma - 1.0) * (u[7] - 0.5 * rho * v2 - 0.5 * B2);
+  q[8] = u[8];
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void prim_to_cons(const T q[9], T u[9], double gamma) {
+  T v2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  T B2 = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+  u[0] = q[0];
+  u[1] = q[0] * q[1]; u[2] = q[0] * q[2]; u[3] = q[0] * q[3];
+  u[4] = q[4]; u[5] = q[5]; u[6] = q[6];
+  u[7] = q[7] / (gamma - 1.0) + 0.5 * q[0] * v2 + 0.5 * B2;
+  u[8] = q[8];
+}
+
+// normal physical flux for unit n; also returns |v_n| + c_f
+template <class T>
+__host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], double gamma, double c_h) {
+  T rho = q[0], vx = q[1], vy = q[2], vz = q[3], bx = q[4], by = q[5], bz = q[6], p = q[7];
+  T vn = vx * n.x + vy * n.y + vz * n.z;
+  T bn = bx * n.x + by * n.y + bz * n.z;
+  T B2 = bx * bx + by * by + bz * bz;
+  T v2 = vx * vx + vy * vy + vz * vz;
+  T pT = p + 0.5 * B2;
+  T E = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
+  T rvn = rho * vn;
+  F[0] = rvn;
+  F[1] = rvn * vx + pT * n.x - bx * bn;
+  F[2] = rvn * vy + pT * n.y - by * bn;
+  F[3] = rvn * vz + pT * n.z - bz * bn;
+  F[4] = vn * bx - bn * vx + q[8] * n.x;
+  F[5] = vn * by - bn * vy + q[8] * n.y;
+  F[6] = vn * bz - bn * vz + q[8] * n.z;
+  F[7] = (E + pT) * vn - bn * (vx * bx + vy * by + vz * bz);
+  F[8] = (c_h * c_h) * bn;
+  // fast magnetosonic speed
+  T irho = 1.0 / rho;
+  T a2 = gamma * p * irho;
+  T b2 = B2 * irho;
+  T bn2 = bn * bn * irho;
+  T s = a2 + b2;
+  T disc = s * s - 4.0 * a2 * bn2;
+  T sd = val(disc) > 0.0 ? dsqrt(disc) : T(0.0);
+  T cf = dsqrt(0.5 * (s + sd));
+  return tabs(vn) + cf;
+}
+
+// Rusanov flux through the face of vector area S (L -> R); returns s.
+template <class T>
+__host__ __device__ __forceinline__ T rusanov(const T qL[9], const T qR[9], V3 S, T F[9], const Params& pr) {
+  double area = norm3(S);
+  double ia = 1.0 / area;
+  V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
+  T FL[9], FR[9], UL[9], UR[9];
+  T lamL = phys_flux(qL, n, FL, pr.gamma, pr.c_h);
+  T lamR = phys_flux(qR, n, FR, pr.gamma, pr.c_h);
+  T s = pick_max(lamL, lamR);
+  s = pick_max(s, T(pr.c_h));
+  prim_to_cons(qL, UL, pr.gamma);
+  prim_to_cons(qR, UR, pr.gamma);
+#pragma unroll
+  for (int v = 0; v < 9; ++v) F[v] = (0.5 * (FL[v] + FR[v]) - 0.5 * s * (UR[v] - UL[v])) * area;
+  return s;
+}
+
+// spherical unit vectors at x (Eqs. 20-21)
+__host__ __device__ __forceinline__ void sph_basis(V3 x, V3& rh, V3& th, V3& ph) {
+  double r = norm3(x);
+  double rc = ::sqrt(x.x * x.x + x.y * x.y);
+  double ir = 1.0 / r, irc = 1.0 / rc;
+  rh = mk(x.x * ir, x.y * ir, x.z * ir);
+  th = mk(x.x * x.z * irc * ir, x.y * x.z * irc * ir, -rc * ir);
+  ph = mk(-x.y * irc, x.x * irc, 0.0);
+}
+
+// Inner low-E ghost (Section 3.2, Eq. 25).  Dirichlet values are face averages,
+// so G = 2b - I.  The boundary field keeps the interior tangential part and
+// takes the map's radial part; the boundary velocity is V_r* B_r B_b / |B_b|^2.
+template <class T>
+__host__ __device__ __forceinline__ void inner_ghost(const T qI[9], V3 xf, T br, T qG[9], const Params& pr) {
+  double ir = 1.0 / norm3(xf);
+  V3 rh = mk(xf.x * ir, xf.y * ir, xf.z * ir);
+  T bIr = qI[4] * rh.x + qI[5] * rh.y + qI[6] * rh.z;
+  T dB = br - bIr;
+  T bbx = qI[4] + dB * rh.x, bby = qI[5] + dB * rh.y, bbz = qI[6] + dB * rh.z;
+  T bb2 = bbx * bbx + bby * bby + bbz * bbz;
+  if (val(bb2) <= 1e-30) bb2 = T(1e-30);
+  T fac = pr.vr_star * br / bb2;
+  qG[0] = 2.0 * pr.rho_b - qI[0];
+  qG[1] = 2.0 * (fac * bbx) - qI[1];
+  qG[2] = 2.0 * (fac * bby) - qI[2];
+  qG[3] = 2.0 * (fac * bbz) - qI[3];
+  qG[4] = 2.0 * bbx - qI[4];
+  qG[5] = 2.0 * bby - qI[5];
+  qG[6] = 2.0 * bbz - qI[6];
+  qG[7] = 2.0 * (pr.rho_b * pr.T_b) - qI[7];
+  qG[8] = -qI[8];
+}
+
+// Outer ghost: Table 2 laws G = I (r_I/r_G)^e in spherical components at the
+// face centroid, V_r by V_r r^2 rho = const when selected, psi_b = 0 or G = I.
+template <class T>
+__host__ __device__ __forceinline__ void outer_ghost(const T qI[9], V3 xI, V3 xG, V3 xf, T qG[9], const Params& pr) {
+  V3 rh, th, ph;
+  sph_basis(xf, rh, th, ph);
+  double rI = norm3(xI), rG = norm3(xG);
+  double q = rI / rG;
+  const double* e = pr.outer_exp;
+  T rho = qI[0] * ::pow(q, e[0]);
+  T br = (qI[4] * rh.x + qI[5] * rh.y + qI[6] * rh.z) * ::pow(q, e[1]);
+  T bt = (qI[4] * th.x + qI[5] * th.y + qI[6] * th.z) * ::pow(q, e[2]);
+  T bp = (qI[4] * ph.x + qI[5] * ph.y) * ::pow(q, e[3]);
+  T vr = qI[1] * rh.x + qI[2] * rh.y + qI[3] * rh.z;
+  if (pr.outer_vr_mass)
+    vr = vr * ((rI * rI) * qI[0]) / ((rG * rG) * rho);
+  else
+    vr = vr * ::pow(q, e[4]);
+  T vt = (qI[1] * th.x + qI[2] * th.y + qI[3] * th.z) * ::pow(q, e[5]);
+  T vp = (qI[1] * ph.x + qI[2] * ph.y) * ::pow(q, e[6]);
+  qG[0] = rho;
+  qG[1] = vr * rh.x + vt * th.x + vp * ph.x;
+  qG[2] = vr * rh.y + vt * th.y + vp * ph.y;
+  qG[3] = vr * rh.z + vt * th.z;
+  qG[4] = br * rh.x + bt * th.x + bp * ph.x;
+  qG[5] = br * rh.y + bt * th.y + bp * ph.y;
+  qG[6] = br * rh.z + bt * th.z;
+  qG[7] = qI[7] * ::pow(q, e[7]);
+  qG[8] = pr.outer_psi_zero ? -qI[8] : qI[8];
+}
+
+// gravity source times volume: V (0, rho g, 0, g . m, 0), g = -G x/|x|^3
+template <class T>
+__host__ __device__ __forceinline__ void gravity_source(const T u[9], V3 x, double vol, double G, T S[9]) {
+  double r = norm3(x);
+  double f = -G / (r * r * r) * vol;
+  V3 gv = mk(f * x.x, f * x.y, f * x.z);
+  S[0] = T(0.0);
+  S[1] = u[0] * gv.x; S[2] = u[0] * gv.y; S[3] = u[0] * gv.z;
+  S[4] = T(0.0); S[5] = T(0.0); S[6] = T(0.0);
+  S[7] = u[1] * gv.x + u[2] * gv.y + u[3] * gv.z;
+  S[8] = T(0.0);
+}
+
+}  // namespace cfv

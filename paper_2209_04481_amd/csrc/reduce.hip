@@ -1,0 +1,99 @@
+// Deterministic reductions and vector updates for the pseudo-time solver:
+// per-variable norms of the Eq. 2 monitor, batched dot products for the
+// Gram-Schmidt step of GMRES, and y = a x + b y.
+//
+// Two stages with a fixed launch shape: each block folds a fixed strided
+// subset in a fixed order and writes one partial; one block then folds the
+// partials in order.  No atomics, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cfv {
+
+static constexpr int kRBlock = 256;
+static constexpr int kRGrid = 1024;  // partials per reduction
+
+template <int B>
+__device__ __forceinline__ double block_sum(double x, double* sh) {
+  // wavefront reduction then across the block's wavefronts
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < B / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+// partial[v*kRGrid + block] = sum over the block's cells of (a - b)^2 for variable v
+__global__ __launch_bounds__(kRBlock) void sq_partials(int64_t nc, const double* __restrict__ a,
+                                                      const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[kRBlock / 64];
+  for (int v = 0; v < 9; ++v) {
+    double s = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < nc; c += int64_t(kRGrid) * kRBlock) {
+      double d = a[v * nc + c] - (b ? b[v * nc + c] : 0.0);
+      s += d * d;
+    }
+    double t = block_sum<kRBlock>(s, sh);
+    if (threadIdx.x == 0) part[v * kRGrid + blockIdx.x] = t;
+  }
+}
+
+// out[v] = (sqrt?) of the sum of partials of variable v (one block per v)
+__global__ __launch_bounds__(kRBlock) void fold_partials(const double* __restrict__ part, int nvec,
+                                                        double* __restrict__ out, int take_sqrt) {
+  __shared__ double sh[kRBlock / 64];
+  const int v = blockIdx.x;
+  if (v >= nvec) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < kRGrid; b += kRBlock) s += part[v * kRGrid + b];
+  double t = block_sum<kRBlock>(s, sh);
+  if (threadIdx.x == 0) out[v] = take_sqrt ? ::sqrt(t) : t;
+}
+
+// partial[i*kRGrid + block] = sum over the block's entries of V_i . w
+__global__ __launch_bounds__(kRBlock) void dot_partials(int64_t n, const double* __restrict__ V, int k,
+                                                       const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[kRBlock / 64];
+  for (int q = 0; q < k; ++q) {
+    const double* x = V + int64_t(q) * n;
+    double s = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock)
+      s += x[c] * w[c];
+    double t = block_sum<kRBlock>(s, sh);
+    if (threadIdx.x == 0) part[q * kRGrid + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kRBlock) void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b,
+                                                       double* __restrict__ y) {
+  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kRBlock)
+    y[c] = a * x[c] + b * y[c];
+}
+
+int reduce_partials_per_vector() { return kRGrid; }
+
+hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(sq_partials, dim3(kRGrid), dim3(kRBlock), 0, s, nc, a, b, part);
+  hipLaunchKernelGGL(fold_partials, dim3(9), dim3(kRBlock), 0, s, part, 9, out9, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, V, k, w, part);
+  hipLaunchKernelGGL(fold_partials, dim3(k), dim3(kRBlock), 0, s, part, k, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  int64_t blocks = (n + kRBlock - 1) / kRBlock;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(axpby_kernel, dim3(unsigned(blocks)), dim3(kRBlock), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+}  // namespace cfv

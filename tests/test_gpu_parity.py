@@ -1,0 +1,242 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: per variable max_c |gpu - oracle| / max_c |oracle| <= 1e-12 for the
+residual, the JVP and the VJP (and the B_r-map gradient); integer topology is
+compared bit-exactly in the host tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import coronal_inputs as ci
+from helpers import rel_err_per_var
+from oracle import mhd, solve
+from oracle.grid import Grid as OGrid
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def gpu_ok():
+    return torch.cuda.is_available()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not gpu_ok():
+        pytest.skip("no GPU")
+
+
+def lib_params(op):
+    from paper_2209_04481_amd import Params
+    return Params(gamma=op.gamma, c_h=op.c_h, G=op.G, vr_star=op.vr_star, rho_b=op.rho_b, T_b=op.T_b,
+                  limiter=op.limiter, outer_exp=tuple(op.outer_exp), outer_vr_mass=op.outer_vr_mass,
+                  outer_psi_zero=op.outer_psi_zero)
+
+
+class Case:
+    def __init__(self, inst, op=None):
+        from paper_2209_04481_amd import Context, Grid
+        self.inst = inst
+        self.op = op or mhd.Params()
+        self.og = OGrid(inst.N, inst.Nr, inst.r_nodes)
+        self.U = torch.tensor(inst.U)
+        self.br = torch.tensor(inst.br)
+        self.grid = Grid(inst.N, inst.Nr, inst.r_nodes)
+        self.ctx = Context(self.grid, lib_params(self.op))
+        self.Ud = self.U.cuda()
+        self.ctx.set_inner_br(self.br.cuda())
+
+
+def small_inst(seed=3):
+    return ci.make_instance(6, 10, "log", lmax=5, seed=seed)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    print("case: tiny 6x8x8x16", flush=True)
+    return Case(ci.workload("tiny"))
+
+
+def test_geometry_matches_oracle(tiny):
+    xc, vol, xf, S = [t.cpu() for t in tiny.ctx.geometry()]
+    torch.cuda.synchronize()
+    g = tiny.og
+    oxc, oV, _, _ = g.cell_geometry(torch.arange(g.ncells))
+    st = mhd._Stencil(g, torch.arange(g.ncells))
+    lc = st.loc(torch.arange(g.ncells))[:, None].expand(-1, 6)
+    oxf, oS, sign, _, _ = st.face_geometry(lc, torch.arange(6).expand(g.ncells, 6))
+    assert float((xc - oxc).abs().max()) < 1e-14 * 21.5
+    assert float((vol / oV - 1).abs().max()) < 1e-14
+    assert float((xf - oxf).abs().max()) < 1e-14 * 21.5
+    assert float((S - oS * sign[..., None]).abs().max()) < 1e-14 * float(oS.abs().max())
+
+
+def test_residual_parity_tiny(tiny):
+    R = tiny.ctx.residual(tiny.Ud).cpu()
+    Ro = mhd.residual(tiny.og, tiny.U, tiny.br, tiny.op)
+    err = rel_err_per_var(R, Ro)
+    print("residual rel err per var", err.tolist())
+    assert float(err.max()) <= TOL
+
+
+def test_residual_is_deterministic(tiny):
+    R1 = tiny.ctx.residual(tiny.Ud)
+    R2 = tiny.ctx.residual(tiny.Ud)
+    assert torch.equal(R1, R2)
+
+
+def test_jvp_parity_tiny(tiny):
+    v = torch.tensor(ci.direction(tiny.inst.ncells, tiny.inst.seed))        # raw N(0,1), all 9 variables
+    dbr = torch.tensor(ci.br_direction(tiny.grid.nb, tiny.inst.seed))
+    R = torch.empty_like(tiny.Ud)
+    Jv = tiny.ctx.jvp(tiny.Ud, v.cuda(), dbr.cuda(), R=R).cpu()
+    Jo, Ro = solve.jvp(tiny.og, tiny.U, tiny.br, tiny.op, v, dbr)
+    e1, e2 = rel_err_per_var(Jv, Jo), rel_err_per_var(R.cpu(), Ro)
+    print("jvp rel err", e1.tolist())
+    assert float(e1.max()) <= TOL and float(e2.max()) <= TOL
+
+
+def test_vjp_parity_tiny(tiny):
+    w = torch.randn(9, tiny.inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(1))
+    gU, gbr = tiny.ctx.vjp(tiny.Ud, w.cuda())
+    gUo, gbro = solve.vjp(tiny.og, tiny.U, tiny.br, tiny.op, w)
+    e1 = rel_err_per_var(gU.cpu(), gUo)
+    e2 = rel_err_per_var(gbr.cpu()[None], gbro[None])
+    print("vjp rel err", e1.tolist(), float(e2))
+    assert float(e1.max()) <= TOL and float(e2.max()) <= TOL
+
+
+def test_dot_product_identity_tiny(tiny):
+    gen = torch.Generator().manual_seed(2)
+    v = torch.randn(9, tiny.inst.ncells, dtype=torch.float64, generator=gen).cuda()
+    dbr = torch.randn(tiny.grid.nb, dtype=torch.float64, generator=gen).cuda()
+    w = torch.randn(9, tiny.inst.ncells, dtype=torch.float64, generator=gen).cuda()
+    Jv = tiny.ctx.jvp(tiny.Ud, v, dbr)
+    gU, gbr = tiny.ctx.vjp(tiny.Ud, w)
+    lhs = float((w * Jv).sum())
+    rhs = float((gU * v).sum() + (gbr * dbr).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float((w * Jv).abs().sum())
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_parity_log_grid_ragged(limiter):
+    """A grid whose cell count (6*6*6*10 = 2160) is not a multiple of the block."""
+    print(f"case: small log grid limiter={limiter}", flush=True)
+    c = Case(small_inst(), mhd.Params(limiter=limiter))
+    v = torch.tensor(ci.scaled_direction(c.inst.U, 9))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, 9))
+    w = torch.randn(9, c.inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(4))
+    R = c.ctx.residual(c.Ud).cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda()).cpu()
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    Ro = mhd.residual(c.og, c.U, c.br, c.op)
+    Jo, _ = solve.jvp(c.og, c.U, c.br, c.op, v, dbr)
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w)
+    for a, b in ((R, Ro), (Jv, Jo), (gU.cpu(), gUo), (gbr.cpu()[None], gbro[None])):
+        assert float(rel_err_per_var(a, b).max()) <= TOL
+
+
+@pytest.mark.parametrize("case", range(1, 10))
+def test_parity_every_table2_outer_law(case):
+    print(f"case: Table 2 outer law {case}", flush=True)
+    inst = ci.make_instance(4, 5, "log", lmax=3, seed=20 + case)
+    inst.U[8] = 1e-3 * np.random.default_rng(case).standard_normal(inst.ncells)   # psi != 0
+    c = Case(inst, mhd.Params.table2(case))
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(case))
+    v = torch.tensor(ci.scaled_direction(inst.U, case))
+    R = c.ctx.residual(c.Ud).cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda()).cpu()
+    gU, _ = c.ctx.vjp(c.Ud, w.cuda())
+    assert float(rel_err_per_var(R, mhd.residual(c.og, c.U, c.br, c.op)).max()) <= TOL
+    assert float(rel_err_per_var(Jv, solve.jvp(c.og, c.U, c.br, c.op, v)[0]).max()) <= TOL
+    assert float(rel_err_per_var(gU.cpu(), solve.vjp(c.og, c.U, c.br, c.op, w)[0]).max()) <= TOL
+
+
+@pytest.mark.parametrize("N,Nr", [(2, 3), (3, 1), (7, 2)])
+def test_degenerate_shapes(N, Nr):
+    """Smallest panels, a single radial layer (both ghosts on one cell)."""
+    print(f"case: degenerate N={N} Nr={Nr}", flush=True)
+    inst = ci.make_instance(N, Nr, "log", lmax=1, seed=N * 10 + Nr)
+    c = Case(inst)
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(0))
+    R = c.ctx.residual(c.Ud).cpu()
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    assert float(rel_err_per_var(R, mhd.residual(c.og, c.U, c.br, c.op)).max()) <= TOL
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w)
+    assert float(rel_err_per_var(gU.cpu(), gUo).max()) <= TOL
+    assert float(rel_err_per_var(gbr.cpu()[None], gbro[None]).max()) <= TOL
+
+
+def test_local_dt_and_reductions(tiny):
+    d = tiny.ctx.local_dt(tiny.Ud, 1e3).cpu()
+    do = solve.local_dt_diag(tiny.og, tiny.U, tiny.br, tiny.op, 1e3)
+    assert float(((d - do).abs() / do.abs()).max()) < 1e-13
+    a = tiny.Ud
+    b = a * 1.001
+    n = tiny.ctx.norms(a, b).cpu()
+    ref = torch.sqrt(((tiny.U - tiny.U * 1.001) ** 2).sum(1))
+    assert torch.allclose(n, ref, rtol=1e-12, atol=0)
+    V = torch.randn(3, 9, tiny.inst.ncells, dtype=torch.float64, device="cuda")
+    w = torch.randn(9, tiny.inst.ncells, dtype=torch.float64, device="cuda")
+    dots = tiny.ctx.dots(V.contiguous(), w).cpu()
+    ref = (V.cpu() * w.cpu()).sum((1, 2))
+    assert torch.allclose(dots, ref, rtol=1e-12, atol=1e-12)
+    y = w.clone()
+    tiny.ctx.axpby(2.0, V[0], -0.5, y)
+    assert torch.allclose(y, 2.0 * V[0] - 0.5 * w, rtol=1e-15, atol=1e-15)
+
+
+def test_error_paths(tiny):
+    from paper_2209_04481_amd import CfvError
+    with pytest.raises(CfvError):
+        tiny.ctx.set_inner_br(torch.zeros(5, dtype=torch.float64, device="cuda"))
+    with pytest.raises(CfvError):
+        tiny.ctx.residual(torch.zeros(9, 10, dtype=torch.float64, device="cuda"))
+
+
+# ---------------------------------------------------------------- full sizes
+def sample_cells(inst, n, seed):
+    """Random cells plus the boundary layers and panel edges/corners."""
+    rng = np.random.default_rng(seed)
+    N, Nr = inst.N, inst.Nr
+    picks = list(rng.integers(0, inst.ncells, size=n))
+    for p in range(6):
+        for (k, j, i) in ((0, 0, 0), (Nr - 1, N - 1, N - 1), (0, N - 1, 0), (Nr // 2, 0, N - 1), (Nr - 1, N // 2, 0)):
+            picks.append(((p * Nr + k) * N + j) * N + i)
+    return torch.tensor(sorted(set(int(x) for x in picks)))
+
+
+@pytest.mark.parametrize("name,n", [("medium", 160), ("large", 96)])
+def test_full_size_sampled_parity(name, n):
+    """At the medium (1.66M cells) and large (13.3M cells) sizes, in the
+    launch configuration the bench uses: sampled cells computed one by one by
+    the oracle from their distance-2 stencils."""
+    print(f"case: full size {name}", flush=True)
+    inst = ci.workload(name)
+    c = Case(inst)
+    S = sample_cells(inst, n, 7)
+    v = torch.tensor(ci.scaled_direction(inst.U, inst.seed))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, inst.seed))
+    R = c.ctx.residual(c.Ud)[:, S.cuda()].cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda())[:, S.cuda()].cpu()
+    Ro = mhd.residual(c.og, c.U, c.br, c.op, cells=S)
+    Jo, _ = solve.jvp(c.og, c.U, c.br, c.op, v, dbr, cells=S)
+    assert float(rel_err_per_var(R, Ro).max()) <= TOL
+    assert float(rel_err_per_var(Jv, Jo).max()) <= TOL
+    # VJP at the sampled cells is exact from w on their distance-2 stencils
+    st = mhd._Stencil(c.og, S)
+    T = st.D2
+    w = torch.zeros(9, inst.ncells, dtype=torch.float64)
+    w[:, T] = torch.randn(9, T.numel(), dtype=torch.float64, generator=torch.Generator().manual_seed(3))
+    gU, _ = c.ctx.vjp(c.Ud, w.cuda(), want_br=False)
+    gUo, _ = solve.vjp(c.og, c.U, c.br, c.op, w[:, T], cells=T)
+    assert float(rel_err_per_var(gU[:, S.cuda()].cpu(), gUo[:, S]).max()) <= TOL
+    # dot-product identity over the whole grid
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    vv = torch.randn(9, inst.ncells, dtype=torch.float64, device="cuda", generator=gen) * c.Ud.abs()
+    ww = torch.randn(9, inst.ncells, dtype=torch.float64, device="cuda", generator=gen)
+    Jvv = c.ctx.jvp(c.Ud, vv)
+    gUw, _ = c.ctx.vjp(c.Ud, ww, want_br=False)
+    lhs, rhs = float((ww * Jvv).sum()), float((gUw * vv).sum())
+    assert abs(lhs - rhs) <= 1e-12 * float((ww * Jvv).abs().sum())

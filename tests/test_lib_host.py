@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI library (no GPU compute calls)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+import coronal_inputs as ci
+from oracle.grid import Grid as OracleGrid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfv.h")
+LIB = os.path.join(ROOT, "paper_2209_04481_amd", "libcfv.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfv_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(LIB):
+        pytest.skip("libcfv.so not built (run __graft_entry__.build())")
+    return LIB
+
+
+def test_library_exports_every_declared_symbol(built):
+    out = subprocess.run(["nm", "-D", "--defined-only", built], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cfv_[a-z0-9_]+)", out))
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    from paper_2209_04481_amd import binding
+    L = binding.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s)
+
+
+@pytest.mark.parametrize("N,Nr,radial", [(8, 16, "geometric"), (5, 7, "log"), (12, 3, "log"),
+                                         (3, 1, "log"), (3, 2, "log"), (4, 1, "log"), (2, 2, "log")])
+def test_face_list_bit_exact_vs_geometric_matching(built, N, Nr, radial):
+    """Library adjacency (closed-form panel-edge table) vs the oracle's
+    point-location derivation: identical canonical face lists."""
+    from paper_2209_04481_amd import Grid
+    r = ci.radial_nodes(Nr, radial)
+    L, R, K = Grid(N, Nr, r).faces()
+    oL, oR, oK = OracleGrid(N, Nr, r).face_list()
+    assert np.array_equal(L, oL.numpy()) and np.array_equal(R, oR.numpy())
+    assert np.array_equal(K.astype(np.int64), oK.numpy())
+
+
+def test_grid_sizes_and_argument_errors(built):
+    from paper_2209_04481_amd import CfvError, Grid
+    g = Grid(6, 4, ci.radial_nodes(4, "log"))
+    assert g.ncells == 6 * 36 * 4 and g.nb == 216
+    assert g.nfaces == 6 * 36 * 5 + 12 * 36 * 4
+    with pytest.raises(CfvError):
+        Grid(6, 4, np.array([1.0, 2.0, 2.0, 3.0, 4.0]))   # not strictly increasing
+    with pytest.raises(CfvError):
+        Grid(1, 4, ci.radial_nodes(4, "log"))
