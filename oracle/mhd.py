@@ -151,13 +151,24 @@ def rusanov(PL, PR, S, prm: Params):
 
 
 def spherical_basis(x):
-    """r-hat, theta-hat, phi-hat at x (..., 3), as in Eqs. 20-21."""
+    """r-hat, theta-hat, phi-hat at x (..., 3), as in Eqs. 20-21.
+
+    On the polar axis (x = y = 0) theta-hat and phi-hat are undefined; there
+    the limit along the meridian phi = 0 is taken: theta-hat = (sign z, 0, 0),
+    phi-hat = (0, 1, 0)."""
     X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
     r = torch.linalg.norm(x, dim=-1)
     rc = torch.sqrt(X * X + Y * Y)
+    axis = rc == 0.0
+    rcs = torch.where(axis, torch.ones_like(rc), rc)
     rhat = x / r[..., None]
-    that = torch.stack([X * Z / (rc * r), Y * Z / (rc * r), -rc / r], dim=-1)
-    phat = torch.stack([-Y / rc, X / rc, torch.zeros_like(X)], dim=-1)
+    that = torch.stack([X * Z / (rcs * r), Y * Z / (rcs * r), -rc / r], dim=-1)
+    phat = torch.stack([-Y / rcs, X / rcs, torch.zeros_like(X)], dim=-1)
+    zero = torch.zeros_like(X)
+    that_ax = torch.stack([torch.where(Z >= 0, torch.ones_like(Z), -torch.ones_like(Z)), zero, zero], dim=-1)
+    phat_ax = torch.stack([zero, torch.ones_like(X), zero], dim=-1)
+    that = torch.where(axis[..., None], that_ax, that)
+    phat = torch.where(axis[..., None], phat_ax, phat)
     return rhat, that, phat
 
 

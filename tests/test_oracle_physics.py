@@ -150,6 +150,16 @@ def test_spherical_basis_reproduces_eqs_20_21():
     assert torch.allclose(torch.linalg.cross(rh, th), ph, atol=1e-14)
 
 
+def test_spherical_basis_on_the_polar_axis_is_the_phi0_limit():
+    """Reading: on the axis theta-hat, phi-hat are the limits along phi = 0."""
+    eps = 1e-9
+    for z in (3.0, -2.0):
+        x = torch.tensor([[0.0, 0.0, z], [eps, 0.0, z]], dtype=DT)
+        rh, th, ph = mhd.spherical_basis(x)
+        assert torch.allclose(th[0], th[1], atol=1e-8) and torch.allclose(ph[0], ph[1], atol=1e-8)
+        assert torch.allclose(torch.linalg.cross(rh[0], th[0]), ph[0], atol=1e-15)
+
+
 def boundary_face_sample(n=50, seed=0, radius=1.0):
     g = torch.Generator().manual_seed(seed)
     xf = torch.randn(n, 3, dtype=DT, generator=g)
