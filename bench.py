@@ -1,0 +1,170 @@
+"""Benchmark of the coronal FV-MHD hot path on one MI355X.
+
+One step = one pass of the hot path over the large workload (6 x 96 x 96 x
+240 = 13,271,040 cells, FP64): ghost fill + residual, JVP (with a B_r-map
+direction), VJP (state and B_r-map gradients) and the Eq. 2 residual norms.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints ONE JSON line.  `value` is the throughput of whole steps in Mcell/s
+(cells x steps / wall time of the timed region, inputs resident in HBM).
+Per-kernel durations come from HIP events recorded on the launch stream by
+the library over the timed region; the roofline entry is for the operation
+whose kernels take the most time, with its algorithmic bytes per cell.
+The CPU baseline times the oracle (test infrastructure) on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell and operation (FP64 SoA, 9 variables)
+ALG_BYTES = {"residual": 144, "jvp": 216, "vjp": 216}
+OP_KERNELS = {
+    "residual": ("grad_limit", "flux"),
+    "jvp": ("grad_limit_jvp", "flux_jvp"),
+    "vjp": ("grad_limit", "adjoint", "adjoint_gather"),
+}
+
+
+def cpu_baseline(inst, ncells_sample: int):
+    """Oracle residual + JVP + VJP on a contiguous block of cells."""
+    import torch
+
+    from oracle import mhd, solve
+    from oracle.grid import Grid as OGrid
+    import coronal_inputs as ci
+
+    og = OGrid(inst.N, inst.Nr, inst.r_nodes)
+    U = torch.from_numpy(inst.U)
+    br = torch.from_numpy(inst.br)
+    mid = inst.ncells // 2
+    cells = torch.arange(mid, mid + ncells_sample)
+    op = mhd.Params()
+    v = torch.from_numpy(ci.scaled_direction(inst.U[:, :1], 1)).expand(9, 1)
+    vfull = torch.zeros_like(U)
+    st = mhd._Stencil(og, cells)
+    vfull[:, st.D2] = torch.randn(9, st.D2.numel(), dtype=torch.float64) * U[:, st.D2].abs()
+    w = torch.randn(9, ncells_sample, dtype=torch.float64)
+    t0 = time.perf_counter()
+    mhd.residual(og, U, br, op, cells=cells)
+    solve.jvp(og, U, br, op, vfull, cells=cells)
+    solve.vjp(og, U, br, op, w, cells=cells)
+    dt = time.perf_counter() - t0
+    del v
+    return {"value": ncells_sample / dt / 1e6, "unit": "Mcell/s (residual+JVP+VJP step)",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{ncells_sample} contiguous cells of the large workload (distance-2 stencil gathered), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import coronal_inputs as ci
+    from paper_2209_04481_amd import Context, Grid, Params
+
+    torch.cuda.set_device(0)
+    t_gen = time.time()
+    inst = ci.workload(args.workload)
+    print(f"[bench] inputs for {args.workload}: {inst.ncells} cells in {time.time() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    grid = Grid(inst.N, inst.Nr, inst.r_nodes)
+    ctx = Context(grid, Params())
+    U = torch.from_numpy(inst.U).cuda()
+    br = torch.from_numpy(inst.br).cuda()
+    v = torch.from_numpy(ci.scaled_direction(inst.U, inst.seed)).cuda()
+    dbr = torch.from_numpy(ci.br_direction(grid.nb, inst.seed)).cuda()
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(inst.seed))
+    ctx.set_inner_br(br)
+    R = torch.empty_like(U)
+    Jv = torch.empty_like(U)
+    gU = torch.empty_like(U)
+    gbr = torch.empty(grid.nb, dtype=torch.float64, device="cuda")
+    nrm = torch.empty(9, dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.residual(U, out=R)
+        ctx.jvp(U, v, dbr, out=Jv)
+        ctx.vjp(U, w, out=gU, gbr=gbr)
+        ctx.norms(R, out=nrm)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    ctx.timing_enable(True)
+    ctx.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times = ctx.timing_read()
+    ctx.timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    nc = inst.ncells
+    per_kernel = {k: {"avg_ms": ms / n, "launches": n} for k, (ms, n) in times.items()}
+    op_ms = {}
+    for op, ks in OP_KERNELS.items():
+        op_ms[op] = sum(times[k][0] / times[k][1] for k in ks if k in times)
+    dom = max(op_ms, key=op_ms.get)
+    achieved = ALG_BYTES[dom] * nc / (op_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{dom} ({' + '.join(OP_KERNELS[dom])})", "avg_ms": round(op_ms[dom], 4),
+                "alg_bytes_per_cell": ALG_BYTES[dom]}
+
+    out = {
+        "metric": "Mcell-residuals/s and JVP+VJP/s FP64 at 13M cells; % of HBM roofline; ensemble speedup",
+        "value": round(nc * args.steps / (t1 - t0) / 1e6, 2),
+        "unit": "Mcell/s (residual+JVP+VJP step)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: cubed-sphere shell 6x{inst.N}x{inst.N}x{inst.Nr} "
+                               f"({nc} cells), r in [1, 21.5], Parker wind + dipole, 1% noise, "
+                               f"B_r map l<=31, Barth-Jespersen limiter"},
+        "residual_mcells_per_s": round(nc / (op_ms["residual"] * 1e-3) / 1e6, 1),
+        "residuals_per_s": round(1e3 / op_ms["residual"], 2),
+        "jvp_per_s": round(1e3 / op_ms["jvp"], 2),
+        "vjp_per_s": round(1e3 / op_ms["vjp"], 2),
+        "op_ms": {k: round(x, 4) for k, x in op_ms.items()},
+        "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

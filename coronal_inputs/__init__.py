@@ -158,20 +158,35 @@ def dipole_field(x: np.ndarray, b_eq: float = GAUSS) -> np.ndarray:
 
 
 def real_harmonics(lmax: int, theta: np.ndarray, phi: np.ndarray):
-    """Real orthonormal Y_lm for l = 1..lmax, m = -l..l (order l up, m up)."""
-    from scipy.special import sph_harm_y
-    phi = np.mod(phi, 2 * math.pi)
+    """Real orthonormal Y_lm for l = 1..lmax, m = -l..l (order l up, m up).
+
+    Fully normalised associated Legendre functions by the standard stable
+    recurrences (no Condon-Shortley phase); Y_lm = sqrt(2) Pbar_l^m cos(m phi)
+    for m > 0, sqrt(2) Pbar_l^|m| sin(|m| phi) for m < 0, Pbar_l^0 for m = 0."""
+    x = np.cos(theta)
+    sx = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    P = {}
+    pmm = np.full_like(x, math.sqrt(1.0 / (4.0 * math.pi)))
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * sx * pmm
+        P[(m, m)] = pmm
+        if m + 1 <= lmax:
+            P[(m + 1, m)] = math.sqrt(2.0 * m + 3.0) * x * pmm
+        for l in range(m + 2, lmax + 1):
+            a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+            b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+            P[(l, m)] = a * (x * P[(l - 1, m)] - b * P[(l - 2, m)])
     out = []
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
-            y = sph_harm_y(l, abs(m), theta, phi)
             if m > 0:
-                out.append(math.sqrt(2.0) * (-1) ** m * y.real)
+                out.append(math.sqrt(2.0) * P[(l, m)] * np.cos(m * phi))
             elif m < 0:
-                out.append(math.sqrt(2.0) * (-1) ** m * y.imag)
+                out.append(math.sqrt(2.0) * P[(l, -m)] * np.sin(-m * phi))
             else:
-                out.append(y.real)
-    return np.stack(out) if out else np.zeros((0,) + theta.shape)
+                out.append(P[(l, 0)])
+    return np.stack(out) if out else np.zeros((0,) + np.shape(theta))
 
 
 def br_map(N: int, lmax: int, seed: int, peak_gauss: float = 5.0) -> np.ndarray:

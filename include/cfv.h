@@ -122,6 +122,15 @@ cfv_status cfv_dots(cfv_ctx* ctx, const double* V, int32_t k, const double* w, d
 /* y = a*x + b*y over n values (a, b scalars from the host). */
 cfv_status cfv_axpby(cfv_ctx* ctx, int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 
+/* ------------------------------------------------------------ profiling --
+ * While enabled, every kernel launch of the context is bracketed by a pair of
+ * HIP events on its launch stream.  cfv_timing_read synchronises on the
+ * recorded events and returns, per kernel name (names: max * 32 chars), the
+ * total milliseconds and the launch count since the previous read, then
+ * clears the record (n = number of names written). */
+cfv_status cfv_timing_enable(cfv_ctx* ctx, int32_t on);
+cfv_status cfv_timing_read(cfv_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

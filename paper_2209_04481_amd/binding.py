@@ -58,6 +58,8 @@ def lib():
         "cfv_norms": ([P, P, P, P, P], c_int32),
         "cfv_dots": ([P, P, c_int32, P, P, P], c_int32),
         "cfv_axpby": ([P, c_int64, c_double, P, c_double, P, P], c_int32),
+        "cfv_timing_enable": ([P, c_int32], c_int32),
+        "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -198,6 +200,22 @@ class Context:
         o = out if out is not None else self._new(k)
         check(lib().cfv_dots(self._h, _ptr(V), int(k), _ptr(w), _ptr(o), _stream(stream)))
         return o
+
+    def timing_enable(self, on=True):
+        check(lib().cfv_timing_enable(self._h, int(bool(on))))
+
+    def timing_read(self, max_names=32):
+        """{kernel name: (total ms, launches)} since the previous read."""
+        names = ctypes.create_string_buffer(32 * max_names)
+        ms = (c_double * max_names)()
+        cnt = (c_int64 * max_names)()
+        n = c_int32()
+        check(lib().cfv_timing_read(self._h, max_names, names, ms, cnt, ctypes.byref(n)))
+        out = {}
+        for q in range(n.value):
+            nm = names.raw[32 * q:32 * q + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[q], cnt[q])
+        return out
 
     def axpby(self, a, x, b, y, stream=None):
         check(lib().cfv_axpby(self._h, y.numel(), float(a), _ptr(x), float(b), _ptr(y), _stream(stream)))

@@ -20,7 +20,7 @@ hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* ou
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, hipStream_t s);
+                      double* A, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
 }  // namespace cfv
 
@@ -30,8 +30,50 @@ struct cfv_grid {
   std::vector<double> D;  // 6 (N+1)^2 3 unit corner directions
 };
 
+// Records an event pair around every kernel launch while enabled.
+struct EventTimer : cfv::KernelTimer {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(const char* name, hipStream_t s) override {
+    Rec r{name, take(), take()};
+    if (r.a) (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+  }
+  void end(hipStream_t s) override {
+    if (!recs.empty() && recs.back().b) (void)hipEventRecord(recs.back().b, s);
+  }
+  void recycle() {
+    for (auto& r : recs) {
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~EventTimer() override {
+    recycle();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct cfv_ctx {
   const cfv_grid* grid = nullptr;
+  EventTimer timer;
+  bool timing = false;
+  cfv::KernelTimer* tm() { return timing ? &timer : nullptr; }
   int device = 0;
   cfv::Params pr{};
   double* dD = nullptr;
@@ -233,7 +275,7 @@ cfv_status cfv_geometry(cfv_ctx* c, double* xc, double* vol, double* xf, double*
 cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
-  CFV_HIP(cfv::launch_residual(c->dev(), U, R, c->W, s));
+  CFV_HIP(cfv::launch_residual(c->dev(), U, R, c->W, s, c->tm()));
   return CFV_OK;
 }
 
@@ -241,14 +283,14 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
                    hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
-  CFV_HIP(cfv::launch_jvp(c->dev(), U, v, dbr, Jv, R, c->W, c->Wd, s));
+  CFV_HIP(cfv::launch_jvp(c->dev(), U, v, dbr, Jv, R, c->W, c->Wd, s, c->tm()));
   return CFV_OK;
 }
 
 cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
-  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, s));
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, s, c->tm()));
   return CFV_OK;
 }
 
@@ -256,7 +298,7 @@ cfv_status cfv_local_dt(cfv_ctx* c, const double* U, double cfl, double* diag, h
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !diag) return fail(CFV_ERR_ARG, "null state or output");
   if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
-  CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, diag, c->W, s));
+  CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, diag, c->W, s, c->tm()));
   return CFV_OK;
 }
 
@@ -279,6 +321,45 @@ cfv_status cfv_axpby(cfv_ctx* c, int64_t n, double a, const double* x, double b,
   if (cfv_status st = check_ctx(c)) return st;
   if (!x || !y || n < 0) return fail(CFV_ERR_ARG, "bad vector arguments");
   CFV_HIP(cfv::launch_axpby(n, a, x, b, y, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_timing_enable(cfv_ctx* c, int32_t on) {
+  if (cfv_status st = check_ctx(c)) return st;
+  c->timing = on != 0;
+  return CFV_OK;
+}
+
+cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!names || !total_ms || !count || !n || max < 1) return fail(CFV_ERR_ARG, "bad timing buffers");
+  std::vector<std::string> keys;
+  std::vector<double> ms;
+  std::vector<int64_t> cnt;
+  for (auto& r : c->timer.recs) {
+    float t = 0.f;
+    if (!r.a || !r.b) continue;
+    CFV_HIP(hipEventSynchronize(r.b));
+    CFV_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    size_t q = 0;
+    while (q < keys.size() && keys[q] != r.name) ++q;
+    if (q == keys.size()) {
+      keys.emplace_back(r.name);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[q] += t;
+    cnt[q] += 1;
+  }
+  c->timer.recycle();
+  const int m = int(keys.size()) < max ? int(keys.size()) : max;
+  for (int q = 0; q < m; ++q) {
+    std::strncpy(names + 32 * q, keys[q].c_str(), 31);
+    names[32 * q + 31] = 0;
+    total_ms[q] = ms[q];
+    count[q] = cnt[q];
+  }
+  *n = m;
   return CFV_OK;
 }
 

@@ -41,11 +41,34 @@ __host__ __device__ __forceinline__ void ghost_prims(const DevGrid& d, int p, in
     outer_ghost(qI, xI, xG, xf, qG, d.pr);
 }
 
+// Optional per-launch timer: brackets each kernel launch with events on the
+// launch stream (see capi.cpp).  Null means no timing.
+struct KernelTimer {
+  virtual void begin(const char* name, hipStream_t s) = 0;
+  virtual void end(hipStream_t s) = 0;
+  virtual ~KernelTimer() = default;
+};
+
+struct TimedScope {
+  KernelTimer* t;
+  hipStream_t s;
+  TimedScope(KernelTimer* t_, const char* name, hipStream_t s_) : t(t_), s(s_) {
+    if (t) t->begin(name, s);
+  }
+  ~TimedScope() {
+    if (t) t->end(s);
+  }
+};
+
 // launchers (residual.hip)
-hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s);
+hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s,
+                           KernelTimer* t = nullptr);
 hipError_t launch_jvp(const DevGrid& d, const double* U, const double* v, const double* dbr, double* Jv, double* R,
-                      double* W, double* Wd, hipStream_t s);
+                      double* W, double* Wd, hipStream_t s, KernelTimer* t = nullptr);
 hipError_t launch_geometry(const DevGrid& d, double* xc, double* vol, double* xf, double* S, hipStream_t s);
-hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s);
+hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s,
+                           KernelTimer* t = nullptr);
+hipError_t launch_grad_limit_forward(const DevGrid& d, const double* U, double* W, hipStream_t s,
+                                     KernelTimer* t = nullptr);
 
 }  // namespace cfv

@@ -223,31 +223,45 @@ __global__ __launch_bounds__(kBlock) void geometry_kernel(DevGrid d, double* xc,
 
 static inline dim3 grid_for(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); }
 
-hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s) {
+hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
-  hipLaunchKernelGGL((grad_limit_kernel<double>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
-                     nullptr);
-  hipLaunchKernelGGL((flux_kernel<double, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
-                     nullptr, R, nullptr, nullptr, 1.0);
+  {
+    TimedScope ts(t, "grad_limit", s);
+    hipLaunchKernelGGL((grad_limit_kernel<double>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
+                       nullptr);
+  }
+  {
+    TimedScope ts(t, "flux", s);
+    hipLaunchKernelGGL((flux_kernel<double, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
+                       nullptr, R, nullptr, nullptr, 1.0);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_jvp(const DevGrid& d, const double* U, const double* v, const double* dbr, double* Jv, double* R,
-                      double* W, double* Wd, hipStream_t s) {
+                      double* W, double* Wd, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
-  hipLaunchKernelGGL((grad_limit_kernel<Dual>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd);
-  hipLaunchKernelGGL((flux_kernel<Dual, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd, R, Jv,
-                     nullptr, 1.0);
+  {
+    TimedScope ts(t, "grad_limit_jvp", s);
+    hipLaunchKernelGGL((grad_limit_kernel<Dual>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd);
+  }
+  {
+    TimedScope ts(t, "flux_jvp", s);
+    hipLaunchKernelGGL((flux_kernel<Dual, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd, R, Jv,
+                       nullptr, 1.0);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_grad_limit_forward(const DevGrid& d, const double* U, double* W, hipStream_t s) {
+hipError_t launch_grad_limit_forward(const DevGrid& d, const double* U, double* W, hipStream_t s, KernelTimer* t) {
+  TimedScope ts(t, "grad_limit", s);
   hipLaunchKernelGGL((grad_limit_kernel<double>), grid_for(d.g.ncells), dim3(kBlock), 0, s, d, U, nullptr, nullptr,
                      W, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s) {
+hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s,
+                           KernelTimer*) {
   const int64_t nc = d.g.ncells;
   hipLaunchKernelGGL((grad_limit_kernel<double>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
                      nullptr);

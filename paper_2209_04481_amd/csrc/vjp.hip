@@ -255,16 +255,20 @@ __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double
   if (c < d.g.ncells) gather_cell(d, U, w, A, gU, c);
 }
 
-hipError_t launch_grad_limit_forward(const DevGrid& d, const double* U, double* W, hipStream_t s);
-
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, hipStream_t s) {
+                      double* A, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
-  hipError_t e = launch_grad_limit_forward(d, U, W, s);
+  hipError_t e = launch_grad_limit_forward(d, U, W, s, t);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, A, gbr);
-  hipLaunchKernelGGL(gather_kernel, grid, dim3(kVBlock), 0, s, d, U, w, A, gU);
+  {
+    TimedScope ts(t, "adjoint", s);
+    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, A, gbr);
+  }
+  {
+    TimedScope ts(t, "adjoint_gather", s);
+    hipLaunchKernelGGL(gather_kernel, grid, dim3(kVBlock), 0, s, d, U, w, A, gU);
+  }
   return hipGetLastError();
 }
 
