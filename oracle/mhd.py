@@ -153,13 +153,13 @@ def rusanov(PL, PR, S, prm: Params):
 def spherical_basis(x):
     """r-hat, theta-hat, phi-hat at x (..., 3), as in Eqs. 20-21.
 
-    On the polar axis (x = y = 0) theta-hat and phi-hat are undefined; there
-    the limit along the meridian phi = 0 is taken: theta-hat = (sign z, 0, 0),
-    phi-hat = (0, 1, 0)."""
+    On the polar axis theta-hat and phi-hat are undefined; within a relative
+    distance 1e-12 of it (where they would be set by rounding) the limit along
+    the meridian phi = 0 is taken: theta-hat = (sign z, 0, 0), phi-hat = (0, 1, 0)."""
     X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
     r = torch.linalg.norm(x, dim=-1)
     rc = torch.sqrt(X * X + Y * Y)
-    axis = rc == 0.0
+    axis = rc <= 1e-12 * r
     rcs = torch.where(axis, torch.ones_like(rc), rc)
     rhat = x / r[..., None]
     that = torch.stack([X * Z / (rcs * r), Y * Z / (rcs * r), -rc / r], dim=-1)

@@ -165,14 +165,15 @@ __host__ __device__ __forceinline__ T rusanov(const T qL[9], const T qR[9], V3 S
   return s;
 }
 
-// spherical unit vectors at x (Eqs. 20-21); on the polar axis, where theta
-// and phi are undefined, the limit along the meridian phi = 0.
+// spherical unit vectors at x (Eqs. 20-21); within a relative distance 1e-12
+// of the polar axis, where theta and phi would be set by rounding, the limit
+// along the meridian phi = 0.
 __host__ __device__ __forceinline__ void sph_basis(V3 x, V3& rh, V3& th, V3& ph) {
   double r = norm3(x);
   double rc = ::sqrt(x.x * x.x + x.y * x.y);
   double ir = 1.0 / r;
   rh = mk(x.x * ir, x.y * ir, x.z * ir);
-  if (rc == 0.0) {
+  if (rc <= 1e-12 * r) {
     th = mk(x.z >= 0.0 ? 1.0 : -1.0, 0.0, 0.0);
     ph = mk(0.0, 1.0, 0.0);
     return;

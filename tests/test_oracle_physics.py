@@ -155,6 +155,10 @@ def test_spherical_basis_on_the_polar_axis_is_the_phi0_limit():
     eps = 1e-9
     for z in (3.0, -2.0):
         x = torch.tensor([[0.0, 0.0, z], [eps, 0.0, z]], dtype=DT)
+        # rounding-level offsets from the axis count as on it
+        xa = torch.tensor([[3e-17, -2e-17, z], [0.0, 0.0, z]], dtype=DT)
+        ra, ta, pa = mhd.spherical_basis(xa)
+        assert torch.equal(ta[0], ta[1]) and torch.equal(pa[0], pa[1])
         rh, th, ph = mhd.spherical_basis(x)
         assert torch.allclose(th[0], th[1], atol=1e-8) and torch.allclose(ph[0], ph[1], atol=1e-8)
         assert torch.allclose(torch.linalg.cross(rh[0], th[0]), ph[0], atol=1e-15)
