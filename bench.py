@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per cell and operation (FP64 SoA, 9 variables)
 ALG_BYTES = {"residual": 144, "jvp": 216, "vjp": 216}
 OP_KERNELS = {
-    "residual": ("grad_limit", "flux"),
-    "jvp": ("grad_limit_jvp", "flux_jvp"),
+    "residual": ("grad_march", "flux_march"),
+    "jvp": ("grad_march_jvp", "flux_march_jvp"),
     "vjp": ("grad_limit", "adjoint", "adjoint_gather"),
 }
 

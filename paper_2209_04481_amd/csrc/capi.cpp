@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "cfv_kernels.hpp"
+#include "cfv_march.hpp"
 
 namespace cfv {
 int reduce_partials_per_vector();
@@ -26,8 +27,18 @@ int64_t vjp_workspace_doubles(const Shape& g);
 
 struct cfv_grid {
   cfv::Shape g;
-  std::vector<double> r;  // Nr + 1
-  std::vector<double> D;  // 6 (N+1)^2 3 unit corner directions
+  std::vector<double> r;   // Nr + 1
+  std::vector<double> D;   // 6 (N+1)^2 3 unit corner directions
+  std::vector<double> cg;  // CG_NCOMP x 6N^2 column geometry
+  std::vector<int32_t> cn; // 8 x 6N^2 angular neighbours and face ownership
+  cfv::GeomRef host_ref() const {
+    cfv::GeomRef G;
+    G.cg = cg.data();
+    G.cn = cn.data();
+    G.r = r.data();
+    G.ncol = g.nb;
+    return G;
+  }
 };
 
 // Records an event pair around every kernel launch while enabled.
@@ -76,7 +87,8 @@ struct cfv_ctx {
   cfv::KernelTimer* tm() { return timing ? &timer : nullptr; }
   int device = 0;
   cfv::Params pr{};
-  double* dD = nullptr;
+  double* dcg = nullptr;
+  int32_t* dcn = nullptr;
   double* dr = nullptr;
   double* dbr = nullptr;
   double* W = nullptr;     // 36 ncells: primitives + limited gradients
@@ -87,8 +99,10 @@ struct cfv_ctx {
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
-    d.G.D = dD;
+    d.G.cg = dcg;
+    d.G.cn = dcn;
     d.G.r = dr;
+    d.G.ncol = grid->g.nb;
     d.pr = pr;
     d.br = dbr;
     return d;
@@ -128,6 +142,64 @@ cfv_status dmalloc(T** p, size_t n) {
   return CFV_OK;
 }
 }  // namespace
+
+// Per-column geometry from the cell vertices at unit radii (see cfv_topo.hpp).
+static void build_column_tables(cfv_grid& G) {
+  using cfv::V3;
+  const cfv::Shape& s = G.g;
+  const int N = s.N, n1 = N + 1;
+  const int64_t ncol = s.nb;
+  G.cg.assign(size_t(cfv::CG_NCOMP) * ncol, 0.0);
+  G.cn.assign(size_t(8) * ncol, 0);
+  auto D = [&](int p, int jj, int ii) {
+    const double* d = &G.D[((size_t(p) * n1 + jj) * n1 + ii) * 3];
+    return cfv::mk(d[0], d[1], d[2]);
+  };
+  auto put = [&](int comp, int64_t col, V3 v) {
+    G.cg[comp * ncol + col] = v.x;
+    G.cg[(comp + 1) * ncol + col] = v.y;
+    G.cg[(comp + 2) * ncol + col] = v.z;
+  };
+  // vertex-formula area and centroid of local face lf of column (p,j,i) with
+  // radii (ra, rb) for the layers dk = 0, 1
+  auto face_at = [&](int p, int j, int i, int lf, double ra, double rb, V3& S, V3& xf) {
+    int off[4][3];
+    cfv::face_vertex_offsets(lf, off);
+    V3 v[4];
+    for (int a = 0; a < 4; ++a) v[a] = (off[a][0] ? rb : ra) * D(p, j + off[a][1], i + off[a][2]);
+    S = 0.5 * cfv::cross3(v[2] - v[0], v[3] - v[1]);
+    xf = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
+  };
+  for (int p = 0; p < 6; ++p)
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        const int64_t col = cfv::column_of(s, p, j, i);
+        put(cfv::CG_CSUM, col, ((D(p, j, i) + D(p, j, i + 1)) + D(p, j + 1, i)) + D(p, j + 1, i + 1));
+        V3 sr, xr;
+        face_at(p, j, i, 1, 1.0, 1.0, sr, xr);
+        put(cfv::CG_SR, col, sr);
+        put(cfv::CG_XR, col, xr);
+        G.cg[cfv::CG_OMEGA * ncol + col] = cfv::dot3(xr, sr);
+        for (int q = 0; q < 4; ++q) {
+          const int lf = 2 + q;
+          cfv::Nbr nb = cfv::neighbour(s, p, 0, j, i, lf);
+          const int64_t ncolv = cfv::column_of(s, nb.p, nb.j, nb.i);
+          const bool own = ncolv > col;
+          V3 a, b, dummy;
+          if (own) {
+            face_at(p, j, i, lf, 0.0, 1.0, a, dummy);
+            face_at(p, j, i, lf, 1.0, 1.0, dummy, b);
+          } else {
+            face_at(nb.p, nb.j, nb.i, nb.back, 0.0, 1.0, a, dummy);
+            face_at(nb.p, nb.j, nb.i, nb.back, 1.0, 1.0, dummy, b);
+          }
+          put(cfv::CG_ANG + 6 * q, col, 2.0 * a);
+          put(cfv::CG_ANG + 6 * q + 3, col, 2.0 * b);
+          G.cn[q * ncol + col] = int32_t(ncolv);
+          G.cn[(4 + q) * ncol + col] = nb.back | (own ? 256 : 0);
+        }
+      }
+}
 
 extern "C" {
 
@@ -170,6 +242,7 @@ cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_gri
         d[1] = y / nrm;
         d[2] = z / nrm;
       }
+  build_column_tables(*g);
   *out = g;
   return CFV_OK;
 }
@@ -230,7 +303,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   const int64_t nc = g->g.ncells;
   cfv_status st;
   c->part_vectors = 32;
-  if ((st = dmalloc(&c->dD, g->D.size())) || (st = dmalloc(&c->dr, g->r.size())) ||
+  if ((st = dmalloc(&c->dcg, g->cg.size())) || (st = dmalloc(&c->dcn, g->cn.size())) ||
+      (st = dmalloc(&c->dr, g->r.size())) ||
       (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->W, size_t(36) * nc)) ||
       (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
@@ -238,7 +312,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
     cfv_ctx_destroy(c);
     return st;
   }
-  hipError_t e = hipMemcpy(c->dD, g->D.data(), g->D.size() * sizeof(double), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(c->dcg, g->cg.data(), g->cg.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->dcn, g->cn.data(), g->cn.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dr, g->r.data(), g->r.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->dbr, 0, size_t(g->g.nb) * sizeof(double));
   if (e != hipSuccess) {
@@ -251,9 +326,10 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
 
 void cfv_ctx_destroy(cfv_ctx* c) {
   if (!c) return;
-  double* bufs[] = {c->dD, c->dr, c->dbr, c->W, c->Wd, c->A, c->part};
+  double* bufs[] = {c->dcg, c->dr, c->dbr, c->W, c->Wd, c->A, c->part};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
+  if (c->dcn) (void)hipFree(c->dcn);
   delete c;
 }
 
@@ -275,7 +351,8 @@ cfv_status cfv_geometry(cfv_ctx* c, double* xc, double* vol, double* xf, double*
 cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
-  CFV_HIP(cfv::launch_residual(c->dev(), U, R, c->W, s, c->tm()));
+  cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, R, nullptr};
+  CFV_HIP(cfv::launch_march(a, false, s, c->tm()));
   return CFV_OK;
 }
 
@@ -283,7 +360,8 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
                    hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
-  CFV_HIP(cfv::launch_jvp(c->dev(), U, v, dbr, Jv, R, c->W, c->Wd, s, c->tm()));
+  cfv::MarchArgs a{c->dev(), U, v, dbr, c->W, c->Wd, R, Jv};
+  CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
   return CFV_OK;
 }
 

@@ -12,7 +12,7 @@ namespace cfv {
 
 // One side of the Rusanov flux: F(q).n, U(q) and lambda = |v_n| + c_f with
 // adjoints Fb, Ub, lamb; accumulates into qb.
-__host__ __device__ inline void flux_side_adjoint(const double q[9], V3 n, const double Fb[9], const double Ub[9],
+__host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3 n, const double Fb[9], const double Ub[9],
                                                   double lamb, double qb[9], double gamma, double c_h) {
   const double rho = q[0], vx = q[1], vy = q[2], vz = q[3], bx = q[4], by = q[5], bz = q[6], p = q[7];
   // forward intermediates
@@ -98,14 +98,14 @@ __host__ __device__ inline void flux_side_adjoint(const double q[9], V3 n, const
 
 // Adjoint of rusanov(): given wb = adjoint of the face flux, accumulate the
 // adjoints of the left and right face states.
-__host__ __device__ inline void rusanov_adjoint(const double qL[9], const double qR[9], V3 S, const double wb[9],
+__host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], const double qR[9], V3 S, const double wb[9],
                                                 double qLb[9], double qRb[9], const Params& pr) {
   const double area = norm3(S);
   const double ia = 1.0 / area;
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
-  double FL[9], FR[9], UL[9], UR[9];
-  const double lamL = phys_flux(qL, n, FL, pr.gamma, pr.c_h);
-  const double lamR = phys_flux(qR, n, FR, pr.gamma, pr.c_h);
+  double UL[9], UR[9];
+  const double lamL = side_speed(qL, n, pr.gamma);
+  const double lamR = side_speed(qR, n, pr.gamma);
   const double s1 = lamL >= lamR ? lamL : lamR;
   const double s = s1 >= pr.c_h ? s1 : pr.c_h;
   prim_to_cons(qL, UL, pr.gamma);
@@ -127,7 +127,7 @@ __host__ __device__ inline void rusanov_adjoint(const double qL[9], const double
 }
 
 // (dP/dU)^T Pb for P = prim(U): returns Ub.
-__host__ __device__ inline void prim_adjoint(const double u[9], const double Pb[9], double Ub[9], double gamma) {
+__host__ __device__ __forceinline__ void prim_adjoint(const double u[9], const double Pb[9], double Ub[9], double gamma) {
   const double rho = u[0];
   const double ir = 1.0 / rho;
   const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;

@@ -60,6 +60,74 @@ struct TimedScope {
   }
 };
 
+// Unweighted least-squares gradient over the six face neighbours,
+//   g = M^-1 sum_n dx_n (q_n - q_c),  M = sum_n dx_n dx_n^T,
+// written as g = sum_n W_n (q_n - q_c) with the weights W_n = M^-1 dx_n (M is
+// inverted by cofactors), followed by the Barth-Jespersen factor.  Extremes
+// over the cell and its neighbours keep the earlier candidate on ties (the
+// cell first, then neighbours in local face order).
+struct LsqWeights {
+  V3 W[6];
+  __host__ __device__ explicit LsqWeights(const V3 dx[6]) {
+    double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      m00 += dx[n].x * dx[n].x; m01 += dx[n].x * dx[n].y; m02 += dx[n].x * dx[n].z;
+      m11 += dx[n].y * dx[n].y; m12 += dx[n].y * dx[n].z; m22 += dx[n].z * dx[n].z;
+    }
+    const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
+    const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
+    const double idet = 1.0 / (m00 * c00 + m01 * c01 + m02 * c02);
+    const double i00 = c00 * idet, i01 = c01 * idet, i02 = c02 * idet;
+    const double i11 = c11 * idet, i12 = c12 * idet, i22 = c22 * idet;
+#pragma unroll
+    for (int n = 0; n < 6; ++n)
+      W[n] = mk(i00 * dx[n].x + i01 * dx[n].y + i02 * dx[n].z, i01 * dx[n].x + i11 * dx[n].y + i12 * dx[n].z,
+                i02 * dx[n].x + i12 * dx[n].y + i22 * dx[n].z);
+  }
+};
+
+// limited gradient of one variable from its cell value and six neighbours
+template <class T>
+__host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const V3 dxf[6], int limiter, T qc,
+                                             const T qn[6], T& gx, T& gy, T& gz) {
+  gx = T(0.0); gy = T(0.0); gz = T(0.0);
+  T qmax = qc, qmin = qc;
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const T dq = qn[n] - qc;
+    gx += L.W[n].x * dq; gy += L.W[n].y * dq; gz += L.W[n].z * dq;
+    qmax = pick_max(qmax, qn[n]);
+    qmin = pick_min(qmin, qn[n]);
+  }
+  if (!limiter) return;
+  // Barth-Jespersen: the smallest ratio (q_ext - q_c) / (g . (x_f - x_c))
+  // below 1, found by comparing magnitudes cross-multiplied (ties keep the
+  // earlier candidate: 1 first, then faces in local order); one division.
+  double bn = 1.0, bd = 1.0;
+  T nb = T(1.0), db = T(1.0);
+  bool act = false;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const T d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
+    const double d2v = val(d2);
+    if (d2v != 0.0) {
+      const T num = d2v > 0.0 ? qmax - qc : qmin - qc;
+      const double an = ::fabs(val(num)), ad = ::fabs(d2v);
+      if (an * bd < bn * ad) {
+        bn = an;
+        bd = ad;
+        nb = num;
+        db = d2;
+        act = true;
+      }
+    }
+  }
+  if (!act) return;
+  const T phi = nb / db;
+  gx = phi * gx; gy = phi * gy; gz = phi * gz;
+}
+
 // launchers (residual.hip)
 hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s,
                            KernelTimer* t = nullptr);

@@ -1,0 +1,471 @@
+// Phase functions of the tiled radial-march kernels (see march.hip).
+// Everything here is __host__ __device__ so that the same code runs on the
+// GPU and under a host emulation of a workgroup.
+#pragma once
+#include "cfv_kernels.hpp"
+
+namespace cfv {
+
+constexpr int kTI = 16, kTJ = 16, kNT = kTI * kTJ;  // tile of columns
+constexpr int kKC = 16;                             // radial layers per chunk
+
+struct MarchArgs {
+  DevGrid d;
+  const double* U;
+  const double* Ud;   // tangent of U (Dual only; null means zero)
+  const double* dbr;  // tangent of the B_r map (Dual only; nullable)
+  double* G;          // limited gradients [27][ncells]
+  double* Gd;         // their tangents (Dual only)
+  double* R;          // residual (nullable for Dual)
+  double* Rd;         // tangent of the residual (Dual only)
+};
+
+struct TileMap {
+  int p, j0, i0, k0, k1;
+};
+
+__host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g) {
+  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kKC - 1) / kKC;
+  return 6 * ntj * nti * nch;
+}
+
+// launch size: a multiple of 8 so that the remap below is a bijection
+__host__ __device__ __forceinline__ int64_t march_blocks(const Shape& g) { return (march_logical_blocks(g) + 7) / 8 * 8; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
+// give each XCD a contiguous range of (tile, chunk) so that neighbouring
+// tiles and chunks, which re-read each other's edge cells, share an L2.
+__host__ __device__ __forceinline__ bool tile_of(const Shape& g, int64_t b, int64_t nb, TileMap& tm) {
+  const int64_t per = nb / 8;
+  const int64_t l = (b % 8) * per + b / 8;
+  if (l >= march_logical_blocks(g)) return false;
+  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kKC - 1) / kKC;
+  int64_t r = l;
+  const int ch = int(r % nch);
+  r /= nch;
+  const int ti = int(r % nti);
+  r /= nti;
+  const int tj = int(r % ntj);
+  tm.p = int(r / ntj);
+  tm.j0 = tj * kTJ;
+  tm.i0 = ti * kTI;
+  tm.k0 = ch * kKC;
+  tm.k1 = tm.k0 + kKC < g.Nr ? tm.k0 + kKC : g.Nr;
+  return true;
+}
+
+// ------------------------------------------------------------- small helpers
+template <class T>
+__host__ __device__ __forceinline__ T* lds_as(double* lds) {
+  return reinterpret_cast<T*>(lds);
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void load_prims(const MarchArgs& a, int64_t c, T P[9]) {
+  const int64_t nc = a.d.g.ncells;
+  T u[9];
+  for (int v = 0; v < 9; ++v) ldT(a.U, a.Ud, v * nc + c, u[v]);
+  cons_to_prim(u, P, a.d.pr.gamma);
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void load_grad(const MarchArgs& a, int64_t c, T Gr[27]) {
+  const int64_t nc = a.d.g.ncells;
+  for (int v = 0; v < 27; ++v) ldT(a.G, a.Gd, v * nc + c, Gr[v]);
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void recon(const T P[9], const T Gr[27], V3 d, T q[9]) {
+  for (int v = 0; v < 9; ++v) q[v] = P[v] + (Gr[3 * v] * d.x + Gr[3 * v + 1] * d.y + Gr[3 * v + 2] * d.z);
+}
+
+__host__ __device__ __forceinline__ void column_pji(const Shape& g, int64_t col, int& p, int& j, int& i) {
+  i = int(col % g.N);
+  j = int((col / g.N) % g.N);
+  p = int(col / (int64_t(g.N) * g.N));
+}
+
+template <class T>
+__host__ __device__ __forceinline__ T map_br(const MarchArgs& a, int64_t col) {
+  T b;
+  ldT(a.d.br, a.dbr, col, b);
+  return b;
+}
+
+// canonical flux across a face: owner on the left
+template <class T>
+__host__ __device__ __forceinline__ void face_flux(bool own, const T qs[9], const T qo[9], V3 S, T F[9], const Params& pr) {
+  const T* L = own ? qs : qo;
+  const T* R = own ? qo : qs;
+  rusanov(L, R, S, F, pr);
+}
+
+// ======================================================== gradient pass
+// LDS plane of (kTI + 2) x (kTJ + 2) positions: the tile at offset (1, 1)
+// and a ring.  Every in-plane neighbour of an active cell has a position:
+// an active in-tile cell publishes itself; a neighbour that is not (tile edge,
+// panel edge, or beyond a partial tile) is loaded by the one active cell next
+// to it, which is the only cell that can see that position.
+constexpr int kPW = kTI + 2, kPH = kTJ + 2, kPlane = kPW * kPH;
+__host__ __device__ __forceinline__ int plane_pos(int ti, int tj) { return (tj + 1) * kPW + (ti + 1); }
+__host__ __device__ __forceinline__ void dir_offset(int q, int& dx, int& dy) {
+  dx = q == 0 ? -1 : q == 1 ? 1 : 0;
+  dy = q == 2 ? -1 : q == 3 ? 1 : 0;
+}
+
+template <class T>
+struct GState {
+  int p, j, i;
+  int64_t col;
+  bool act;
+  unsigned remote;  // bit q: the neighbour across angular face q is loaded by this cell
+  T Pm[9], P0[9], Pp[9];
+};
+
+template <class T>
+struct GradWG {
+  static constexpr int kTw = int(sizeof(T) / sizeof(double));
+  // primitives plane (9 T per position), then the column centroid sums (3)
+  static constexpr int kLds = 9 * kPlane * kTw + 3 * kPlane;
+
+  __host__ __device__ static bool in_tile_active(const Shape& g, const TileMap& tm, int ti, int tj) {
+    return ti >= 0 && ti < kTI && tj >= 0 && tj < kTJ && tm.i0 + ti < g.N && tm.j0 + tj < g.N;
+  }
+
+  __host__ __device__ static void init(const MarchArgs& a, const TileMap& tm, GState<T>& st, int t, double* lds) {
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    const int ti = t % kTI, tj = t / kTI;
+    st.p = tm.p;
+    st.j = tm.j0 + tj;
+    st.i = tm.i0 + ti;
+    st.act = st.j < g.N && st.i < g.N;
+    st.remote = 0;
+    if (!st.act) return;
+    st.col = column_of(g, st.p, st.j, st.i);
+    double* cs = lds + 9 * kPlane * kTw;
+    const V3 c0 = cg3(G, CG_CSUM, st.col);
+    const int me = plane_pos(ti, tj);
+    cs[me] = c0.x; cs[kPlane + me] = c0.y; cs[2 * kPlane + me] = c0.z;
+    for (int q = 0; q < 4; ++q) {
+      int dx, dy;
+      dir_offset(q, dx, dy);
+      if (in_tile_active(g, tm, ti + dx, tj + dy)) continue;
+      st.remote |= 1u << q;
+      const V3 cn = cg3(G, CG_CSUM, G.cn[q * G.ncol + st.col]);
+      const int pos = plane_pos(ti + dx, tj + dy);
+      cs[pos] = cn.x; cs[kPlane + pos] = cn.y; cs[2 * kPlane + pos] = cn.z;
+    }
+    load_prims(a, cell_index(g, st.p, tm.k0, st.j, st.i), st.P0);
+    if (tm.k0 > 0) load_prims(a, cell_index(g, st.p, tm.k0 - 1, st.j, st.i), st.Pm);
+  }
+
+  __host__ __device__ static void publish(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
+                                          double* lds) {
+    if (!st.act) return;
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    const int ti = t % kTI, tj = t / kTI;
+    if (k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
+    T* L = lds_as<T>(lds);
+    const int me = plane_pos(ti, tj);
+    for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
+    for (int q = 0; q < 4; ++q) {
+      if (!(st.remote & (1u << q))) continue;
+      int dx, dy;
+      dir_offset(q, dx, dy);
+      int np, nj, ni;
+      column_pji(g, G.cn[q * G.ncol + st.col], np, nj, ni);
+      T qn[9];
+      load_prims(a, cell_index(g, np, k, nj, ni), qn);
+      const int pos = plane_pos(ti + dx, tj + dy);
+      for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
+    }
+  }
+
+  __host__ __device__ static void compute(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
+                                          double* lds) {
+    if (!st.act) return;
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    const T* L = lds_as<T>(lds);
+    const double* cs = lds + 9 * kPlane * kTw;
+    const int ti = t % kTI, tj = t / kTI;
+    const double rs = 0.125 * (G.r[k] + G.r[k + 1]);
+    const V3 xc = rs * cg3(G, CG_CSUM, st.col);
+    // geometry: neighbour offsets and face-centroid offsets
+    V3 dx[6], dxf[6];
+    int pos[4];
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) {
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, lf, Nbr{}, 0, S, xf, own);
+      dxf[lf] = xf - xc;
+      if (lf == 0) {
+        dx[0] = (k > 0 ? cell_centre(G, g, st.p, k - 1, st.j, st.i) : ghost_centre(xc, S, xf)) - xc;
+      } else if (lf == 1) {
+        dx[1] = (k + 1 < g.Nr ? cell_centre(G, g, st.p, k + 1, st.j, st.i) : ghost_centre(xc, S, xf)) - xc;
+      } else {
+        int ddx, ddy;
+        dir_offset(lf - 2, ddx, ddy);
+        pos[lf - 2] = plane_pos(ti + ddx, tj + ddy);
+        const int q = pos[lf - 2];
+        dx[lf] = rs * mk(cs[q], cs[kPlane + q], cs[2 * kPlane + q]) - xc;
+      }
+    }
+    const LsqWeights W(dx);
+    // ghost states on the boundary layers
+    T gin[9], gout[9];
+    if (k == 0) {
+      V3 xG;
+      ghost_prims(a.d, st.p, k, st.j, st.i, 0, st.P0, xc, map_br<T>(a, st.col), gin, xG);
+    }
+    if (k + 1 == g.Nr) {
+      V3 xG;
+      ghost_prims(a.d, st.p, k, st.j, st.i, 1, st.P0, xc, T(0.0), gout, xG);
+    }
+    const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      T qn[6];
+      qn[0] = k > 0 ? st.Pm[v] : gin[v];
+      qn[1] = k + 1 < g.Nr ? st.Pp[v] : gout[v];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) qn[2 + q] = L[v * kPlane + pos[q]];
+      T gx, gy, gz;
+      limited_grad(W, dxf, a.d.pr.limiter, st.P0[v], qn, gx, gy, gz);
+      stT(a.G, a.Gd, (3 * v) * g.ncells + c, gx);
+      stT(a.G, a.Gd, (3 * v + 1) * g.ncells + c, gy);
+      stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
+    }
+    for (int v = 0; v < 9; ++v) {
+      st.Pm[v] = st.P0[v];
+      st.P0[v] = st.Pp[v];
+    }
+  }
+};
+
+// ============================================================ flux pass
+template <class T>
+struct FState {
+  int p, j, i;
+  int64_t col;
+  bool act;
+  T qtop[9];  // top-face state of layer k-1
+  T accp[9];  // residual of layer k-1 without its top face
+  T acc[9];   // residual of layer k so far
+  T q3[9], q5[9];
+};
+
+template <class T>
+__host__ __device__ __forceinline__ void store_res(const MarchArgs& a, int64_t c, const T r[9]);
+template <>
+__host__ __device__ __forceinline__ void store_res<double>(const MarchArgs& a, int64_t c, const double r[9]) {
+  for (int v = 0; v < 9; ++v) a.R[v * a.d.g.ncells + c] = r[v];
+}
+template <>
+__host__ __device__ __forceinline__ void store_res<Dual>(const MarchArgs& a, int64_t c, const Dual r[9]) {
+  for (int v = 0; v < 9; ++v) {
+    if (a.R) a.R[v * a.d.g.ncells + c] = r[v].v;
+    a.Rd[v * a.d.g.ncells + c] = r[v].d;
+  }
+}
+
+template <class T>
+struct FluxWG {
+  // two buffers: west/south face states, then east/north face fluxes
+  static constexpr int kLds = 2 * 18 * kNT * int(sizeof(T) / sizeof(double));
+
+  // state of cell (column ncol, layer k) reconstructed at the face centroid xf
+  __host__ __device__ static void remote_state(const MarchArgs& a, int64_t ncol, int k, V3 xf, T q[9]) {
+    const Shape& g = a.d.g;
+    int np, nj, ni;
+    column_pji(g, ncol, np, nj, ni);
+    const int64_t c = cell_index(g, np, k, nj, ni);
+    T P[9], Gr[27];
+    load_prims(a, c, P);
+    load_grad(a, c, Gr);
+    recon(P, Gr, xf - cell_centre(a.d.G, g, np, k, nj, ni), q);
+  }
+
+  __host__ __device__ static void init(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t) {
+    const Shape& g = a.d.g;
+    st.p = tm.p;
+    st.j = tm.j0 + t / kTI;
+    st.i = tm.i0 + t % kTI;
+    st.act = st.j < g.N && st.i < g.N;
+    if (!st.act || tm.k0 == 0) return;
+    // top-face state of the layer below the chunk
+    st.col = column_of(g, st.p, st.j, st.i);
+    const int km = tm.k0 - 1;
+    const int64_t c = cell_index(g, st.p, km, st.j, st.i);
+    T P[9], Gr[27];
+    load_prims(a, c, P);
+    load_grad(a, c, Gr);
+    const V3 xc = cell_centre(a.d.G, g, st.p, km, st.j, st.i);
+    const V3 xf = a.d.G.r[tm.k0] * cg3(a.d.G, CG_XR, st.col);
+    recon(P, Gr, xf - xc, st.qtop);
+  }
+
+  __host__ __device__ static void states(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
+                                         double* lds) {
+    if (!st.act) return;
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    st.col = column_of(g, st.p, st.j, st.i);
+    const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+    T u[9], P[9], Gr[27];
+    for (int v = 0; v < 9; ++v) ldT(a.U, a.Ud, v * g.ncells + c, u[v]);
+    cons_to_prim(u, P, a.d.pr.gamma);
+    load_grad(a, c, Gr);
+    const V3 xc = cell_centre(G, g, st.p, k, st.j, st.i);
+
+    // radial face below: k - 1/2 (owner k-1), or the inner boundary face
+    {
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
+      T qb[9], F[9];
+      recon(P, Gr, xf - xc, qb);
+      if (k == 0) {
+        T qG[9];
+        V3 xG;
+        ghost_prims(a.d, st.p, k, st.j, st.i, 0, P, xc, map_br<T>(a, st.col), qG, xG);
+        rusanov(qb, qG, S, F, a.d.pr);
+        for (int v = 0; v < 9; ++v) st.acc[v] = F[v];
+      } else {
+        rusanov(st.qtop, qb, S, F, a.d.pr);
+        if (k - 1 >= tm.k0) {
+          for (int v = 0; v < 9; ++v) st.accp[v] += F[v];
+          store_res(a, c - int64_t(g.N) * g.N, st.accp);
+        }
+        for (int v = 0; v < 9; ++v) st.acc[v] = -F[v];
+      }
+    }
+    // gravity source
+    {
+      T src[9];
+      gravity_source(u, xc, cell_volume(G, g, st.p, k, st.j, st.i), a.d.pr.G, src);
+      for (int v = 0; v < 9; ++v) st.acc[v] -= src[v];
+    }
+    // top face state (and the outer boundary face)
+    {
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
+      recon(P, Gr, xf - xc, st.qtop);
+      if (k == g.Nr - 1) {
+        T qG[9], F[9];
+        V3 xG;
+        ghost_prims(a.d, st.p, k, st.j, st.i, 1, P, xc, T(0.0), qG, xG);
+        rusanov(st.qtop, qG, S, F, a.d.pr);
+        for (int v = 0; v < 9; ++v) st.acc[v] += F[v];
+      }
+    }
+    // angular face states: west and south to LDS, east and north kept
+    T* Sb = lds_as<T>(lds);
+    for (int q = 0; q < 4; ++q) {
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
+      T s[9];
+      recon(P, Gr, xf - xc, s);
+      if (q == 0)
+        for (int v = 0; v < 9; ++v) Sb[v * kNT + t] = s[v];
+      else if (q == 2)
+        for (int v = 0; v < 9; ++v) Sb[(9 + v) * kNT + t] = s[v];
+      else if (q == 1)
+        for (int v = 0; v < 9; ++v) st.q3[v] = s[v];
+      else
+        for (int v = 0; v < 9; ++v) st.q5[v] = s[v];
+    }
+  }
+
+  __host__ __device__ static void faces(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
+                                        double* lds) {
+    if (!st.act) return;
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    const T* Sb = lds_as<T>(lds);
+    T* Fb = lds_as<T>(lds) + 18 * kNT;
+    const int ti = t % kTI, tj = t / kTI;
+    for (int q = 0; q < 4; ++q) {
+      const bool east = q == 1 || q == 3;
+      const bool edge_west = q == 0 && ti == 0;
+      const bool edge_south = q == 2 && tj == 0;
+      if (!east && !edge_west && !edge_south) continue;
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
+      const int64_t nbcol = G.cn[q * G.ncol + st.col];
+      T qs[9], qo[9], F[9];
+      if (q == 1) {
+        for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
+        if (st.i + 1 < g.N && ti + 1 < kTI)
+          for (int v = 0; v < 9; ++v) qo[v] = Sb[v * kNT + t + 1];
+        else
+          remote_state(a, nbcol, k, xf, qo);
+      } else if (q == 3) {
+        for (int v = 0; v < 9; ++v) qs[v] = st.q5[v];
+        if (st.j + 1 < g.N && tj + 1 < kTJ)
+          for (int v = 0; v < 9; ++v) qo[v] = Sb[(9 + v) * kNT + t + kTI];
+        else
+          remote_state(a, nbcol, k, xf, qo);
+      } else {
+        const int off = q == 0 ? 0 : 9;
+        for (int v = 0; v < 9; ++v) qs[v] = Sb[(off + v) * kNT + t];
+        remote_state(a, nbcol, k, xf, qo);
+      }
+      face_flux(own, qs, qo, S, F, a.d.pr);
+      for (int v = 0; v < 9; ++v) st.acc[v] += own ? F[v] : -F[v];
+      if (q == 1)
+        for (int v = 0; v < 9; ++v) Fb[v * kNT + t] = F[v];
+      else if (q == 3)
+        for (int v = 0; v < 9; ++v) Fb[(9 + v) * kNT + t] = F[v];
+    }
+    (void)tm;
+  }
+
+  __host__ __device__ static void accumulate(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
+                                             double* lds) {
+    if (!st.act) return;
+    const Shape& g = a.d.g;
+    const GeomRef& G = a.d.G;
+    const T* Fb = lds_as<T>(lds) + 18 * kNT;
+    const int ti = t % kTI, tj = t / kTI;
+    if (ti > 0) {
+      const bool own = (G.cn[4 * G.ncol + st.col] >> 8) != 0;
+      for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[v * kNT + t - 1] : -Fb[v * kNT + t - 1];
+    }
+    if (tj > 0) {
+      const bool own = (G.cn[6 * G.ncol + st.col] >> 8) != 0;
+      for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[(9 + v) * kNT + t - kTI] : -Fb[(9 + v) * kNT + t - kTI];
+    }
+    for (int v = 0; v < 9; ++v) st.accp[v] = st.acc[v];
+    if (k == g.Nr - 1) store_res(a, cell_index(g, st.p, k, st.j, st.i), st.acc);
+    (void)tm;
+  }
+
+  // the last layer of the chunk still needs the radial face above it
+  __host__ __device__ static void finish(const MarchArgs& a, const TileMap& tm, FState<T>& st, int) {
+    if (!st.act || tm.k1 >= a.d.g.Nr) return;
+    const Shape& g = a.d.g;
+    const int k = tm.k1;
+    const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+    T P[9], Gr[27], qb[9], F[9];
+    load_prims(a, c, P);
+    load_grad(a, c, Gr);
+    V3 S, xf;
+    bool own;
+    canon_face(a.d.G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
+    recon(P, Gr, xf - cell_centre(a.d.G, g, st.p, k, st.j, st.i), qb);
+    rusanov(st.qtop, qb, S, F, a.d.pr);
+    for (int v = 0; v < 9; ++v) st.accp[v] += F[v];
+    store_res(a, c - int64_t(g.N) * g.N, st.accp);
+  }
+};
+
+hipError_t launch_march(const MarchArgs& a, bool dual, hipStream_t s, KernelTimer* t);
+
+}  // namespace cfv

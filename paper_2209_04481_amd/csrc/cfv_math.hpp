@@ -115,27 +115,13 @@ __host__ __device__ __forceinline__ void prim_to_cons(const T q[9], T u[9], doub
   u[8] = q[8];
 }
 
-// normal physical flux for unit n; also returns |v_n| + c_f
+// |v_n| + c_f of one side (c_f the fast magnetosonic speed along n)
 template <class T>
-__host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], double gamma, double c_h) {
-  T rho = q[0], vx = q[1], vy = q[2], vz = q[3], bx = q[4], by = q[5], bz = q[6], p = q[7];
-  T vn = vx * n.x + vy * n.y + vz * n.z;
+__host__ __device__ __forceinline__ T side_speed(const T q[9], V3 n, double gamma) {
+  T rho = q[0], bx = q[4], by = q[5], bz = q[6], p = q[7];
+  T vn = q[1] * n.x + q[2] * n.y + q[3] * n.z;
   T bn = bx * n.x + by * n.y + bz * n.z;
   T B2 = bx * bx + by * by + bz * bz;
-  T v2 = vx * vx + vy * vy + vz * vz;
-  T pT = p + 0.5 * B2;
-  T E = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
-  T rvn = rho * vn;
-  F[0] = rvn;
-  F[1] = rvn * vx + pT * n.x - bx * bn;
-  F[2] = rvn * vy + pT * n.y - by * bn;
-  F[3] = rvn * vz + pT * n.z - bz * bn;
-  F[4] = vn * bx - bn * vx + q[8] * n.x;
-  F[5] = vn * by - bn * vy + q[8] * n.y;
-  F[6] = vn * bz - bn * vz + q[8] * n.z;
-  F[7] = (E + pT) * vn - bn * (vx * bx + vy * by + vz * bz);
-  F[8] = (c_h * c_h) * bn;
-  // fast magnetosonic speed
   T irho = 1.0 / rho;
   T a2 = gamma * p * irho;
   T b2 = B2 * irho;
@@ -147,21 +133,52 @@ __host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], doub
   return tabs(vn) + cf;
 }
 
+// F += wf * (F(q).n) + wu * U(q): one side's share of the Rusanov flux
+template <class T>
+__host__ __device__ __forceinline__ void side_accumulate(const T q[9], V3 n, double wf, T wu, T F[9],
+                                                         double gamma, double c_h) {
+  T rho = q[0], vx = q[1], vy = q[2], vz = q[3], bx = q[4], by = q[5], bz = q[6], p = q[7], psi = q[8];
+  T vn = vx * n.x + vy * n.y + vz * n.z;
+  T bn = bx * n.x + by * n.y + bz * n.z;
+  T B2 = bx * bx + by * by + bz * bz;
+  T v2 = vx * vx + vy * vy + vz * vz;
+  T pT = p + 0.5 * B2;
+  T E = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
+  T rvn = rho * vn;
+  T vb = vx * bx + vy * by + vz * bz;
+  F[0] += wf * rvn + wu * rho;
+  F[1] += wf * (rvn * vx + pT * n.x - bx * bn) + wu * (rho * vx);
+  F[2] += wf * (rvn * vy + pT * n.y - by * bn) + wu * (rho * vy);
+  F[3] += wf * (rvn * vz + pT * n.z - bz * bn) + wu * (rho * vz);
+  F[4] += wf * (vn * bx - bn * vx + psi * n.x) + wu * bx;
+  F[5] += wf * (vn * by - bn * vy + psi * n.y) + wu * by;
+  F[6] += wf * (vn * bz - bn * vz + psi * n.z) + wu * bz;
+  F[7] += wf * ((E + pT) * vn - bn * vb) + wu * E;
+  F[8] += wf * ((c_h * c_h) * bn) + wu * psi;
+}
+
+// normal physical flux for unit n; also returns |v_n| + c_f
+template <class T>
+__host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], double gamma, double c_h) {
+  for (int v = 0; v < 9; ++v) F[v] = T(0.0);
+  side_accumulate(q, n, 1.0, T(0.0), F, gamma, c_h);
+  return side_speed(q, n, gamma);
+}
+
 // Rusanov flux through the face of vector area S (L -> R); returns s.
+//   F = (F_L + F_R)/2 |S| - s/2 (U_R - U_L) |S|,  s = max(lam_L, lam_R, c_h)
 template <class T>
 __host__ __device__ __forceinline__ T rusanov(const T qL[9], const T qR[9], V3 S, T F[9], const Params& pr) {
-  double area = norm3(S);
-  double ia = 1.0 / area;
-  V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
-  T FL[9], FR[9], UL[9], UR[9];
-  T lamL = phys_flux(qL, n, FL, pr.gamma, pr.c_h);
-  T lamR = phys_flux(qR, n, FR, pr.gamma, pr.c_h);
-  T s = pick_max(lamL, lamR);
+  const double area = norm3(S);
+  const double ia = 1.0 / area;
+  const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
+  T s = pick_max(side_speed(qL, n, pr.gamma), side_speed(qR, n, pr.gamma));
   s = pick_max(s, T(pr.c_h));
-  prim_to_cons(qL, UL, pr.gamma);
-  prim_to_cons(qR, UR, pr.gamma);
-#pragma unroll
-  for (int v = 0; v < 9; ++v) F[v] = (0.5 * (FL[v] + FR[v]) - 0.5 * s * (UR[v] - UL[v])) * area;
+  const T hs = 0.5 * s;
+  for (int v = 0; v < 9; ++v) F[v] = T(0.0);
+  side_accumulate(qL, n, 0.5, hs, F, pr.gamma, pr.c_h);
+  side_accumulate(qR, n, 0.5, -hs, F, pr.gamma, pr.c_h);
+  for (int v = 0; v < 9; ++v) F[v] = F[v] * area;
   return s;
 }
 

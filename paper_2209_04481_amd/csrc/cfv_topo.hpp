@@ -30,7 +30,7 @@ struct EdgeLink {
 };
 enum : int8_t { EW = 0, EE = 1, ES = 2, EN = 3 };
 
-__host__ __device__ inline EdgeLink edge_link(int p, int e) {
+__host__ __device__ __forceinline__ EdgeLink edge_link(int p, int e) {
   // clang-format off
   const EdgeLink T[6][4] = {
     {{3, 1, 2, EE}, {1, 0, 2, EW}, {5, 2, 1, EN}, {4, 2, 0, ES}},
@@ -44,7 +44,7 @@ __host__ __device__ inline EdgeLink edge_link(int p, int e) {
   return T[p][e];
 }
 
-__host__ __device__ inline int edge_coord(int code, int s, int M) {
+__host__ __device__ __forceinline__ int edge_coord(int code, int s, int M) {
   return code == 0 ? 0 : code == 1 ? M : code == 2 ? s : M - s;
 }
 
@@ -53,11 +53,11 @@ struct Shape {
   int64_t ncells, nb;
 };
 
-__host__ __device__ inline int64_t cell_index(const Shape& g, int p, int k, int j, int i) {
+__host__ __device__ __forceinline__ int64_t cell_index(const Shape& g, int p, int k, int j, int i) {
   return ((int64_t(p) * g.Nr + k) * g.N + j) * g.N + i;
 }
 
-__host__ __device__ inline void decode(const Shape& g, int64_t c, int& p, int& k, int& j, int& i) {
+__host__ __device__ __forceinline__ void decode(const Shape& g, int64_t c, int& p, int& k, int& j, int& i) {
   i = int(c % g.N);
   int64_t t = c / g.N;
   j = int(t % g.N);
@@ -72,7 +72,7 @@ struct Nbr {
   int back;  // local face of the neighbour that faces back (cells only)
 };
 
-__host__ __device__ inline Nbr neighbour(const Shape& g, int p, int k, int j, int i, int lf) {
+__host__ __device__ __forceinline__ Nbr neighbour(const Shape& g, int p, int k, int j, int i, int lf) {
   Nbr n{0, p, k, j, i, lf ^ 1};
   const int N = g.N, M = g.N - 1;
   int e = -1, s = 0;
@@ -99,21 +99,9 @@ __host__ __device__ inline Nbr neighbour(const Shape& g, int p, int k, int j, in
   return n;
 }
 
-// ------------------------------------------------------------------ geometry
-// D: unit corner directions [p][j'][i'][3], j', i' in 0..N; r: Nr+1 radii.
-struct GeomRef {
-  const double* D;
-  const double* r;
-};
-
-__host__ __device__ inline V3 corner(const GeomRef& G, const Shape& g, int p, int jj, int ii) {
-  const double* d = G.D + ((int64_t(p) * (g.N + 1) + jj) * (g.N + 1) + ii) * 3;
-  return mk(d[0], d[1], d[2]);
-}
-
 // vertex offsets (dk, dj, di) per local face, ordered so that
 // S = 1/2 (v2 - v0) x (v3 - v1) points out of the cell.
-__host__ __device__ inline void face_vertex_offsets(int lf, int off[4][3]) {
+__host__ __device__ __forceinline__ void face_vertex_offsets(int lf, int off[4][3]) {
   // clang-format off
   const int T[6][4][3] = {
     {{0,0,0},{0,1,0},{0,1,1},{0,0,1}},
@@ -128,52 +116,79 @@ __host__ __device__ inline void face_vertex_offsets(int lf, int off[4][3]) {
     for (int b = 0; b < 3; ++b) off[a][b] = T[lf][a][b];
 }
 
-// vector area (outward from cell (p,k,j,i)) and centroid of local face lf
-__host__ __device__ inline void face_geom(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
-                                          V3& S, V3& xf) {
-  int off[4][3];
-  face_vertex_offsets(lf, off);
-  V3 v[4];
-  for (int a = 0; a < 4; ++a) {
-    double r = G.r[k + off[a][0]];
-    v[a] = r * corner(G, g, p, j + off[a][1], i + off[a][2]);
-  }
-  V3 c = cross3(v[2] - v[0], v[3] - v[1]);
-  S = 0.5 * c;
-  xf = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
+// ------------------------------------------------------------------ geometry
+// All cell and face geometry is separable in the radius: a cell (column col,
+// layer k) has centroid (r_k + r_{k+1})/8 * csum, volume (r_{k+1}^3 - r_k^3)/3 *
+// omega, radial faces at radius r with vector area r^2 sr and centroid r xr,
+// and angular faces with vector area (r_{k+1}^2 - r_k^2)/2 * a and centroid
+// (r_k + r_{k+1})/4 * b.  The per-column numbers are built on the host from
+// the cell vertices (the vertex formulas at unit radii), and for every angular
+// face they are the OWNER's numbers, so both sides of a face use the same
+// values.  Column tables, each of length ncol = 6N^2, component-major:
+enum : int {
+  CG_CSUM = 0, CG_OMEGA = 3, CG_SR = 4, CG_XR = 7, CG_ANG = 10,  // + 6*q: a (3), b (3), q = lf - 2
+  CG_NCOMP = 34
+};
+// integer tables (component-major, 4 angular faces q = lf - 2):
+//   cn[q*ncol + col]      neighbour column across face q
+//   cn[(4+q)*ncol + col]  back local face of the neighbour | owner flag << 8
+struct GeomRef {
+  const double* cg;
+  const int32_t* cn;
+  const double* r;
+  int64_t ncol;
+};
+
+__host__ __device__ __forceinline__ int64_t column_of(const Shape& g, int p, int j, int i) {
+  return (int64_t(p) * g.N + j) * g.N + i;
 }
 
-__host__ __device__ inline V3 cell_centre(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  V3 s = ((corner(G, g, p, j, i) + corner(G, g, p, j, i + 1)) + corner(G, g, p, j + 1, i)) + corner(G, g, p, j + 1, i + 1);
-  return (0.125 * (G.r[k] + G.r[k + 1])) * s;
+__host__ __device__ __forceinline__ V3 cg3(const GeomRef& G, int comp, int64_t col) {
+  return mk(G.cg[comp * G.ncol + col], G.cg[(comp + 1) * G.ncol + col], G.cg[(comp + 2) * G.ncol + col]);
 }
 
-// V = 1/3 sum_f x_f . S_f; only the two radial faces contribute (the angular
-// faces lie in planes through the origin), giving (r1^3 - r0^3)/3 * omega.
-__host__ __device__ inline double cell_volume(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  V3 d0 = corner(G, g, p, j, i), d1 = corner(G, g, p, j, i + 1);
-  V3 d2 = corner(G, g, p, j + 1, i + 1), d3 = corner(G, g, p, j + 1, i);
-  V3 c = cross3(d2 - d0, d3 - d1);
-  double omega = dot3(0.25 * (((d0 + d1) + d2) + d3), 0.5 * c);
-  double r0 = G.r[k], r1 = G.r[k + 1];
-  return (r1 * r1 * r1 - r0 * r0 * r0) * omega / 3.0;
+__host__ __device__ __forceinline__ V3 cell_centre(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
+  return (0.125 * (G.r[k] + G.r[k + 1])) * cg3(G, CG_CSUM, column_of(g, p, j, i));
+}
+
+__host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
+  const double r0 = G.r[k], r1 = G.r[k + 1];
+  return (r1 * r1 * r1 - r0 * r0 * r0) * G.cg[CG_OMEGA * G.ncol + column_of(g, p, j, i)] / 3.0;
 }
 
 // canonical geometry of the face across local face lf of cell (p,k,j,i): the
-// owner's vector area (pointing from the owner to the other side) and the
-// owner's centroid; owner tells whether (p,k,j,i) is the owner.
-__host__ __device__ inline void canon_face(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
-                                           const Nbr& nb, int64_t self, V3& S, V3& xf, bool& owner) {
-  owner = (nb.id >= g.ncells) || (nb.id > self);
-  if (owner) {
-    face_geom(G, g, p, k, j, i, lf, S, xf);
-  } else {
-    face_geom(G, g, nb.p, nb.k, nb.j, nb.i, nb.back, S, xf);
+// owner's vector area (pointing from the owner to the other side), the
+// owner's centroid, and whether (p,k,j,i) is the owner.  The owner of a face
+// is the cell with the lower index, or the interior cell on the boundary.
+__host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
+                                           const Nbr&, int64_t, V3& S, V3& xf, bool& owner) {
+  const int64_t col = column_of(g, p, j, i);
+  if (lf < 2) {
+    const double r = G.r[k + lf];
+    const V3 sr = cg3(G, CG_SR, col);
+    S = (r * r) * sr;
+    xf = r * cg3(G, CG_XR, col);
+    owner = lf == 1 || k == 0;
+    if (lf == 0 && k == 0) S = mk(-S.x, -S.y, -S.z);  // boundary face: outward
+    return;
   }
+  const int q = lf - 2;
+  const double r0 = G.r[k], r1 = G.r[k + 1];
+  S = (0.5 * (r1 * r1 - r0 * r0)) * cg3(G, CG_ANG + 6 * q, col);
+  xf = (0.25 * (r0 + r1)) * cg3(G, CG_ANG + 6 * q + 3, col);
+  owner = (G.cn[(4 + q) * G.ncol + col] >> 8) != 0;
+}
+
+// vector area pointing out of cell (p,k,j,i) and centroid of its face lf
+__host__ __device__ __forceinline__ void face_geom(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
+                                          V3& S, V3& xf) {
+  bool own;
+  canon_face(G, g, p, k, j, i, lf, Nbr{}, 0, S, xf, own);
+  if (!own) S = mk(-S.x, -S.y, -S.z);
 }
 
 // mirror of the boundary cell centre across its boundary face
-__host__ __device__ inline V3 ghost_centre(V3 xI, V3 S, V3 xf) {
+__host__ __device__ __forceinline__ V3 ghost_centre(V3 xI, V3 S, V3 xf) {
   double ia = 1.0 / norm3(S);
   V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
   double d = dot3(xf - xI, n);

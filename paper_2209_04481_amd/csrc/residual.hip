@@ -39,71 +39,35 @@ __host__ __device__ inline void grad_limit_cell(const DevGrid& d, const double* 
   cons_to_prim(u, qc, d.pr.gamma);
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
 
-  // moment matrix, right-hand sides, extremes, face offsets
-  double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
-  T rx[9], ry[9], rz[9], qmax[9], qmin[9];
+  T qn[6][9];
+  V3 dx[6], dxf[6];
 #pragma unroll
-  for (int v = 0; v < 9; ++v) {
-    rx[v] = T(0.0); ry[v] = T(0.0); rz[v] = T(0.0);
-    qmax[v] = qc[v]; qmin[v] = qc[v];
-  }
-  V3 dxf[6];
   for (int lf = 0; lf < 6; ++lf) {
     Nbr nb = neighbour(d.g, p, k, j, i, lf);
     V3 S, xf;
     bool own;
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
     dxf[lf] = xf - xc;
-    T qn[9];
     V3 xn;
     if (nb.id >= nc) {
       const int64_t col = (int64_t(p) * d.g.N + j) * d.g.N + i;
       T br;
       if (lf == 0) ldT(d.br, dbr, col, br); else br = T(0.0);
-      ghost_prims(d, p, k, j, i, lf, qc, xc, br, qn, xn);
+      ghost_prims(d, p, k, j, i, lf, qc, xc, br, qn[lf], xn);
     } else {
       T un[9];
-#pragma unroll
       for (int v = 0; v < 9; ++v) ldT(U, Ud, v * nc + nb.id, un[v]);
-      cons_to_prim(un, qn, d.pr.gamma);
+      cons_to_prim(un, qn[lf], d.pr.gamma);
       xn = cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
     }
-    const V3 dx = xn - xc;
-    m00 += dx.x * dx.x; m01 += dx.x * dx.y; m02 += dx.x * dx.z;
-    m11 += dx.y * dx.y; m12 += dx.y * dx.z; m22 += dx.z * dx.z;
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-      T dq = qn[v] - qc[v];
-      rx[v] += dx.x * dq; ry[v] += dx.y * dq; rz[v] += dx.z * dq;
-      qmax[v] = pick_max(qmax[v], qn[v]);
-      qmin[v] = pick_min(qmin[v], qn[v]);
-    }
+    dx[lf] = xn - xc;
   }
-  // inverse of the symmetric moment matrix by cofactors
-  const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
-  const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
-  const double idet = 1.0 / (m00 * c00 + m01 * c01 + m02 * c02);
-  const double i00 = c00 * idet, i01 = c01 * idet, i02 = c02 * idet;
-  const double i11 = c11 * idet, i12 = c12 * idet, i22 = c22 * idet;
-
+  const LsqWeights L(dx);
 #pragma unroll
   for (int v = 0; v < 9; ++v) {
-    T gx = i00 * rx[v] + i01 * ry[v] + i02 * rz[v];
-    T gy = i01 * rx[v] + i11 * ry[v] + i12 * rz[v];
-    T gz = i02 * rx[v] + i12 * ry[v] + i22 * rz[v];
-    if (d.pr.limiter) {
-      T phi = T(1.0);
-      for (int lf = 0; lf < 6; ++lf) {
-        T d2 = gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z;
-        double d2v = val(d2);
-        if (d2v != 0.0) {
-          T num = d2v > 0.0 ? qmax[v] - qc[v] : qmin[v] - qc[v];
-          T pf = pick_min(T(1.0), num / d2);
-          phi = pick_min(phi, pf);
-        }
-      }
-      gx = phi * gx; gy = phi * gy; gz = phi * gz;
-    }
+    T q6[6] = {qn[0][v], qn[1][v], qn[2][v], qn[3][v], qn[4][v], qn[5][v]};
+    T gx, gy, gz;
+    limited_grad(L, dxf, d.pr.limiter, qc[v], q6, gx, gy, gz);
     stT(W, Wd, v * nc + c, qc[v]);
     stT(W, Wd, (9 + 3 * v) * nc + c, gx);
     stT(W, Wd, (10 + 3 * v) * nc + c, gy);

@@ -59,16 +59,8 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const int64_t col = (int64_t(p) * d.g.N + j) * d.g.N + i;
   const double brc = d.br[col];
 
-  // ---- recompute c's own stencil: offsets, extremes, unlimited gradient
+  // ---- recompute c's own stencil: offsets, weights, extremes, unlimited gradient
   V3 dx[6], dxf[6];
-  double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
-  double rx[9], ry[9], rz[9], qmax[9], qmin[9];
-  int amax[9], amin[9];
-  for (int v = 0; v < 9; ++v) {
-    rx[v] = ry[v] = rz[v] = 0.0;
-    qmax[v] = qmin[v] = Pc[v];
-    amax[v] = amin[v] = -1;
-  }
   double qGin[9], qGout[9];
   for (int lf = 0; lf < 6; ++lf) {
     Nbr nb = neighbour(d.g, p, k, j, i, lf);
@@ -76,30 +68,32 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     bool own;
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
     dxf[lf] = xf - xc;
-    double qn[9];
     V3 xn;
     if (nb.id >= nc) {
-      ghost_prims(d, p, k, j, i, lf, Pc, xc, lf == 0 ? brc : 0.0, qn, xn);
-      for (int v = 0; v < 9; ++v) (lf == 0 ? qGin : qGout)[v] = qn[v];
+      ghost_prims(d, p, k, j, i, lf, Pc, xc, lf == 0 ? brc : 0.0, lf == 0 ? qGin : qGout, xn);
     } else {
-      for (int v = 0; v < 9; ++v) qn[v] = W[v * nc + nb.id];
       xn = cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
     }
     dx[lf] = xn - xc;
-    m00 += dx[lf].x * dx[lf].x; m01 += dx[lf].x * dx[lf].y; m02 += dx[lf].x * dx[lf].z;
-    m11 += dx[lf].y * dx[lf].y; m12 += dx[lf].y * dx[lf].z; m22 += dx[lf].z * dx[lf].z;
+  }
+  const LsqWeights Lw(dx);
+  double gxs[9], gys[9], gzs[9], qmax[9], qmin[9];
+  int amax[9], amin[9];
+  for (int v = 0; v < 9; ++v) {
+    gxs[v] = gys[v] = gzs[v] = 0.0;
+    qmax[v] = qmin[v] = Pc[v];
+    amax[v] = amin[v] = -1;
+  }
+  for (int lf = 0; lf < 6; ++lf) {
+    Nbr nb = neighbour(d.g, p, k, j, i, lf);
     for (int v = 0; v < 9; ++v) {
-      const double dq = qn[v] - Pc[v];
-      rx[v] += dx[lf].x * dq; ry[v] += dx[lf].y * dq; rz[v] += dx[lf].z * dq;
-      if (!(qmax[v] >= qn[v])) { qmax[v] = qn[v]; amax[v] = lf; }
-      if (!(qmin[v] <= qn[v])) { qmin[v] = qn[v]; amin[v] = lf; }
+      const double qn = nb.id >= nc ? (lf == 0 ? qGin : qGout)[v] : W[v * nc + nb.id];
+      const double dq = qn - Pc[v];
+      gxs[v] += Lw.W[lf].x * dq; gys[v] += Lw.W[lf].y * dq; gzs[v] += Lw.W[lf].z * dq;
+      if (!(qmax[v] >= qn)) { qmax[v] = qn; amax[v] = lf; }
+      if (!(qmin[v] <= qn)) { qmin[v] = qn; amin[v] = lf; }
     }
   }
-  const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
-  const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
-  const double idet = 1.0 / (m00 * c00 + m01 * c01 + m02 * c02);
-  const double i00 = c00 * idet, i01 = c01 * idet, i02 = c02 * idet;
-  const double i11 = c11 * idet, i12 = c12 * idet, i22 = c22 * idet;
 
   // ---- flux adjoints: own side (and ghost side) of each face
   double Pb[9], Gb[27], PbGin[9], PbGout[9];
@@ -153,28 +147,36 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   for (int lf = 0; lf < 6; ++lf)
     for (int v = 0; v < 9; ++v) out[lf][v] = 0.0;
   for (int v = 0; v < 9; ++v) {
-    const double gx = i00 * rx[v] + i01 * ry[v] + i02 * rz[v];
-    const double gy = i01 * rx[v] + i11 * ry[v] + i12 * rz[v];
-    const double gz = i02 * rx[v] + i12 * ry[v] + i22 * rz[v];
+    const double gx = gxs[v], gy = gys[v], gz = gzs[v];
     double gbx = Gb[3 * v], gby = Gb[3 * v + 1], gbz = Gb[3 * v + 2];
     if (d.pr.limiter) {
-      double phi = 1.0, num = 0.0, den = 1.0;
+      // the same choice as the forward limiter (limited_grad)
+      double phi = 1.0, num = 0.0, den = 1.0, bn = 1.0, bd = 1.0;
       int act = -1;
-      for (int lf = 0; lf < 6; ++lf) {
-        const double d2 = gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z;
+      V3 dact = mk(0.0, 0.0, 0.0);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const double d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
         if (d2 != 0.0) {
           const double nm = d2 > 0.0 ? qmax[v] - Pc[v] : qmin[v] - Pc[v];
-          const double r = nm / d2;
-          const double pf = 1.0 <= r ? 1.0 : r;
-          if (!(phi <= pf)) { phi = pf; act = lf; num = nm; den = d2; }
+          const double an = ::fabs(nm), ad = ::fabs(d2);
+          if (an * bd < bn * ad) {
+            bn = an;
+            bd = ad;
+            num = nm;
+            den = d2;
+            act = f;
+            dact = dxf[f];
+          }
         }
       }
+      if (act >= 0) phi = num / den;
       const double phib = gbx * gx + gby * gy + gbz * gz;
       gbx *= phi; gby *= phi; gbz *= phi;
       if (act >= 0) {
         const double numb = phib / den;
         const double denb = -phib * phi / den;
-        gbx += denb * dxf[act].x; gby += denb * dxf[act].y; gbz += denb * dxf[act].z;
+        gbx += denb * dact.x; gby += denb * dact.y; gbz += denb * dact.z;
         const int ext = den > 0.0 ? amax[v] : amin[v];
         Pb[v] -= numb;
         if (ext < 0) {
@@ -186,12 +188,9 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
         }
       }
     }
-    // g = Minv sum_n dx_n (q_n - q_c): q_n gets dx_n . (Minv gb)
-    const double hx = i00 * gbx + i01 * gby + i02 * gbz;
-    const double hy = i01 * gbx + i11 * gby + i12 * gbz;
-    const double hz = i02 * gbx + i12 * gby + i22 * gbz;
+    // g = sum_n W_n (q_n - q_c): q_n gets W_n . gb, the cell minus their sum
     for (int lf = 0; lf < 6; ++lf) {
-      const double t = dx[lf].x * hx + dx[lf].y * hy + dx[lf].z * hz;
+      const double t = Lw.W[lf].x * gbx + Lw.W[lf].y * gby + Lw.W[lf].z * gbz;
       Pb[v] -= t;
       const bool ghost = (lf == 0 && k == 0) || (lf == 1 && k == d.g.Nr - 1);
       if (ghost) (lf == 0 ? PbGin : PbGout)[v] += t;
