@@ -97,9 +97,11 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
 }
 
 // Adjoint of rusanov(): given wb = adjoint of the face flux, accumulate the
-// adjoints of the left and right face states.
+// adjoints of the left and right face states; want_L / want_R select which
+// sides are needed (a side not wanted is skipped).
 __host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], const double qR[9], V3 S, const double wb[9],
-                                                double qLb[9], double qRb[9], const Params& pr) {
+                                                double qLb[9], double qRb[9], const Params& pr,
+                                                bool want_L = true, bool want_R = true) {
   const double area = norm3(S);
   const double ia = 1.0 / area;
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
@@ -122,8 +124,8 @@ __host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], con
   if (s1 >= pr.c_h) {
     if (lamL >= lamR) lamLb = sb; else lamRb = sb;
   }
-  flux_side_adjoint(qL, n, Fb, ULb, lamLb, qLb, pr.gamma, pr.c_h);
-  flux_side_adjoint(qR, n, Fb, URb, lamRb, qRb, pr.gamma, pr.c_h);
+  if (want_L) flux_side_adjoint(qL, n, Fb, ULb, lamLb, qLb, pr.gamma, pr.c_h);
+  if (want_R) flux_side_adjoint(qR, n, Fb, URb, lamRb, qRb, pr.gamma, pr.c_h);
 }
 
 // (dP/dU)^T Pb for P = prim(U): returns Ub.

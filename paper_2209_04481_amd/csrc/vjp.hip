@@ -26,97 +26,110 @@ static constexpr int kVBlock = 256;
 int64_t vjp_workspace_doubles(const Shape& g) { return int64_t(63) * g.ncells; }
 
 // Adjoint of the ghost law for the ghost of boundary cell (p,k,j,i) across
-// face lf: accumulates (dqG/dqI)^T qGb into qIb and returns (dqG/dbr)^T qGb.
-__host__ __device__ inline double ghost_adjoint(const DevGrid& d, int p, int k, int j, int i, int lf,
-                                                const double qI[9], V3 xI, double br, const double qGb[9],
-                                                double qIb[9]) {
+// face lf: accumulates (dqG/dqI)^T qGb into qIb and returns (dqG/dbr)^T qGb,
+// one forward-derivative pass of the ghost law per input.
+__host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p, int k, int j, int i, int lf,
+                                                         const double qI[9], V3 xI, double br, const double qGb[9],
+                                                         double qIb[9]) {
   double brb = 0.0;
   const int nin = lf == 0 ? 10 : 9;
+#pragma unroll 1
   for (int a = 0; a < nin; ++a) {
     Dual q[9], qG[9];
+#pragma unroll
     for (int v = 0; v < 9; ++v) q[v] = Dual(qI[v], v == a ? 1.0 : 0.0);
-    Dual b(br, a == 9 ? 1.0 : 0.0);
+    const Dual b(br, a == 9 ? 1.0 : 0.0);
     V3 xG;
     ghost_prims(d, p, k, j, i, lf, q, xI, b, qG, xG);
     double t = 0.0;
+#pragma unroll
     for (int v = 0; v < 9; ++v) t += qG[v].d * qGb[v];
-    if (a < 9) qIb[a] += t; else brb = t;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) qIb[v] += v == a ? t : 0.0;
+    brb = a == 9 ? t : brb;
   }
   return brb;
 }
 
+// Pass 2 for cell c.  No local array is indexed by a run-time value (such
+// arrays would live in scratch memory): face loops either unroll or branch on
+// the face id before touching per-face arrays.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, double* __restrict__ A,
                                              double* __restrict__ gbr, int64_t c) {
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
   decode(d.g, c, p, k, j, i);
+  const bool bin = k == 0, bout = k == d.g.Nr - 1;
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
-  double Pc[9], Gc[27], wc[9];
-  for (int v = 0; v < 9; ++v) Pc[v] = W[v * nc + c];
-  for (int v = 0; v < 27; ++v) Gc[v] = W[(9 + v) * nc + c];
-  for (int v = 0; v < 9; ++v) wc[v] = w[v * nc + c];
-  const int64_t col = (int64_t(p) * d.g.N + j) * d.g.N + i;
+  double Pc[9], wc[9];
+#pragma unroll
+  for (int v = 0; v < 9; ++v) {
+    Pc[v] = W[v * nc + c];
+    wc[v] = w[v * nc + c];
+  }
+  const int64_t col = column_of(d.g, p, j, i);
   const double brc = d.br[col];
 
-  // ---- recompute c's own stencil: offsets, weights, extremes, unlimited gradient
+  // ---- geometry, neighbour ids and ghost states
   V3 dx[6], dxf[6];
+  int64_t nid[6];
   double qGin[9], qGout[9];
+#pragma unroll
   for (int lf = 0; lf < 6; ++lf) {
-    Nbr nb = neighbour(d.g, p, k, j, i, lf);
+    const Nbr nb = neighbour(d.g, p, k, j, i, lf);
     V3 S, xf;
     bool own;
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
     dxf[lf] = xf - xc;
+    nid[lf] = nb.id;
     V3 xn;
-    if (nb.id >= nc) {
-      ghost_prims(d, p, k, j, i, lf, Pc, xc, lf == 0 ? brc : 0.0, lf == 0 ? qGin : qGout, xn);
-    } else {
+    if (nb.id >= nc)
+      xn = ghost_centre(xc, S, xf);
+    else
       xn = cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
-    }
     dx[lf] = xn - xc;
   }
+  if (bin) {
+    V3 xG;
+    ghost_prims(d, p, k, j, i, 0, Pc, xc, brc, qGin, xG);
+  }
+  if (bout) {
+    V3 xG;
+    ghost_prims(d, p, k, j, i, 1, Pc, xc, 0.0, qGout, xG);
+  }
   const LsqWeights Lw(dx);
-  double gxs[9], gys[9], gzs[9], qmax[9], qmin[9];
-  int amax[9], amin[9];
-  for (int v = 0; v < 9; ++v) {
-    gxs[v] = gys[v] = gzs[v] = 0.0;
-    qmax[v] = qmin[v] = Pc[v];
-    amax[v] = amin[v] = -1;
-  }
-  for (int lf = 0; lf < 6; ++lf) {
-    Nbr nb = neighbour(d.g, p, k, j, i, lf);
-    for (int v = 0; v < 9; ++v) {
-      const double qn = nb.id >= nc ? (lf == 0 ? qGin : qGout)[v] : W[v * nc + nb.id];
-      const double dq = qn - Pc[v];
-      gxs[v] += Lw.W[lf].x * dq; gys[v] += Lw.W[lf].y * dq; gzs[v] += Lw.W[lf].z * dq;
-      if (!(qmax[v] >= qn)) { qmax[v] = qn; amax[v] = lf; }
-      if (!(qmin[v] <= qn)) { qmin[v] = qn; amin[v] = lf; }
-    }
-  }
 
-  // ---- flux adjoints: own side (and ghost side) of each face
+  // ---- flux adjoints of the six faces: own side (and the ghost side)
   double Pb[9], Gb[27], PbGin[9], PbGout[9];
+#pragma unroll
   for (int v = 0; v < 9; ++v) Pb[v] = PbGin[v] = PbGout[v] = 0.0;
+#pragma unroll
   for (int v = 0; v < 27; ++v) Gb[v] = 0.0;
+#pragma unroll 1
   for (int lf = 0; lf < 6; ++lf) {
-    Nbr nb = neighbour(d.g, p, k, j, i, lf);
+    const Nbr nb = neighbour(d.g, p, k, j, i, lf);
     V3 S, xf;
     bool own;
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
-    double qs[9], qo[9], wb[9];
-    const V3 ds = dxf[lf];
-    for (int v = 0; v < 9; ++v) qs[v] = Pc[v] + (Gc[3 * v] * ds.x + Gc[3 * v + 1] * ds.y + Gc[3 * v + 2] * ds.z);
+    const V3 ds = xf - xc;
     const bool ghost = nb.id >= nc;
+    double qs[9], qo[9], wb[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+      qs[v] = Pc[v] + (W[(9 + 3 * v) * nc + c] * ds.x + W[(10 + 3 * v) * nc + c] * ds.y +
+                       W[(11 + 3 * v) * nc + c] * ds.z);
     if (ghost) {
+#pragma unroll
       for (int v = 0; v < 9; ++v) {
-        qo[v] = (lf == 0 ? qGin : qGout)[v];
+        qo[v] = lf == 0 ? qGin[v] : qGout[v];
         wb[v] = wc[v];  // the ghost carries no residual
       }
     } else {
+      const int64_t o = nb.id;
       const V3 dn = xf - cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
+#pragma unroll
       for (int v = 0; v < 9; ++v) {
-        const int64_t o = nb.id;
         qo[v] = W[v * nc + o] + (W[(9 + 3 * v) * nc + o] * dn.x + W[(10 + 3 * v) * nc + o] * dn.y +
                                  W[(11 + 3 * v) * nc + o] * dn.z);
         const double wn = w[v * nc + o];
@@ -124,41 +137,63 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       }
     }
     double qLb[9], qRb[9];
+#pragma unroll
     for (int v = 0; v < 9; ++v) qLb[v] = qRb[v] = 0.0;
+    // this cell's side, and the ghost side on a boundary face
     if (own)
-      rusanov_adjoint(qs, qo, S, wb, qLb, qRb, d.pr);
+      rusanov_adjoint(qs, qo, S, wb, qLb, qRb, d.pr, true, ghost);
     else
-      rusanov_adjoint(qo, qs, S, wb, qLb, qRb, d.pr);
-    const double* qsb = own ? qLb : qRb;
+      rusanov_adjoint(qo, qs, S, wb, qLb, qRb, d.pr, false, true);
+#pragma unroll
     for (int v = 0; v < 9; ++v) {
-      Pb[v] += qsb[v];
-      Gb[3 * v] += qsb[v] * ds.x;
-      Gb[3 * v + 1] += qsb[v] * ds.y;
-      Gb[3 * v + 2] += qsb[v] * ds.z;
-    }
-    if (ghost) {
-      double* pg = lf == 0 ? PbGin : PbGout;
-      for (int v = 0; v < 9; ++v) pg[v] += qRb[v];
+      const double qsb = own ? qLb[v] : qRb[v];
+      Pb[v] += qsb;
+      Gb[3 * v] += qsb * ds.x;
+      Gb[3 * v + 1] += qsb * ds.y;
+      Gb[3 * v + 2] += qsb * ds.z;
+      if (ghost) {
+        if (lf == 0) PbGin[v] += qRb[v];
+        else PbGout[v] += qRb[v];
+      }
     }
   }
 
-  // ---- limiter and gradient adjoint, per variable
-  double out[6][9];
-  for (int lf = 0; lf < 6; ++lf)
-    for (int v = 0; v < 9; ++v) out[lf][v] = 0.0;
+  // ---- per variable: recompute the gradient and limiter choice, then their
+  // adjoint; contributions to the six neighbours are stored at once
+#pragma unroll
   for (int v = 0; v < 9; ++v) {
-    const double gx = gxs[v], gy = gys[v], gz = gzs[v];
+    double qn[6];
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) {
+      if (lf == 0 && bin) qn[lf] = qGin[v];
+      else if (lf == 1 && bout) qn[lf] = qGout[v];
+      else qn[lf] = W[v * nc + nid[lf]];
+    }
+    const double qc = Pc[v];
+    double gx = 0.0, gy = 0.0, gz = 0.0, qmax = qc, qmin = qc;
+    int amax = -1, amin = -1;
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) {
+      const double dq = qn[lf] - qc;
+      gx += Lw.W[lf].x * dq; gy += Lw.W[lf].y * dq; gz += Lw.W[lf].z * dq;
+      if (!(qmax >= qn[lf])) { qmax = qn[lf]; amax = lf; }
+      if (!(qmin <= qn[lf])) { qmin = qn[lf]; amin = lf; }
+    }
     double gbx = Gb[3 * v], gby = Gb[3 * v + 1], gbz = Gb[3 * v + 2];
+    double o[6];
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) o[lf] = 0.0;
+    double pb = Pb[v];
     if (d.pr.limiter) {
       // the same choice as the forward limiter (limited_grad)
-      double phi = 1.0, num = 0.0, den = 1.0, bn = 1.0, bd = 1.0;
+      double bn = 1.0, bd = 1.0, num = 0.0, den = 1.0;
       int act = -1;
       V3 dact = mk(0.0, 0.0, 0.0);
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         const double d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
         if (d2 != 0.0) {
-          const double nm = d2 > 0.0 ? qmax[v] - Pc[v] : qmin[v] - Pc[v];
+          const double nm = d2 > 0.0 ? qmax - qc : qmin - qc;
           const double an = ::fabs(nm), ad = ::fabs(d2);
           if (an * bd < bn * ad) {
             bn = an;
@@ -170,44 +205,50 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
           }
         }
       }
-      if (act >= 0) phi = num / den;
+      const double phi = act >= 0 ? num / den : 1.0;
       const double phib = gbx * gx + gby * gy + gbz * gz;
       gbx *= phi; gby *= phi; gbz *= phi;
       if (act >= 0) {
         const double numb = phib / den;
         const double denb = -phib * phi / den;
         gbx += denb * dact.x; gby += denb * dact.y; gbz += denb * dact.z;
-        const int ext = den > 0.0 ? amax[v] : amin[v];
-        Pb[v] -= numb;
-        if (ext < 0) {
-          Pb[v] += numb;
-        } else {
-          Nbr nb = neighbour(d.g, p, k, j, i, ext);
-          if (nb.id >= nc) (ext == 0 ? PbGin : PbGout)[v] += numb;
-          else out[ext][v] += numb;
-        }
+        const int ext = den > 0.0 ? amax : amin;
+        pb -= numb;
+        if (ext < 0) pb += numb;
+#pragma unroll
+        for (int lf = 0; lf < 6; ++lf)
+          if (ext == lf) o[lf] += numb;
       }
     }
     // g = sum_n W_n (q_n - q_c): q_n gets W_n . gb, the cell minus their sum
+#pragma unroll
     for (int lf = 0; lf < 6; ++lf) {
       const double t = Lw.W[lf].x * gbx + Lw.W[lf].y * gby + Lw.W[lf].z * gbz;
-      Pb[v] -= t;
-      const bool ghost = (lf == 0 && k == 0) || (lf == 1 && k == d.g.Nr - 1);
-      if (ghost) (lf == 0 ? PbGin : PbGout)[v] += t;
-      else out[lf][v] += t;
+      pb -= t;
+      o[lf] += t;
     }
+    Pb[v] = pb;
+    // ghost positions fold back below; cell positions go to the gather pass
+#pragma unroll
+    for (int v2 = 0; v2 < 9; ++v2) {
+      if (v2 != v) continue;
+      if (bin) PbGin[v2] += o[0];
+      if (bout) PbGout[v2] += o[1];
+    }
+    A[(9 + v) * nc + c] = bin ? 0.0 : o[0];
+    A[(18 + v) * nc + c] = bout ? 0.0 : o[1];
+#pragma unroll
+    for (int lf = 2; lf < 6; ++lf) A[(9 + 9 * lf + v) * nc + c] = o[lf];
   }
 
   // ---- ghost laws back onto the cell and the B_r map
-  if (k == 0) {
+  if (bin) {
     const double brb = ghost_adjoint(d, p, k, j, i, 0, Pc, xc, brc, PbGin, Pb);
     if (gbr) gbr[col] = brb;
   }
-  if (k == d.g.Nr - 1) (void)ghost_adjoint(d, p, k, j, i, 1, Pc, xc, 0.0, PbGout, Pb);
-
+  if (bout) (void)ghost_adjoint(d, p, k, j, i, 1, Pc, xc, 0.0, PbGout, Pb);
+#pragma unroll
   for (int v = 0; v < 9; ++v) A[v * nc + c] = Pb[v];
-  for (int lf = 0; lf < 6; ++lf)
-    for (int v = 0; v < 9; ++v) A[(9 + 9 * lf + v) * nc + c] = out[lf][v];
 }
 
 __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __restrict__ U,
