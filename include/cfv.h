@@ -122,6 +122,52 @@ cfv_status cfv_dots(cfv_ctx* ctx, const double* V, int32_t k, const double* w, d
 /* y = a*x + b*y over n values (a, b scalars from the host). */
 cfv_status cfv_axpby(cfv_ctx* ctx, int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 
+/* ---------------------------------------------------- implicit solver --
+ * Solve (diag + J) x = rhs (transpose = 0) or (diag + J^T) x = rhs
+ * (transpose = 1), J = dR/dU at U applied matrix-free through the JVP or the
+ * VJP, diag[ncells] a per-cell diagonal applied to all 9 variables: GMRES(m)
+ * from x = 0 with modified Gram-Schmidt, restarted up to max_restarts times,
+ * stopping when |rhs - A x| <= rtol |rhs| (rtol = 0 runs all iterations).
+ * hist (host, nullable, hist_len entries) receives |r_j|/|rhs| after every
+ * iteration; iters and final_rel (host, nullable) the iteration count and
+ * the last relative residual.  x must not alias rhs.  The Arnoldi vectors,
+ * dot products and updates stay on the device; the stream is synchronised
+ * once per iteration to bring the Hessenberg column to the host, where the
+ * Givens least squares is solved.  The Krylov workspace ((m+1) state
+ * vectors) is owned by the context and grown on first use.
+ * This is the linear solve of the implicit backward-Euler pseudo-time step
+ * of Section 2.1. */
+cfv_status cfv_solve(cfv_ctx* ctx, const double* U, const double* diag, const double* rhs, int32_t transpose,
+                     int32_t m, int32_t max_restarts, double rtol, double* x, double* hist, int32_t hist_len,
+                     int32_t* iters, double* final_rel, hipStream_t s);
+/* One backward-Euler pseudo-time step: U_new = U + x with (V/dt + J) x = -R(U),
+ * V/dt from cfv_local_dt at the given cfl, solved by cfv_solve.  U_new must
+ * not alias U. */
+cfv_status cfv_be_step(cfv_ctx* ctx, const double* U, double cfl, int32_t m, int32_t max_restarts, double rtol,
+                       double* U_new, double* hist, int32_t hist_len, int32_t* iters, double* final_rel,
+                       hipStream_t s);
+
+/* ------------------------------------------------- second derivatives --
+ * Directional derivatives of the linearisations, for the second-order terms
+ * of the adjoint of the implicit step map (the Newton linearisation of
+ * Section 2.1 differentiated once more).  Both take a central difference of
+ * two exact first-derivative evaluations at +-h along the direction, with
+ * one scalar h = eps / max_e |d_e| / (|u_e| + 1e-3 max|u_var(e)|): every
+ * entry moves by at most eps relative to its own size (or to a thousandth of
+ * its variable's largest magnitude).  This is the one approximate piece of
+ * the sensitivity; h_used (host, nullable) returns h.  Both synchronise the
+ * stream twice (the step is chosen on the host) and use a context-owned
+ * workspace of two state vectors, allocated on first use.
+ *
+ * gU2 = d/de [J_U(U + e x)^T w] and, when gbr2 is not NULL,
+ * gbr2 = d/de [J_b(U + e x)^T w] (6N^2 values), at e = 0. */
+cfv_status cfv_vjp_dir(cfv_ctx* ctx, const double* U, const double* w, const double* x, double eps, double* gU2,
+                       double* gbr2, double* h_used, hipStream_t s);
+/* Jv2 = d/de [J_U(U + e dU, b + e dbr) v] at e = 0 (dbr may be NULL: the map
+ * held by the context is not moved). */
+cfv_status cfv_jvp_dir(cfv_ctx* ctx, const double* U, const double* v, const double* dU, const double* dbr, double eps,
+                       double* Jv2, double* h_used, hipStream_t s);
+
 /* ------------------------------------------------------------ profiling --
  * While enabled, every kernel launch of the context is bracketed by a pair of
  * HIP events on its launch stream.  cfv_timing_read synchronises on the

@@ -58,6 +58,10 @@ def lib():
         "cfv_norms": ([P, P, P, P, P], c_int32),
         "cfv_dots": ([P, P, c_int32, P, P, P], c_int32),
         "cfv_axpby": ([P, c_int64, c_double, P, c_double, P, P], c_int32),
+        "cfv_solve": ([P, P, P, P, c_int32, c_int32, c_int32, c_double, P, P, c_int32, P, P, P], c_int32),
+        "cfv_be_step": ([P, P, c_double, c_int32, c_int32, c_double, P, P, c_int32, P, P, P], c_int32),
+        "cfv_vjp_dir": ([P, P, P, P, c_double, P, P, P, P], c_int32),
+        "cfv_jvp_dir": ([P, P, P, P, P, c_double, P, P, P], c_int32),
         "cfv_timing_enable": ([P, c_int32], c_int32),
         "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
@@ -184,6 +188,24 @@ class Context:
                             _ptr(gbr), _stream(stream)))
         return gU, gbr
 
+    def vjp_dir(self, U, w, x, eps=1e-6, out=None, gbr=None, want_br=True, stream=None):
+        """d/de of the VJP at U + e x (central difference); returns (gU2, gbr2, h)."""
+        gU = out if out is not None else self._new(9, self.grid.ncells)
+        if gbr is None and want_br:
+            gbr = self._new(self.grid.nb)
+        h = c_double()
+        check(lib().cfv_vjp_dir(self._h, self._state(U, "U"), self._state(w, "w"), self._state(x, "x"), float(eps),
+                                self._state(gU, "gU2"), _ptr(gbr), ctypes.byref(h), _stream(stream)))
+        return gU, gbr, h.value
+
+    def jvp_dir(self, U, v, dU, dbr=None, eps=1e-6, out=None, stream=None):
+        """d/de of the JVP J(U + e dU, b + e dbr) v (central difference); returns (Jv2, h)."""
+        Jv = out if out is not None else self._new(9, self.grid.ncells)
+        h = c_double()
+        check(lib().cfv_jvp_dir(self._h, self._state(U, "U"), self._state(v, "v"), self._state(dU, "dU"), _ptr(dbr),
+                                float(eps), self._state(Jv, "Jv2"), ctypes.byref(h), _stream(stream)))
+        return Jv, h.value
+
     def local_dt(self, U, cfl, out=None, stream=None):
         d = out if out is not None else self._new(self.grid.ncells)
         check(lib().cfv_local_dt(self._h, self._state(U, "U"), float(cfl), _ptr(d), _stream(stream)))
@@ -200,6 +222,30 @@ class Context:
         o = out if out is not None else self._new(k)
         check(lib().cfv_dots(self._h, _ptr(V), int(k), _ptr(w), _ptr(o), _stream(stream)))
         return o
+
+    def solve(self, U, diag, rhs, transpose=False, m=30, max_restarts=0, rtol=0.0, out=None, stream=None):
+        """GMRES on (diag + J) x = rhs or its transpose; returns (x, history)."""
+        x = out if out is not None else self._new(9, self.grid.ncells)
+        hl = m * (max_restarts + 1)
+        hist = np.zeros(hl)
+        it = c_int32()
+        fr = c_double()
+        check(lib().cfv_solve(self._h, self._state(U, "U"), _ptr(diag), self._state(rhs, "rhs"), int(bool(transpose)),
+                              int(m), int(max_restarts), float(rtol), self._state(x, "x"),
+                              hist.ctypes.data_as(c_void_p), hl, ctypes.byref(it), ctypes.byref(fr), _stream(stream)))
+        return x, hist[:it.value]
+
+    def be_step(self, U, cfl=1e3, m=30, max_restarts=0, rtol=0.0, out=None, stream=None):
+        """One backward-Euler step; returns (U_new, history)."""
+        Un = out if out is not None else self._new(9, self.grid.ncells)
+        hl = m * (max_restarts + 1)
+        hist = np.zeros(hl)
+        it = c_int32()
+        fr = c_double()
+        check(lib().cfv_be_step(self._h, self._state(U, "U"), float(cfl), int(m), int(max_restarts), float(rtol),
+                                self._state(Un, "U_new"), hist.ctypes.data_as(c_void_p), hl, ctypes.byref(it),
+                                ctypes.byref(fr), _stream(stream)))
+        return Un, hist[:it.value]
 
     def timing_enable(self, on=True):
         check(lib().cfv_timing_enable(self._h, int(bool(on))))

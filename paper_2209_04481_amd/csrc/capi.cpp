@@ -23,6 +23,14 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* 
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
                       double* A, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
+hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y, hipStream_t s);
+hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
+hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s);
+hipError_t launch_lincomb(int64_t n, int k, const double* y, const double* V, double* x, hipStream_t s);
+hipError_t launch_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s);
+hipError_t launch_absmax(int64_t n, int nvar, const double* a, double* out, double* part, hipStream_t s);
+hipError_t launch_ratio_max(int64_t n, int nvar, const double* x, const double* u, const double* sv, double* out,
+                            double* part, hipStream_t s);
 }  // namespace cfv
 
 struct cfv_grid {
@@ -96,6 +104,19 @@ struct cfv_ctx {
   double* A = nullptr;     // adjoint workspace
   double* part = nullptr;  // reduction partials
   int part_vectors = 0;
+  // Krylov workspace (allocated on first use, grown as needed)
+  int kry_m = 0;
+  double* kry_V = nullptr;    // (m + 1) vectors of 9 ncells
+  double* kry_w = nullptr;    // 9 ncells
+  double* kry_r = nullptr;    // 9 ncells: residual / rhs scratch
+  double* kry_d = nullptr;    // ncells: diagonal scratch
+  double* kry_x = nullptr;    // 9 ncells: solution of the implicit step
+  double* kry_s = nullptr;    // device scalars: H column (m + 2) and y (m)
+  // second-derivative workspace (allocated on first use)
+  double* dir_u = nullptr;    // 9 ncells: shifted state
+  double* dir_g = nullptr;    // 9 ncells: second evaluation
+  double* dir_b = nullptr;    // 3 x 6N^2: shifted maps and the second B_r gradient
+  double* dir_s = nullptr;    // 32 device scalars
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -330,6 +351,10 @@ void cfv_ctx_destroy(cfv_ctx* c) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->dcn) (void)hipFree(c->dcn);
+  double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
+                  c->dir_u, c->dir_g, c->dir_b, c->dir_s};
+  for (double* b : kb)
+    if (b) (void)hipFree(b);
   delete c;
 }
 
@@ -399,6 +424,261 @@ cfv_status cfv_axpby(cfv_ctx* c, int64_t n, double a, const double* x, double b,
   if (cfv_status st = check_ctx(c)) return st;
   if (!x || !y || n < 0) return fail(CFV_ERR_ARG, "bad vector arguments");
   CFV_HIP(cfv::launch_axpby(n, a, x, b, y, s));
+  return CFV_OK;
+}
+
+// ------------------------------------------------------------------ solver
+static cfv_status ensure_krylov(cfv_ctx* c, int m) {
+  if (c->kry_m >= m) return CFV_OK;
+  double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x};
+  for (double* b : kb)
+    if (b) (void)hipFree(b);
+  c->kry_V = c->kry_w = c->kry_r = c->kry_d = c->kry_s = c->kry_x = nullptr;
+  c->kry_m = 0;
+  const size_t n = size_t(9) * c->grid->g.ncells;
+  cfv_status st;
+  if ((st = dmalloc(&c->kry_V, size_t(m + 1) * n)) || (st = dmalloc(&c->kry_w, n)) || (st = dmalloc(&c->kry_r, n)) ||
+      (st = dmalloc(&c->kry_d, size_t(c->grid->g.ncells))) || (st = dmalloc(&c->kry_s, size_t(2 * m + 4))) ||
+      (st = dmalloc(&c->kry_x, n)))
+    return st;
+  c->kry_m = m;
+  return CFV_OK;
+}
+
+// w = (diag + J) x  or  (diag + J^T) x
+static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag, int transpose, const double* x,
+                                 double* w, hipStream_t s) {
+  if (transpose) {
+    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, s, c->tm()));
+  } else {
+    cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
+    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+  }
+  CFV_HIP(cfv::launch_add_diag(c->grid->g.ncells, diag, x, w, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const double* rhs, int32_t transpose,
+                     int32_t m, int32_t max_restarts, double rtol, double* x, double* hist, int32_t hist_len,
+                     int32_t* iters, double* final_rel, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !diag || !rhs || !x) return fail(CFV_ERR_ARG, "null argument");
+  if (m < 1 || m > 200 || max_restarts < 0) return fail(CFV_ERR_ARG, "need 1 <= m <= 200 and max_restarts >= 0");
+  if (cfv_status st = ensure_krylov(c, m)) return st;
+  const int64_t n = 9 * c->grid->g.ncells;
+  double* V = c->kry_V;
+  double* w = c->kry_w;
+  double* r = c->kry_r;
+  double* hd = c->kry_s;           // H column on the device (m + 2)
+  double* yd = c->kry_s + m + 2;   // least-squares solution (m)
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), col(m + 2), y(m);
+  auto Hc = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
+  CFV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+  // |rhs| for the relative residual
+  double bnorm = 0.0;
+  CFV_HIP(cfv::launch_norm2(n, rhs, hd, c->part, s));
+  CFV_HIP(hipMemcpyAsync(&bnorm, hd, sizeof(double), hipMemcpyDeviceToHost, s));
+  CFV_HIP(hipStreamSynchronize(s));
+  int total = 0;
+  double rel = bnorm > 0.0 ? 1.0 : 0.0;
+  if (bnorm == 0.0) {
+    if (iters) *iters = 0;
+    if (final_rel) *final_rel = 0.0;
+    return CFV_OK;
+  }
+  for (int cycle = 0; cycle <= max_restarts; ++cycle) {
+    // r = rhs - A x
+    if (cycle == 0) {
+      CFV_HIP(hipMemcpyAsync(r, rhs, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      if (cfv_status st = apply_operator(c, U, diag, transpose, x, w, s)) return st;
+      CFV_HIP(cfv::launch_axpby(n, 1.0, rhs, 0.0, r, s));
+      CFV_HIP(cfv::launch_axpby(n, -1.0, w, 1.0, r, s));
+    }
+    double beta = 0.0;
+    CFV_HIP(cfv::launch_norm2(n, r, hd, c->part, s));
+    CFV_HIP(hipMemcpyAsync(&beta, hd, sizeof(double), hipMemcpyDeviceToHost, s));
+    CFV_HIP(cfv::launch_div_dev(n, hd, r, V, s));
+    CFV_HIP(hipStreamSynchronize(s));
+    if (!(beta > 0.0)) break;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kdone = 0;
+    bool stop = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + size_t(j) * n;
+      if (cfv_status st = apply_operator(c, U, diag, transpose, vj, w, s)) return st;
+      // modified Gram-Schmidt: coefficients stay on the device
+      for (int i = 0; i <= j; ++i) {
+        CFV_HIP(cfv::launch_dots(n, V + size_t(i) * n, 1, w, hd + i, c->part, s));
+        CFV_HIP(cfv::launch_axpy_dev(n, hd + i, -1.0, V + size_t(i) * n, w, s));
+      }
+      CFV_HIP(cfv::launch_norm2(n, w, hd + j + 1, c->part, s));
+      CFV_HIP(hipMemcpyAsync(col.data(), hd, size_t(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      CFV_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i <= j + 1; ++i) Hc(i, j) = col[i];
+      const double hnext = col[j + 1];
+      if (hnext > 0.0) CFV_HIP(cfv::launch_div_dev(n, hd + j + 1, w, V + size_t(j + 1) * n, s));
+      // Givens rotations on the new column
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+        Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+        Hc(i, j) = t;
+      }
+      const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+      cs[j] = Hc(j, j) / den;
+      sn[j] = Hc(j + 1, j) / den;
+      Hc(j, j) = den;
+      Hc(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      rel = std::fabs(g[j + 1]) / bnorm;
+      if (hist && total < hist_len) hist[total] = rel;
+      ++total;
+      kdone = j + 1;
+      if (rel <= rtol || !(hnext > 0.0)) {
+        stop = true;
+        break;
+      }
+    }
+    // back substitution and x += V y
+    for (int i = kdone - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < kdone; ++q) t -= Hc(i, q) * y[q];
+      y[i] = t / Hc(i, i);
+    }
+    CFV_HIP(hipMemcpyAsync(yd, y.data(), size_t(kdone) * sizeof(double), hipMemcpyHostToDevice, s));
+    CFV_HIP(cfv::launch_lincomb(n, kdone, yd, V, w, s));
+    CFV_HIP(cfv::launch_axpby(n, 1.0, w, 1.0, x, s));
+    CFV_HIP(hipStreamSynchronize(s));
+    if (stop) break;
+  }
+  if (iters) *iters = total;
+  if (final_rel) *final_rel = rel;
+  return CFV_OK;
+}
+
+cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32_t max_restarts, double rtol,
+                       double* U_new, double* hist, int32_t hist_len, int32_t* iters, double* final_rel,
+                       hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !U_new || U_new == U) return fail(CFV_ERR_ARG, "null state, or U_new aliases U");
+  if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
+  if (m < 1 || m > 200) return fail(CFV_ERR_ARG, "need 1 <= m <= 200");
+  if (cfv_status st = ensure_krylov(c, m)) return st;
+  const int64_t n = 9 * c->grid->g.ncells;
+  // U_new holds the right-hand side -R(U) during the solve
+  cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
+  CFV_HIP(cfv::launch_march(a, false, s, c->tm()));
+  CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
+  CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
+  if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
+                                final_rel, s))
+    return st;
+  CFV_HIP(hipMemcpyAsync(U_new, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CFV_HIP(cfv::launch_axpby(n, 1.0, c->kry_x, 1.0, U_new, s));
+  return CFV_OK;
+}
+
+// ------------------------------------------------- second derivatives
+static cfv_status ensure_dir(cfv_ctx* c) {
+  if (c->dir_u) return CFV_OK;
+  const size_t n = size_t(9) * c->grid->g.ncells;
+  cfv_status st;
+  if ((st = dmalloc(&c->dir_u, n)) || (st = dmalloc(&c->dir_g, n)) ||
+      (st = dmalloc(&c->dir_b, size_t(3) * c->grid->g.nb)) || (st = dmalloc(&c->dir_s, 32))) {
+    double* kb[] = {c->dir_u, c->dir_g, c->dir_b, c->dir_s};
+    for (double* b : kb)
+      if (b) (void)hipFree(b);
+    c->dir_u = c->dir_g = c->dir_b = c->dir_s = nullptr;
+    return st;
+  }
+  return CFV_OK;
+}
+
+// max over entries of |x| / (|u| + 1e-3 max|u_v|) for nvar vectors of length
+// n (vectors with u identically zero are left out); synchronises the stream.
+static cfv_status step_ratio(cfv_ctx* c, int64_t n, int nvar, const double* x, const double* u, double* ratio,
+                             hipStream_t s) {
+  double* amax = c->dir_s;       // nvar <= 9
+  double* sv = c->dir_s + 12;    // floors
+  double* out = c->dir_s + 24;
+  CFV_HIP(cfv::launch_absmax(n, nvar, u, amax, c->part, s));
+  double h[9];
+  CFV_HIP(hipMemcpyAsync(h, amax, size_t(nvar) * sizeof(double), hipMemcpyDeviceToHost, s));
+  CFV_HIP(hipStreamSynchronize(s));
+  for (int v = 0; v < nvar; ++v) h[v] = h[v] > 0.0 ? 1e-3 * h[v] : 0.0;
+  CFV_HIP(hipMemcpyAsync(sv, h, size_t(nvar) * sizeof(double), hipMemcpyHostToDevice, s));
+  CFV_HIP(cfv::launch_ratio_max(n, nvar, x, u, sv, out, c->part, s));
+  CFV_HIP(hipMemcpyAsync(ratio, out, sizeof(double), hipMemcpyDeviceToHost, s));
+  CFV_HIP(hipStreamSynchronize(s));
+  return CFV_OK;
+}
+
+cfv_status cfv_vjp_dir(cfv_ctx* c, const double* U, const double* w, const double* x, double eps, double* gU2,
+                       double* gbr2, double* h_used, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !w || !x || !gU2) return fail(CFV_ERR_ARG, "null state, weights, direction or output");
+  if (!(eps > 0.0) || !(eps < 1.0)) return fail(CFV_ERR_ARG, "eps must lie in (0, 1)");
+  if (cfv_status st = ensure_dir(c)) return st;
+  const int64_t nc = c->grid->g.ncells, n = 9 * nc, nb = c->grid->g.nb;
+  double ratio = 0.0;
+  if (cfv_status st = step_ratio(c, nc, 9, x, U, &ratio, s)) return st;
+  const double h = ratio > 0.0 ? eps / ratio : eps;
+  if (h_used) *h_used = h;
+  double* gbm = c->dir_b;
+  // + side into the outputs, - side into the workspace
+  CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CFV_HIP(cfv::launch_axpby(n, h, x, 1.0, c->dir_u, s));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, s, c->tm()));
+  CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CFV_HIP(cfv::launch_axpby(n, -h, x, 1.0, c->dir_u, s));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, s, c->tm()));
+  const double ih = 0.5 / h;
+  CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, gU2, s));
+  if (gbr2) CFV_HIP(cfv::launch_axpby(nb, -ih, gbm, ih, gbr2, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_jvp_dir(cfv_ctx* c, const double* U, const double* v, const double* dU, const double* dbr, double eps,
+                       double* Jv2, double* h_used, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !v || !dU || !Jv2) return fail(CFV_ERR_ARG, "null state, vectors or output");
+  if (!(eps > 0.0) || !(eps < 1.0)) return fail(CFV_ERR_ARG, "eps must lie in (0, 1)");
+  if (cfv_status st = ensure_dir(c)) return st;
+  const int64_t nc = c->grid->g.ncells, n = 9 * nc, nb = c->grid->g.nb;
+  double ratio = 0.0, rb = 0.0;
+  if (cfv_status st = step_ratio(c, nc, 9, dU, U, &ratio, s)) return st;
+  if (dbr)
+    if (cfv_status st = step_ratio(c, nb, 1, dbr, c->dbr, &rb, s)) return st;
+  const double rmax = ratio > rb ? ratio : rb;
+  const double h = rmax > 0.0 ? eps / rmax : eps;
+  if (h_used) *h_used = h;
+  double* brp = c->dir_b;
+  double* brm = c->dir_b + nb;
+  cfv::DevGrid dp = c->dev(), dm = c->dev();
+  if (dbr) {
+    CFV_HIP(hipMemcpyAsync(brp, c->dbr, size_t(nb) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CFV_HIP(cfv::launch_axpby(nb, h, dbr, 1.0, brp, s));
+    CFV_HIP(hipMemcpyAsync(brm, c->dbr, size_t(nb) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CFV_HIP(cfv::launch_axpby(nb, -h, dbr, 1.0, brm, s));
+    dp.br = brp;
+    dm.br = brm;
+  }
+  CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CFV_HIP(cfv::launch_axpby(n, h, dU, 1.0, c->dir_u, s));
+  {
+    cfv::MarchArgs a{dp, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, Jv2};
+    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+  }
+  CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CFV_HIP(cfv::launch_axpby(n, -h, dU, 1.0, c->dir_u, s));
+  {
+    cfv::MarchArgs a{dm, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, c->dir_g};
+    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+  }
+  const double ih = 0.5 / h;
+  CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, Jv2, s));
   return CFV_OK;
 }
 

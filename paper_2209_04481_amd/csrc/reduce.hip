@@ -27,6 +27,61 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
   return r;  // valid in thread 0
 }
 
+template <int B>
+__device__ __forceinline__ double block_max(double x, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) x = ::fmax(x, __shfl_down(x, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < B / 64; ++w) r = ::fmax(r, sh[w]);
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+// partial[v*kRGrid + block] = max over the block's entries of |a_v| (nvar vectors of length n)
+__global__ __launch_bounds__(kRBlock) void absmax_partials(int64_t n, int nvar, const double* __restrict__ a,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[kRBlock / 64];
+  for (int v = 0; v < nvar; ++v) {
+    double m = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock)
+      m = ::fmax(m, ::fabs(a[v * n + c]));
+    double t = block_max<kRBlock>(m, sh);
+    if (threadIdx.x == 0) part[v * kRGrid + blockIdx.x] = t;
+  }
+}
+
+// partial[block] = max over entries of |x| / (|u| + s_v) over nvar vectors of
+// length n, with a per-vector floor s_v (device array); s_v <= 0 drops vector v.
+__global__ __launch_bounds__(kRBlock) void ratio_partials(int64_t n, int nvar, const double* __restrict__ x,
+                                                         const double* __restrict__ u, const double* __restrict__ sv,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[kRBlock / 64];
+  double m = 0.0;
+  for (int v = 0; v < nvar; ++v) {
+    const double s = sv[v];
+    if (!(s > 0.0)) continue;
+    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock)
+      m = ::fmax(m, ::fabs(x[v * n + c]) / (::fabs(u[v * n + c]) + s));
+  }
+  double t = block_max<kRBlock>(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[v] = max of the partials of vector v (one block per v)
+__global__ __launch_bounds__(kRBlock) void fold_max(const double* __restrict__ part, int nvec,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[kRBlock / 64];
+  const int v = blockIdx.x;
+  if (v >= nvec) return;
+  double m = 0.0;
+  for (int b = threadIdx.x; b < kRGrid; b += kRBlock) m = ::fmax(m, part[v * kRGrid + b]);
+  double t = block_max<kRBlock>(m, sh);
+  if (threadIdx.x == 0) out[v] = t;
+}
+
 // partial[v*kRGrid + block] = sum over the block's cells of (a - b)^2 for variable v
 __global__ __launch_bounds__(kRBlock) void sq_partials(int64_t nc, const double* __restrict__ a,
                                                       const double* __restrict__ b, double* __restrict__ part) {
@@ -74,7 +129,81 @@ __global__ __launch_bounds__(kRBlock) void axpby_kernel(int64_t n, double a, con
     y[c] = a * x[c] + b * y[c];
 }
 
+// y += sign * (*coef) * x   (coefficient read from device memory)
+__global__ __launch_bounds__(kRBlock) void axpy_dev_kernel(int64_t n, const double* __restrict__ coef, double sign,
+                                                           const double* __restrict__ x, double* __restrict__ y) {
+  const double a = sign * coef[0];
+  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kRBlock)
+    y[c] += a * x[c];
+}
+
+// y = x / (*den)
+__global__ __launch_bounds__(kRBlock) void div_dev_kernel(int64_t n, const double* __restrict__ den,
+                                                          const double* __restrict__ x, double* __restrict__ y) {
+  const double d = den[0];
+  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kRBlock)
+    y[c] = x[c] / d;
+}
+
+// w[v*nc + c] += diag[c] * x[v*nc + c]
+__global__ __launch_bounds__(kRBlock) void add_diag_kernel(int64_t nc, const double* __restrict__ diag,
+                                                           const double* __restrict__ x, double* __restrict__ w) {
+  const int64_t n = 9 * nc;
+  for (int64_t e = int64_t(blockIdx.x) * kRBlock + threadIdx.x; e < n; e += int64_t(gridDim.x) * kRBlock)
+    w[e] += diag[e % nc] * x[e];
+}
+
+// x = sum_i y[i] V_i over k vectors of length n (coefficients on the device)
+__global__ __launch_bounds__(kRBlock) void lincomb_kernel(int64_t n, int k, const double* __restrict__ y,
+                                                          const double* __restrict__ V, double* __restrict__ x) {
+  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kRBlock) {
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += y[i] * V[int64_t(i) * n + c];
+    x[c] = s;
+  }
+}
+
+static unsigned stream_blocks(int64_t n) {
+  int64_t b = (n + kRBlock - 1) / kRBlock;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return unsigned(b);
+}
+
+hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_dev_kernel, dim3(stream_blocks(n)), dim3(kRBlock), 0, s, n, coef, sign, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(div_dev_kernel, dim3(stream_blocks(n)), dim3(kRBlock), 0, s, n, den, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(add_diag_kernel, dim3(stream_blocks(9 * nc)), dim3(kRBlock), 0, s, nc, diag, x, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(int64_t n, int k, const double* y, const double* V, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(stream_blocks(n)), dim3(kRBlock), 0, s, n, k, y, V, x);
+  return hipGetLastError();
+}
+
 int reduce_partials_per_vector() { return kRGrid; }
+
+hipError_t launch_absmax(int64_t n, int nvar, const double* a, double* out, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(absmax_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, nvar, a, part);
+  hipLaunchKernelGGL(fold_max, dim3(nvar), dim3(kRBlock), 0, s, part, nvar, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ratio_max(int64_t n, int nvar, const double* x, const double* u, const double* sv, double* out,
+                            double* part, hipStream_t s) {
+  hipLaunchKernelGGL(ratio_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, nvar, x, u, sv, part);
+  hipLaunchKernelGGL(fold_max, dim3(1), dim3(kRBlock), 0, s, part, 1, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s) {
   hipLaunchKernelGGL(sq_partials, dim3(kRGrid), dim3(kRBlock), 0, s, nc, a, b, part);
@@ -85,6 +214,12 @@ hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* ou
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s) {
   hipLaunchKernelGGL(dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, V, k, w, part);
   hipLaunchKernelGGL(fold_partials, dim3(k), dim3(kRBlock), 0, s, part, k, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, x, 1, x, part);
+  hipLaunchKernelGGL(fold_partials, dim3(1), dim3(kRBlock), 0, s, part, 1, out, 1);
   return hipGetLastError();
 }
 
