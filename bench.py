@@ -4,7 +4,11 @@ One step = one pass of the hot path over the large workload (6 x 96 x 96 x
 240 = 13,271,040 cells, FP64): ghost fill + residual, JVP (with a B_r-map
 direction), VJP (state and B_r-map gradients) and the Eq. 2 residual norms.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-ensemble]
+
+The line also carries the ensemble figure: 64 uneven instances (29.95M
+cells), residual + JVP of all of them as one captured graph of persistent
+launches against 64 single-instance launches in sequence.
 
 Prints ONE JSON line.  `value` is the throughput of whole steps in Mcell/s
 (cells x steps / wall time of the timed region, inputs resident in HBM).
@@ -66,6 +70,65 @@ def cpu_baseline(inst, ncells_sample: int):
                       f"{dt:.1f} s"}
 
 
+def bench_ensemble(reps: int):
+    """64 uneven instances (29.95M cells): residual + JVP of all of them as one
+    captured graph of two persistent launches, against 64 single-instance
+    launches in sequence on the same stream (not captured)."""
+    import torch
+
+    import coronal_inputs as ci
+    from paper_2209_04481_amd import Context, Ensemble, Grid, Params
+    from paper_2209_04481_amd.autotune import autotune
+
+    t0 = time.time()
+    insts = ci.ensemble_instances()
+    ctxs, U, v = [], [], []
+    for q, inst in enumerate(insts):
+        c = Context(Grid(inst.N, inst.Nr, inst.r_nodes), Params())
+        c.set_inner_br(torch.from_numpy(inst.br).cuda())
+        ctxs.append(c)
+        U.append(torch.from_numpy(inst.U).cuda())
+        v.append(torch.from_numpy(ci.scaled_direction(inst.U, 900 + q)).cuda())
+    del insts
+    R = [torch.empty_like(u) for u in U]
+    J = [torch.empty_like(u) for u in U]
+    cells = sum(c.grid.ncells for c in ctxs)
+    print(f"[bench] ensemble inputs: {len(ctxs)} instances, {cells} cells in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    ens = Ensemble(ctxs)
+    ens.bind(U, v=v, R=R, Jv=J)
+    best, ms = autotune(ens, reps=3, stream=s, use_cache=False)
+    ens.capture(s)
+    ens.replay(s)
+    s.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        ens.replay(s)
+    b.record(s)
+    b.synchronize()
+    batched = a.elapsed_time(b) / reps
+    with torch.cuda.stream(s):
+        for c, u, w, r, j in zip(ctxs, U, v, R, J):
+            c.jvp(u, w, out=j, R=r)
+        s.synchronize()
+        a.record(s)
+        for _ in range(reps):
+            for c, u, w, r, j in zip(ctxs, U, v, R, J):
+                c.jvp(u, w, out=j, R=r)
+        b.record(s)
+        b.synchronize()
+    sequential = a.elapsed_time(b) / reps
+    print(f"[bench] ensemble: batched {batched:.3f} ms, sequential {sequential:.3f} ms", file=sys.stderr, flush=True)
+    return {"instances": len(ctxs), "cells": cells, "op": "residual + JVP per instance",
+            "batched_graph_ms": round(batched, 4), "sequential_ms": round(sequential, 4),
+            "speedup": round(sequential / batched, 3), "repeats": reps,
+            "batched_mcells_per_s": round(cells / (batched * 1e-3) / 1e6, 1),
+            "tuning": best.as_dict(), "autotune_ms": {k: round(x, 4) for k, x in ms.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +137,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-reps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -160,6 +225,10 @@ def main():
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
     }
+    if not args.no_ensemble:
+        del ctx, U, v, w, R, Jv, gU
+        torch.cuda.empty_cache()
+        out["ensemble"] = bench_ensemble(args.ensemble_reps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample)

@@ -309,3 +309,9 @@ def ensemble_specs(n: int = 64, seed: int = BASE_SEED + 4000):
     specs = (shapes * reps)[:n]
     order = np.random.default_rng(seed).permutation(n)
     return [(specs[o][0], specs[o][1], seed + 1 + idx) for idx, o in enumerate(order)]
+
+
+def ensemble_instances(n: int = 64, lmax: int = 15):
+    """The ensemble's instances: each a log-spaced shell with its own seeded
+    state and magnetogram (as the 1.66M-cell workload, at its own size)."""
+    return [make_instance(N, Nr, "log", lmax=lmax, seed=s) for N, Nr, s in ensemble_specs(n)]

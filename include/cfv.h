@@ -51,6 +51,7 @@ enum {
 
 typedef struct cfv_grid cfv_grid;
 typedef struct cfv_ctx cfv_ctx;
+typedef struct cfv_ensemble cfv_ensemble;
 
 /* Physical and numerical parameters (nondimensional). */
 typedef struct {
@@ -167,6 +168,51 @@ cfv_status cfv_vjp_dir(cfv_ctx* ctx, const double* U, const double* w, const dou
  * held by the context is not moved). */
 cfv_status cfv_jvp_dir(cfv_ctx* ctx, const double* U, const double* v, const double* dU, const double* dbr, double eps,
                        double* Jv2, double* h_used, hipStream_t s);
+
+/* ------------------------------------------------------------ ensemble --
+ * Many independent instances (different grids, B_r maps and states; the
+ * magnetogram-driven ensembles the model is meant for) evaluated by one
+ * persistent launch per pass.  The work items are (instance, 16x16 column
+ * tile, chunk of 16 layers); every instance's items are the same ones its
+ * single-instance launch runs, so each instance's outputs are bitwise those
+ * of cfv_residual / cfv_jvp on its own context.  The contexts keep owning
+ * their grid tables, B_r map and gradient workspaces, so one context may
+ * appear in only one ensemble run at a time, and no two runs of ensembles
+ * sharing a context may overlap. */
+typedef struct {
+  int32_t queue;          /* 0: static split of the item list (each XCD takes a
+                             contiguous eighth); 1: device work counter */
+  int32_t blocks_per_cu;  /* persistent workgroups per compute unit, 1..16 */
+  int32_t order;          /* 0: instance order; 1: largest items first */
+} cfv_tuning;
+/* ctxs: host array of n contexts on the current device (not owned). */
+cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning* t, cfv_ensemble** out);
+void cfv_ensemble_destroy(cfv_ensemble* e);
+/* Change the schedule (drops a captured graph). */
+cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t);
+/* Number of work items and the workgroups a launch uses (host outputs). */
+cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks);
+/* Bind the per-instance device buffers (host arrays of n device pointers,
+ * copied into a device descriptor table; synchronous).  With v not NULL the
+ * run is the JVP: Jv[q] = J_U v[q] (+ J_b dbr[q] when dbr is not NULL), and
+ * R[q] too when R is not NULL.  With v NULL it is the residual: R required,
+ * Jv and dbr NULL.  Drops a captured graph. */
+cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const double* const* v,
+                             const double* const* dbr, double* const* R, double* const* Jv);
+/* Run the bound ensemble on stream s (two persistent launches). */
+cfv_status cfv_ensemble_run(cfv_ensemble* e, hipStream_t s);
+/* Bind (no map directions) and run. */
+cfv_status cfv_ensemble_residual_jvp(cfv_ensemble* e, const double* const* U, const double* const* v,
+                                     double* const* R, double* const* Jv, hipStream_t s);
+/* Capture one run of the bound ensemble into a HIP graph (s must be a created
+ * stream, not the null stream) and replay it.  The graph holds kernel nodes
+ * only (the queue counters are cleared by a kernel, not a memset). */
+cfv_status cfv_ensemble_graph_capture(cfv_ensemble* e, hipStream_t s);
+cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s);
+/* Per-kernel event timing of eager runs, as cfv_timing_enable / _read. */
+cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on);
+cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, double* total_ms, int64_t* count,
+                                    int32_t* n);
 
 /* ------------------------------------------------------------ profiling --
  * While enabled, every kernel launch of the context is bracketed by a pair of

@@ -7,4 +7,4 @@ its exact Jacobian-vector product and its adjoint, written as HIP kernels
 for gfx950 behind a C ABI (include/cfv.h) and bound here with ctypes.
 """
 from .params import Params, OUTER_CASES, V_REF  # noqa: F401
-from .binding import CfvError, Context, Grid, lib  # noqa: F401
+from .binding import CfvError, Context, Ensemble, Grid, Tuning, lib  # noqa: F401

@@ -25,6 +25,10 @@ class CfvParams(ctypes.Structure):
                 ("outer_exp", c_double * 8), ("outer_vr_mass", c_int32), ("outer_psi_zero", c_int32)]
 
 
+class CfvTuning(ctypes.Structure):
+    _fields_ = [("queue", c_int32), ("blocks_per_cu", c_int32), ("order", c_int32)]
+
+
 class CfvError(RuntimeError):
     pass
 
@@ -62,6 +66,17 @@ def lib():
         "cfv_be_step": ([P, P, c_double, c_int32, c_int32, c_double, P, P, c_int32, P, P, P], c_int32),
         "cfv_vjp_dir": ([P, P, P, P, c_double, P, P, P, P], c_int32),
         "cfv_jvp_dir": ([P, P, P, P, P, c_double, P, P, P], c_int32),
+        "cfv_ensemble_create": ([P, c_int32, P, ctypes.POINTER(P)], c_int32),
+        "cfv_ensemble_destroy": ([P], None),
+        "cfv_ensemble_set_tuning": ([P, P], c_int32),
+        "cfv_ensemble_items": ([P, P, P], c_int32),
+        "cfv_ensemble_bind": ([P, P, P, P, P, P], c_int32),
+        "cfv_ensemble_run": ([P, P], c_int32),
+        "cfv_ensemble_residual_jvp": ([P, P, P, P, P, P], c_int32),
+        "cfv_ensemble_graph_capture": ([P, P], c_int32),
+        "cfv_ensemble_graph_launch": ([P, P], c_int32),
+        "cfv_ensemble_timing_enable": ([P, c_int32], c_int32),
+        "cfv_ensemble_timing_read": ([P, c_int32, P, P, P, P], c_int32),
         "cfv_timing_enable": ([P, c_int32], c_int32),
         "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
@@ -94,6 +109,29 @@ def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _timing_read(fn, h, max_names):
+    names = ctypes.create_string_buffer(32 * max_names)
+    ms = (c_double * max_names)()
+    cnt = (c_int64 * max_names)()
+    n = c_int32()
+    check(fn(h, max_names, names, ms, cnt, ctypes.byref(n)))
+    out = {}
+    for q in range(n.value):
+        nm = names.raw[32 * q:32 * q + 32].split(b"\0", 1)[0].decode()
+        out[nm] = (ms[q], cnt[q])
+    return out
+
+
+def _ptr_array(ts, what):
+    """Host array of device pointers (None -> NULL array)."""
+    if ts is None:
+        return None
+    arr = (c_void_p * len(ts))()
+    for q, t in enumerate(ts):
+        arr[q] = _ptr(t).value if t is not None else None
+    return arr
 
 
 class Grid:
@@ -252,17 +290,102 @@ class Context:
 
     def timing_read(self, max_names=32):
         """{kernel name: (total ms, launches)} since the previous read."""
-        names = ctypes.create_string_buffer(32 * max_names)
-        ms = (c_double * max_names)()
-        cnt = (c_int64 * max_names)()
-        n = c_int32()
-        check(lib().cfv_timing_read(self._h, max_names, names, ms, cnt, ctypes.byref(n)))
-        out = {}
-        for q in range(n.value):
-            nm = names.raw[32 * q:32 * q + 32].split(b"\0", 1)[0].decode()
-            out[nm] = (ms[q], cnt[q])
-        return out
+        return _timing_read(lib().cfv_timing_read, self._h, max_names)
 
     def axpby(self, a, x, b, y, stream=None):
         check(lib().cfv_axpby(self._h, y.numel(), float(a), _ptr(x), float(b), _ptr(y), _stream(stream)))
         return y
+
+
+class Tuning:
+    """Schedule of the ensemble launch (cfv_tuning)."""
+
+    def __init__(self, queue: int = 1, blocks_per_cu: int = 2, order: int = 1):
+        self.queue, self.blocks_per_cu, self.order = int(queue), int(blocks_per_cu), int(order)
+
+    def c(self):
+        return CfvTuning(self.queue, self.blocks_per_cu, self.order)
+
+    def as_dict(self):
+        return {"queue": self.queue, "blocks_per_cu": self.blocks_per_cu, "order": self.order}
+
+    def __repr__(self):
+        return f"Tuning({self.queue}, {self.blocks_per_cu}, {self.order})"
+
+
+class Ensemble:
+    """Many instances (contexts) evaluated by one persistent launch per pass:
+    cfv_ensemble_*.  Lists of tensors are per instance, in context order."""
+
+    def __init__(self, contexts, tuning: Tuning | None = None):
+        self.contexts = list(contexts)
+        self.tuning = tuning or Tuning()
+        arr = (c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        h = c_void_p()
+        t = self.tuning.c()
+        check(lib().cfv_ensemble_create(arr, len(self.contexts), ctypes.byref(t), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cfv_ensemble_destroy(h)
+            self._h = None
+
+    def set_tuning(self, tuning: Tuning):
+        t = tuning.c()
+        check(lib().cfv_ensemble_set_tuning(self._h, ctypes.byref(t)))
+        self.tuning = tuning
+
+    def items(self):
+        """(work items, workgroups per launch)."""
+        tot, blk = c_int64(), c_int32()
+        check(lib().cfv_ensemble_items(self._h, ctypes.byref(tot), ctypes.byref(blk)))
+        return tot.value, blk.value
+
+    def _check(self, ts, name, shape_of):
+        if ts is None:
+            return
+        if len(ts) != len(self.contexts):
+            raise CfvError(f"{name}: need one tensor per instance")
+        for t, c in zip(ts, self.contexts):
+            if tuple(t.shape) != shape_of(c):
+                raise CfvError(f"{name} must have shape {shape_of(c)}")
+
+    def bind(self, U, v=None, dbr=None, R=None, Jv=None):
+        """Bind per-instance buffers (kept alive by the ensemble)."""
+        st = lambda c: (9, c.grid.ncells)
+        for ts, name, sh in ((U, "U", st), (v, "v", st), (R, "R", st), (Jv, "Jv", st),
+                             (dbr, "dbr", lambda c: (c.grid.nb,))):
+            self._check(ts, name, sh)
+        self._keep = (U, v, dbr, R, Jv)
+        check(lib().cfv_ensemble_bind(self._h, _ptr_array(U, "U"), _ptr_array(v, "v"), _ptr_array(dbr, "dbr"),
+                                      _ptr_array(R, "R"), _ptr_array(Jv, "Jv")))
+
+    def run(self, stream=None):
+        check(lib().cfv_ensemble_run(self._h, _stream(stream)))
+
+    def residual_jvp(self, U, v, R=None, Jv=None, stream=None):
+        """Bind and run; returns (R, Jv) lists (allocated when not given)."""
+        import torch
+        R = R if R is not None else [torch.empty(9, c.grid.ncells, dtype=torch.float64, device="cuda")
+                                     for c in self.contexts]
+        Jv = Jv if Jv is not None else [torch.empty(9, c.grid.ncells, dtype=torch.float64, device="cuda")
+                                        for c in self.contexts]
+        self.bind(U, v=v, R=R, Jv=Jv)
+        self.run(stream)
+        return R, Jv
+
+    def capture(self, stream):
+        """Capture one run of the bound ensemble into a graph (stream: a torch.cuda.Stream)."""
+        check(lib().cfv_ensemble_graph_capture(self._h, _stream(stream)))
+
+    def replay(self, stream):
+        check(lib().cfv_ensemble_graph_launch(self._h, _stream(stream)))
+
+    def timing_enable(self, on=True):
+        check(lib().cfv_ensemble_timing_enable(self._h, int(bool(on))))
+
+    def timing_read(self, max_names=32):
+        return _timing_read(lib().cfv_ensemble_timing_read, self._h, max_names)

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -104,6 +105,7 @@ struct cfv_ctx {
   double* A = nullptr;     // adjoint workspace
   double* part = nullptr;  // reduction partials
   int part_vectors = 0;
+  cfv::MarchArgs* slot = nullptr;  // descriptor of the current march launch
   // Krylov workspace (allocated on first use, grown as needed)
   int kry_m = 0;
   double* kry_V = nullptr;    // (m + 1) vectors of 9 ncells
@@ -329,7 +331,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
       (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->W, size_t(36) * nc)) ||
       (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
-      (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector()))) {
+      (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector())) ||
+      (st = dmalloc(&c->slot, 1))) {
     cfv_ctx_destroy(c);
     return st;
   }
@@ -351,6 +354,7 @@ void cfv_ctx_destroy(cfv_ctx* c) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->dcn) (void)hipFree(c->dcn);
+  if (c->slot) (void)hipFree(c->slot);
   double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
                   c->dir_u, c->dir_g, c->dir_b, c->dir_s};
   for (double* b : kb)
@@ -377,7 +381,7 @@ cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, R, nullptr};
-  CFV_HIP(cfv::launch_march(a, false, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
   return CFV_OK;
 }
 
@@ -386,7 +390,7 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
   cfv::MarchArgs a{c->dev(), U, v, dbr, c->W, c->Wd, R, Jv};
-  CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
   return CFV_OK;
 }
 
@@ -452,7 +456,7 @@ static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag
     CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
-    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
   }
   CFV_HIP(cfv::launch_add_diag(c->grid->g.ncells, diag, x, w, s));
   return CFV_OK;
@@ -569,7 +573,7 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   const int64_t n = 9 * c->grid->g.ncells;
   // U_new holds the right-hand side -R(U) during the solve
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
-  CFV_HIP(cfv::launch_march(a, false, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
   CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
   if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
@@ -669,32 +673,29 @@ cfv_status cfv_jvp_dir(cfv_ctx* c, const double* U, const double* v, const doubl
   CFV_HIP(cfv::launch_axpby(n, h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dp, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, Jv2};
-    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
   }
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dm, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, c->dir_g};
-    CFV_HIP(cfv::launch_march(a, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
   }
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, Jv2, s));
   return CFV_OK;
 }
 
-cfv_status cfv_timing_enable(cfv_ctx* c, int32_t on) {
-  if (cfv_status st = check_ctx(c)) return st;
-  c->timing = on != 0;
-  return CFV_OK;
-}
+}  // extern "C"
 
-cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
-  if (cfv_status st = check_ctx(c)) return st;
+namespace {
+// per kernel name: total milliseconds and launches of the recorded events; clears the record
+cfv_status timing_read(EventTimer& timer, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
   if (!names || !total_ms || !count || !n || max < 1) return fail(CFV_ERR_ARG, "bad timing buffers");
   std::vector<std::string> keys;
   std::vector<double> ms;
   std::vector<int64_t> cnt;
-  for (auto& r : c->timer.recs) {
+  for (auto& r : timer.recs) {
     float t = 0.f;
     if (!r.a || !r.b) continue;
     CFV_HIP(hipEventSynchronize(r.b));
@@ -709,7 +710,7 @@ cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_m
     ms[q] += t;
     cnt[q] += 1;
   }
-  c->timer.recycle();
+  timer.recycle();
   const int m = int(keys.size()) < max ? int(keys.size()) : max;
   for (int q = 0; q < m; ++q) {
     std::strncpy(names + 32 * q, keys[q].c_str(), 31);
@@ -719,6 +720,234 @@ cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_m
   }
   *n = m;
   return CFV_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- ensemble
+struct cfv_ensemble {
+  std::vector<cfv_ctx*> ctx;
+  cfv_tuning tune{};
+  int device = 0;
+  int num_cu = 0;
+  std::vector<int64_t> off;             // n + 1 prefix sums of items
+  int64_t total = 0;
+  cfv::MarchArgs* dargs = nullptr;      // n descriptors
+  int64_t* doff = nullptr;              // n + 1
+  int64_t* dperm = nullptr;             // total
+  unsigned* dcnt = nullptr;             // 2 queue counters
+  bool bound = false;
+  bool dual = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  EventTimer timer;
+  bool timing = false;
+};
+
+namespace {
+void drop_graph(cfv_ensemble* e) {
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  e->exec = nullptr;
+  e->graph = nullptr;
+}
+
+cfv_status check_tuning(const cfv_tuning* t) {
+  if (!t) return fail(CFV_ERR_ARG, "null tuning");
+  if ((t->queue != 0 && t->queue != 1) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
+      (t->order != 0 && t->order != 1))
+    return fail(CFV_ERR_ARG, "tuning: queue 0|1, blocks_per_cu 1..16, order 0|1");
+  return CFV_OK;
+}
+
+// processing order of the items: instance order, or the items of the largest
+// tiles first (cost ~ active columns x layers of the item), stable
+cfv_status upload_perm(cfv_ensemble* e) {
+  std::vector<int64_t> perm(size_t(e->total));
+  for (int64_t w = 0; w < e->total; ++w) perm[size_t(w)] = w;
+  if (e->tune.order == 1) {
+    std::vector<int32_t> cost(size_t(e->total));
+    for (size_t q = 0; q < e->ctx.size(); ++q) {
+      const cfv::Shape& g = e->ctx[q]->grid->g;
+      for (int64_t l = 0; l < e->off[q + 1] - e->off[q]; ++l) {
+        cfv::TileMap tm;
+        cfv::tile_of_logical(g, l, tm);
+        const int wi = std::min(cfv::kTI, g.N - tm.i0), wj = std::min(cfv::kTJ, g.N - tm.j0);
+        cost[size_t(e->off[q] + l)] = wi * wj * (tm.k1 - tm.k0);
+      }
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
+  }
+  CFV_HIP(hipMemcpy(e->dperm, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  return CFV_OK;
+}
+
+unsigned ensemble_blocks(const cfv_ensemble* e) {
+  int64_t b = int64_t(e->tune.blocks_per_cu) * e->num_cu;
+  const int64_t cap = (e->total + 7) / 8 * 8;
+  if (b > cap) b = cap;
+  b = b / 8 * 8;
+  if (b < 8) b = 8;
+  return unsigned(b);
+}
+
+cfv_status ensemble_launch(cfv_ensemble* e, hipStream_t s, bool timed) {
+  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, int(e->ctx.size()), e->total, e->tune.queue,
+                        ensemble_blocks(e)};
+  CFV_HIP(cfv::launch_march_ensemble(L, e->dual, s, timed && e->timing ? &e->timer : nullptr));
+  return CFV_OK;
+}
+}  // namespace
+extern "C" {
+
+cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning* t, cfv_ensemble** out) {
+  g_err.clear();
+  if (!ctxs || !out || n < 1) return fail(CFV_ERR_ARG, "need n >= 1 contexts and an output");
+  if (cfv_status st = check_tuning(t)) return st;
+  int dev = 0;
+  CFV_HIP(hipGetDevice(&dev));
+  for (int q = 0; q < n; ++q) {
+    if (cfv_status st = check_ctx(ctxs[q])) return st;
+    if (ctxs[q]->device != dev) return fail(CFV_ERR_ARG, "all contexts must live on the current device");
+  }
+  cfv_ensemble* e = new (std::nothrow) cfv_ensemble;
+  if (!e) return fail(CFV_ERR_ALLOC, "host allocation");
+  e->ctx.assign(ctxs, ctxs + n);
+  e->tune = *t;
+  e->device = dev;
+  hipError_t he = hipDeviceGetAttribute(&e->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (he != hipSuccess || e->num_cu < 1) {
+    delete e;
+    return fail(CFV_ERR_HIP, "cannot query the compute unit count");
+  }
+  e->off.assign(size_t(n) + 1, 0);
+  for (int q = 0; q < n; ++q) e->off[size_t(q) + 1] = e->off[size_t(q)] + cfv::march_logical_blocks(ctxs[q]->grid->g);
+  e->total = e->off[size_t(n)];
+  cfv_status st;
+  if ((st = dmalloc(&e->dargs, size_t(n))) || (st = dmalloc(&e->doff, size_t(n) + 1)) ||
+      (st = dmalloc(&e->dperm, size_t(e->total))) || (st = dmalloc(&e->dcnt, 2))) {
+    cfv_ensemble_destroy(e);
+    return st;
+  }
+  he = hipMemcpy(e->doff, e->off.data(), e->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    cfv_ensemble_destroy(e);
+    return fail(CFV_ERR_HIP, hipGetErrorString(he));
+  }
+  if ((st = upload_perm(e))) {
+    cfv_ensemble_destroy(e);
+    return st;
+  }
+  *out = e;
+  return CFV_OK;
+}
+
+void cfv_ensemble_destroy(cfv_ensemble* e) {
+  if (!e) return;
+  drop_graph(e);
+  void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete e;
+}
+
+cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (cfv_status st = check_tuning(t)) return st;
+  e->tune = *t;
+  drop_graph(e);
+  return upload_perm(e);
+}
+
+cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (total) *total = e->total;
+  if (blocks) *blocks = int32_t(ensemble_blocks(e));
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const double* const* v,
+                             const double* const* dbr, double* const* R, double* const* Jv) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!U) return fail(CFV_ERR_ARG, "null state array");
+  const bool dual = v != nullptr;
+  if (dual && !Jv) return fail(CFV_ERR_ARG, "a JVP needs Jv outputs");
+  if (!dual && (!R || Jv || dbr)) return fail(CFV_ERR_ARG, "a residual-only ensemble needs R and no Jv or dbr");
+  const size_t n = e->ctx.size();
+  std::vector<cfv::MarchArgs> h(n);
+  for (size_t q = 0; q < n; ++q) {
+    cfv_ctx* c = e->ctx[q];
+    if (!U[q] || (dual && (!v[q] || !Jv[q])) || (!dual && !R[q]))
+      return fail(CFV_ERR_ARG, "null pointer for instance " + std::to_string(q));
+    h[q] = cfv::MarchArgs{c->dev(), U[q], dual ? v[q] : nullptr, dbr ? dbr[q] : nullptr, c->W,
+                          dual ? c->Wd : nullptr, R ? R[q] : nullptr, dual ? Jv[q] : nullptr};
+  }
+  CFV_HIP(hipMemcpy(e->dargs, h.data(), n * sizeof(cfv::MarchArgs), hipMemcpyHostToDevice));
+  e->dual = dual;
+  e->bound = true;
+  drop_graph(e);
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_run(cfv_ensemble* e, hipStream_t s) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!e->bound) return fail(CFV_ERR_ARG, "bind the instance buffers first");
+  return ensemble_launch(e, s, true);
+}
+
+cfv_status cfv_ensemble_residual_jvp(cfv_ensemble* e, const double* const* U, const double* const* v,
+                                     double* const* R, double* const* Jv, hipStream_t s) {
+  if (cfv_status st = cfv_ensemble_bind(e, U, v, nullptr, R, Jv)) return st;
+  return cfv_ensemble_run(e, s);
+}
+
+cfv_status cfv_ensemble_graph_capture(cfv_ensemble* e, hipStream_t s) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!e->bound) return fail(CFV_ERR_ARG, "bind the instance buffers first");
+  if (!s) return fail(CFV_ERR_ARG, "capture needs a created (non-null) stream");
+  drop_graph(e);
+  CFV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  cfv_status st = ensemble_launch(e, s, false);
+  hipGraph_t g = nullptr;
+  const hipError_t he = hipStreamEndCapture(s, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (he != hipSuccess) return fail(CFV_ERR_HIP, hipGetErrorString(he));
+  e->graph = g;
+  CFV_HIP(hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0));
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!e->exec) return fail(CFV_ERR_ARG, "no captured graph (capture after the last bind or tuning change)");
+  CFV_HIP(hipGraphLaunch(e->exec, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  e->timing = on != 0;
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, double* total_ms, int64_t* count,
+                                    int32_t* n) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  return timing_read(e->timer, max, names, total_ms, count, n);
+}
+
+cfv_status cfv_timing_enable(cfv_ctx* c, int32_t on) {
+  if (cfv_status st = check_ctx(c)) return st;
+  c->timing = on != 0;
+  return CFV_OK;
+}
+
+cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
+  if (cfv_status st = check_ctx(c)) return st;
+  return timing_read(c->timer, max, names, total_ms, count, n);
 }
 
 }  // extern "C"

@@ -16,6 +16,14 @@ struct DevGrid {
   const double* br;  // inner-boundary B_r map, 6N^2, order (p, j, i)
 };
 
+// The first kernel argument read in place from the kernel-argument segment:
+// large descriptors (grid, parameters) are then loaded where they are used
+// instead of being preloaded whole into scalar registers, which spill.
+template <class A>
+__device__ __forceinline__ const A& first_kernel_arg() {
+  return *(const A*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 // load/store a scalar of type T from a value array and (for Dual) a tangent array
 __host__ __device__ __forceinline__ void ldT(const double* a, const double*, int64_t i, double& x) { x = a[i]; }
 __host__ __device__ __forceinline__ void ldT(const double* a, const double* b, int64_t i, Dual& x) {

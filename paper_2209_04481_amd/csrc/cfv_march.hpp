@@ -32,13 +32,8 @@ __host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g)
 // launch size: a multiple of 8 so that the remap below is a bijection
 __host__ __device__ __forceinline__ int64_t march_blocks(const Shape& g) { return (march_logical_blocks(g) + 7) / 8 * 8; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
-// give each XCD a contiguous range of (tile, chunk) so that neighbouring
-// tiles and chunks, which re-read each other's edge cells, share an L2.
-__host__ __device__ __forceinline__ bool tile_of(const Shape& g, int64_t b, int64_t nb, TileMap& tm) {
-  const int64_t per = nb / 8;
-  const int64_t l = (b % 8) * per + b / 8;
-  if (l >= march_logical_blocks(g)) return false;
+// logical block l (chunk fastest, then tile i, tile j, panel) -> tile and chunk
+__host__ __device__ __forceinline__ void tile_of_logical(const Shape& g, int64_t l, TileMap& tm) {
   const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kKC - 1) / kKC;
   int64_t r = l;
   const int ch = int(r % nch);
@@ -51,6 +46,16 @@ __host__ __device__ __forceinline__ bool tile_of(const Shape& g, int64_t b, int6
   tm.i0 = ti * kTI;
   tm.k0 = ch * kKC;
   tm.k1 = tm.k0 + kKC < g.Nr ? tm.k0 + kKC : g.Nr;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
+// give each XCD a contiguous range of (tile, chunk) so that neighbouring
+// tiles and chunks, which re-read each other's edge cells, share an L2.
+__host__ __device__ __forceinline__ bool tile_of(const Shape& g, int64_t b, int64_t nb, TileMap& tm) {
+  const int64_t per = nb / 8;
+  const int64_t l = (b % 8) * per + b / 8;
+  if (l >= march_logical_blocks(g)) return false;
+  tile_of_logical(g, l, tm);
   return true;
 }
 
@@ -466,6 +471,27 @@ struct FluxWG {
   }
 };
 
-hipError_t launch_march(const MarchArgs& a, bool dual, hipStream_t s, KernelTimer* t);
+// One instance; slot: device memory for one descriptor, owned by the caller
+// (calls sharing a slot must be ordered on one stream).
+hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t);
+
+// Ensemble launch: n instances described by args[n] (device), with
+// item_off[n + 1] (device) the prefix sums of march_logical_blocks per
+// instance (unused when n = 1).  Items (instance, tile, chunk) are taken in
+// the order perm[total] (device; null = identity) either statically (each of
+// the 8 XCDs takes a contiguous eighth of the list, strided over its
+// workgroups) or from a device counter (queue != 0; counters[2] are reset by
+// the launch itself).
+struct EnsembleLaunch {
+  const MarchArgs* args;
+  const int64_t* item_off;
+  const int64_t* perm;
+  unsigned* counters;
+  int n;
+  int64_t total;
+  int queue;
+  unsigned blocks;
+};
+hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t s, KernelTimer* t);
 
 }  // namespace cfv

@@ -24,11 +24,10 @@
 namespace cfv {
 
 // --------------------------------------------------------------- device glue
+// One (tile, chunk) of each pass; the single-instance kernels run one per
+// workgroup, the ensemble kernels (ensemble.hip) loop over a queue of them.
 template <class T>
-__global__ __launch_bounds__(kNT) void grad_march_kernel(MarchArgs a) {
-  __shared__ double lds[GradWG<T>::kLds];
-  TileMap tm;
-  if (!tile_of(a.d.g, blockIdx.x, gridDim.x, tm)) return;
+__device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMap& tm, double* lds) {
   const int t = threadIdx.x;
   GState<T> st;
   GradWG<T>::init(a, tm, st, t, lds);
@@ -41,10 +40,7 @@ __global__ __launch_bounds__(kNT) void grad_march_kernel(MarchArgs a) {
 }
 
 template <class T>
-__global__ __launch_bounds__(kNT) void flux_march_kernel(MarchArgs a) {
-  __shared__ double lds[FluxWG<T>::kLds];
-  TileMap tm;
-  if (!tile_of(a.d.g, blockIdx.x, gridDim.x, tm)) return;
+__device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMap& tm, double* lds) {
   const int t = threadIdx.x;
   FState<T> st;
   FluxWG<T>::init(a, tm, st, t);
@@ -59,22 +55,118 @@ __global__ __launch_bounds__(kNT) void flux_march_kernel(MarchArgs a) {
   FluxWG<T>::finish(a, tm, st, t);
 }
 
-hipError_t launch_march(const MarchArgs& a, bool dual, hipStream_t s, KernelTimer* t) {
-  const unsigned nb = unsigned(march_blocks(a.d.g));
+// ----------------------------------------------------------------- ensemble
+__global__ void reset_counters_kernel(unsigned* c) {
+  if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+}
+
+// copies its by-value descriptor into device memory (the single-instance
+// launch is the one-instance ensemble, whose descriptor lives in a slot)
+__global__ void put_args_kernel(MarchArgs, MarchArgs* __restrict__ dst) {
+  static_assert(sizeof(MarchArgs) % 8 == 0, "descriptor copied in 8-byte words");
+  constexpr int kW = int(sizeof(MarchArgs) / 8);
+  const uint64_t* src = (const uint64_t*)&first_kernel_arg<MarchArgs>();
+  uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+  for (int q = threadIdx.x; q < kW; q += blockDim.x) d[q] = src[q];
+}
+
+// next item of this workgroup: static (XCD-aware strided) or from the queue
+__device__ __forceinline__ int64_t next_item(const EnsembleLaunch& e, int64_t step, unsigned* counter, int* slot) {
+  if (e.queue) {
+    __syncthreads();  // every thread has read the previous slot
+    if (threadIdx.x == 0) *slot = int(atomicAdd(counter, 1u));
+    __syncthreads();
+    return *slot;
+  }
+  // workgroup b sits on XCD b % 8 as the (b / 8)-th of Q = blocks / 8; the
+  // XCD's workgroups share a contiguous eighth of the queue
+  const int64_t Q = e.blocks / 8, per = (e.total + 7) / 8;
+  const int64_t x = blockIdx.x % 8, r = blockIdx.x / 8;
+  const int64_t w = r + step * Q, idx = x * per + w;
+  return w < per && idx < e.total ? idx : e.total;
+}
+
+// the item index is the same in every lane: say so, so that descriptor and
+// table reads become scalar loads
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint64_t u = uint64_t(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int find_instance(const int64_t* __restrict__ off, int n, int64_t w) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= w) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <class T, bool Flux>
+__global__ __launch_bounds__(kNT) void march_ensemble_kernel(EnsembleLaunch e) {
+  constexpr int kL = Flux ? FluxWG<T>::kLds : GradWG<T>::kLds;
+  __shared__ double lds[kL];
+  __shared__ int slot;
+  unsigned* counter = e.counters + (Flux ? 1 : 0);
+  for (int64_t step = 0;; ++step) {
+    const int64_t q = uniform(next_item(e, step, counter, &slot));
+    if (q >= e.total) break;
+    const int64_t w = e.perm ? uniform(e.perm[q]) : q;
+    const int inst = e.n > 1 ? int(uniform(find_instance(e.item_off, e.n, w))) : 0;
+    const MarchArgs& a = e.args[inst];
+    TileMap tm;
+    tile_of_logical(a.d.g, e.n > 1 ? w - e.item_off[inst] : w, tm);
+    __syncthreads();  // the previous item's LDS reads are done
+    if (Flux)
+      flux_march_tile<T>(a, tm, lds);
+    else
+      grad_march_tile<T>(a, tm, lds);
+  }
+}
+
+hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t s, KernelTimer* t) {
+  if (e.total <= 0) return hipSuccess;
+  if (e.queue) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, e.counters);
+  if (dual) {
+    {
+      TimedScope ts(t, "grad_march_ens_jvp", s);
+      hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
+    }
+    TimedScope ts(t, "flux_march_ens_jvp", s);
+    hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  } else {
+    {
+      TimedScope ts(t, "grad_march_ens", s);
+      hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
+    }
+    TimedScope ts(t, "flux_march_ens", s);
+    hipLaunchKernelGGL((march_ensemble_kernel<double, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  }
+  return hipGetLastError();
+}
+
+// One instance: the descriptor goes to the context's slot, then the same
+// persistent kernels run with one workgroup per item (no queue, no table).
+hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t) {
+  hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
+  const int64_t total = march_logical_blocks(a.d.g);
+  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
   if (dual) {
     {
       TimedScope ts(t, "grad_march_jvp", s);
-      hipLaunchKernelGGL((grad_march_kernel<Dual>), dim3(nb), dim3(kNT), 0, s, a);
+      hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
     }
     TimedScope ts(t, "flux_march_jvp", s);
-    hipLaunchKernelGGL((flux_march_kernel<Dual>), dim3(nb), dim3(kNT), 0, s, a);
+    hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
   } else {
     {
       TimedScope ts(t, "grad_march", s);
-      hipLaunchKernelGGL((grad_march_kernel<double>), dim3(nb), dim3(kNT), 0, s, a);
+      hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
     }
     TimedScope ts(t, "flux_march", s);
-    hipLaunchKernelGGL((flux_march_kernel<double>), dim3(nb), dim3(kNT), 0, s, a);
+    hipLaunchKernelGGL((march_ensemble_kernel<double, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
   }
   return hipGetLastError();
 }

@@ -281,9 +281,10 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
   for (int v = 0; v < 9; ++v) gU[v * nc + c] = Ub[v];
 }
 
-__global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid d, const double* __restrict__ w,
+__global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, double* __restrict__ A,
                                                           double* __restrict__ gbr) {
+  const DevGrid& d = first_kernel_arg<DevGrid>();
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c < d.g.ncells) adjoint_cell(d, w, W, A, gbr, c);
 }
