@@ -39,6 +39,29 @@ OP_KERNELS = {
 }
 
 
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch recorded from the rocprofv3 counter passes in
+    profiles/, or None when the kernel sources changed since they were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record: "):
+                    continue
+                rec = json.loads(line[len("traffic-record: "):])
+                if rec.get("kernel") != kernel or rec.get("workload") != workload:
+                    continue
+                h = hashlib.sha1()
+                for src in rec["sources"]:
+                    with open(os.path.join(ROOT, "paper_2209_04481_amd", "csrc", src), "rb") as g:
+                        h.update(g.read())
+                if h.hexdigest() != rec["sources_sha1"]:
+                    return None, os.path.relpath(path, ROOT) + " (stale: kernel sources changed)"
+                return rec["bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(inst, ncells_sample: int):
     """Oracle residual + JVP + VJP on a contiguous block of cells."""
     import torch
@@ -136,8 +159,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-sample", type=int, default=327680)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy a 1 GiB buffer twice (reference dispatches for HBM counters)")
     ap.add_argument("--ensemble-reps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -201,8 +226,11 @@ def main():
         op_ms[op] = sum(times[k][0] / times[k][1] for k in ks if k in times)
     dom = max(op_ms, key=op_ms.get)
     achieved = ALG_BYTES[dom] * nc / (op_ms[dom] * 1e-3) / 1e9
+    traffic, traffic_src = traffic_record(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_note": ("bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy; "
+                                 f"from {traffic_src}") if traffic_src else None,
                 "kernel": f"{dom} ({' + '.join(OP_KERNELS[dom])})", "avg_ms": round(op_ms[dom], 4),
                 "alg_bytes_per_cell": ALG_BYTES[dom]}
 
@@ -225,6 +253,13 @@ def main():
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_ensemble:
         del ctx, U, v, w, R, Jv, gU
         torch.cuda.empty_cache()

@@ -137,10 +137,6 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
 }
 
 // launchers (residual.hip)
-hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s,
-                           KernelTimer* t = nullptr);
-hipError_t launch_jvp(const DevGrid& d, const double* U, const double* v, const double* dbr, double* Jv, double* R,
-                      double* W, double* Wd, hipStream_t s, KernelTimer* t = nullptr);
 hipError_t launch_geometry(const DevGrid& d, double* xc, double* vol, double* xf, double* S, hipStream_t s);
 hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s,
                            KernelTimer* t = nullptr);

@@ -1,16 +1,15 @@
-// Residual and forward-derivative kernels (first, two-pass form).
+// Cell-centric kernels: the forward pass the adjoint replays, the local time
+// step, and the geometry export.
 //
-// Pass 1 (grad_limit): per cell, primitives of the cell and its six face
-// neighbours (ghost states on boundary faces), the unweighted least-squares
-// gradient, and the Barth-Jespersen factor; writes the primitives and the
-// limited gradient (9 + 27 values) to a workspace.
-// Pass 2 (flux): per cell, for each of its six faces, reconstructs both sides
-// at the face centroid, evaluates the Rusanov flux in the face's canonical
-// orientation (owner on the left, owner's geometry) and accumulates it with
-// the sign of the side; subtracts V times the gravity source.
-//
-// Both passes are templated on the scalar: double for R(U), Dual for
-// J_U v + J_b dbr together with R.
+// grad_limit: per cell, primitives of the cell and its six face neighbours
+// (ghost states on boundary faces), the unweighted least-squares gradient,
+// and the Barth-Jespersen factor; writes the primitives and the limited
+// gradient (9 + 27 values) to a workspace.
+// flux (diagonal form): per cell, for each of its six faces, reconstructs
+// both sides at the face centroid and takes the Rusanov speed times the face
+// area: the backward-Euler diagonal.  (The same routine with the flux
+// accumulation is the cell-centric residual, templated on the scalar; the
+// residual and JVP themselves run in the radial-march kernels.)
 #include "cfv_kernels.hpp"
 
 namespace cfv {
@@ -186,36 +185,6 @@ __global__ __launch_bounds__(kBlock) void geometry_kernel(DevGrid d, double* xc,
 }
 
 static inline dim3 grid_for(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); }
-
-hipError_t launch_residual(const DevGrid& d, const double* U, double* R, double* W, hipStream_t s, KernelTimer* t) {
-  const int64_t nc = d.g.ncells;
-  {
-    TimedScope ts(t, "grad_limit", s);
-    hipLaunchKernelGGL((grad_limit_kernel<double>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
-                       nullptr);
-  }
-  {
-    TimedScope ts(t, "flux", s);
-    hipLaunchKernelGGL((flux_kernel<double, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, nullptr, nullptr, W,
-                       nullptr, R, nullptr, nullptr, 1.0);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_jvp(const DevGrid& d, const double* U, const double* v, const double* dbr, double* Jv, double* R,
-                      double* W, double* Wd, hipStream_t s, KernelTimer* t) {
-  const int64_t nc = d.g.ncells;
-  {
-    TimedScope ts(t, "grad_limit_jvp", s);
-    hipLaunchKernelGGL((grad_limit_kernel<Dual>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd);
-  }
-  {
-    TimedScope ts(t, "flux_jvp", s);
-    hipLaunchKernelGGL((flux_kernel<Dual, false>), grid_for(nc), dim3(kBlock), 0, s, d, U, v, dbr, W, Wd, R, Jv,
-                       nullptr, 1.0);
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_grad_limit_forward(const DevGrid& d, const double* U, double* W, hipStream_t s, KernelTimer* t) {
   TimedScope ts(t, "grad_limit", s);
