@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 # algorithmic HBM bytes per cell and operation (FP64 SoA, 9 variables)
 ALG_BYTES = {"residual": 144, "jvp": 216, "vjp": 216}
 OP_KERNELS = {
@@ -39,26 +40,28 @@ OP_KERNELS = {
 }
 
 
-def traffic_record(kernel: str, workload: str):
-    """HBM bytes per launch recorded from the rocprofv3 counter passes in
-    profiles/, or None when the kernel sources changed since they were taken."""
+def profile_record(prefix: str, match: dict):
+    """A record line ("<prefix>: {json}") from the rocprofv3 summaries in
+    profiles/ whose keys match; returns (record, source) with record None when
+    the kernel sources changed since the counters were taken."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
-                if not line.startswith("traffic-record: "):
+                if not line.startswith(prefix + ": "):
                     continue
-                rec = json.loads(line[len("traffic-record: "):])
-                if rec.get("kernel") != kernel or rec.get("workload") != workload:
+                rec = json.loads(line[len(prefix) + 2:])
+                if any(rec.get(k) != v for k, v in match.items()):
                     continue
                 h = hashlib.sha1()
                 for src in rec["sources"]:
                     with open(os.path.join(ROOT, "paper_2209_04481_amd", "csrc", src), "rb") as g:
                         h.update(g.read())
+                rel = os.path.relpath(path, ROOT)
                 if h.hexdigest() != rec["sources_sha1"]:
-                    return None, os.path.relpath(path, ROOT) + " (stale: kernel sources changed)"
-                return rec["bytes_per_launch"], os.path.relpath(path, ROOT)
+                    return None, rel + " (stale: kernel sources changed)"
+                return rec, rel
     return None, None
 
 
@@ -226,7 +229,8 @@ def main():
         op_ms[op] = sum(times[k][0] / times[k][1] for k in ks if k in times)
     dom = max(op_ms, key=op_ms.get)
     achieved = ALG_BYTES[dom] * nc / (op_ms[dom] * 1e-3) / 1e9
-    traffic, traffic_src = traffic_record(dom, args.workload)
+    trec, traffic_src = profile_record("traffic-record", {"kernel": dom, "workload": args.workload})
+    traffic = trec["bytes_per_launch"] if trec else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_note": ("bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy; "
@@ -253,6 +257,14 @@ def main():
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
     }
+    vrec, vsrc = profile_record("valu-record", {"workload": args.workload})
+    if vrec:
+        out["fp64_valu"] = {
+            op: {"flop_per_cell": f, "tflops": round(f * nc / (op_ms[op] * 1e-3) / 1e12, 2),
+                 "frac": round(f * nc / (op_ms[op] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+            for op, f in vrec["flop_per_cell"].items()}
+        out["fp64_valu_note"] = (f"executed FP64 flops per cell from rocprofv3 counters ({vsrc}) over the measured "
+                                 f"operation times; peak {FP64_PEAK_TFLOPS} TFLOP/s")
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

@@ -16,7 +16,8 @@ Nuances of Global Coronal Models") and shares no code with the HIP path:
   Section 2.1), second-order finite-volume reconstruction, the low-E inner
   boundary (Eq. 25, Section 3.2) and the outer ghost laws (Table 2).
 * ``solve``: local pseudo-time step, the Eq. 2 residual monitor, GMRES and the
-  backward-Euler step (Section 2.1), and the Br sensitivity.
+  backward-Euler step (Section 2.1), and the exact B_r-map gradient of an
+  objective after several implicit steps (dense, small grids).
 
 Everything is float64 PyTorch CPU code, vectorised over cells and faces with
 no blocking or fusion.  Forward-mode derivatives (JVP) use torch.func.jvp and

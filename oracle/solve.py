@@ -11,6 +11,10 @@
 * ``gmres``: unrestarted GMRES(m), x0 = 0, modified Gram-Schmidt, Givens
   least squares, for the implicit step (D + J) x = -R (Section 2.1: backward
   Euler with large CFL).
+* ``layer_objective`` and ``step_map_sensitivity``: an objective on the state
+  after n implicit steps with a fixed diagonal, and its exact gradient with
+  respect to the inner B_r map, by reverse mode through the unrolled steps
+  with the Jacobian formed densely (small grids only).
 """
 from __future__ import annotations
 
@@ -124,3 +128,47 @@ def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None):
 
     x, hist = gmres(A, -R, m)
     return U + x, hist, R
+
+
+def layer_objective(grid: Grid, layer=None):
+    """lam with L = <lam, U>: the mean over the 6N^2 cells of one radial layer
+    (default the outermost) of the momentum (rho v) projected on r_hat at the
+    cell's upper (r+) face centroid."""
+    k = grid.Nr - 1 if layer is None else int(layer)
+    cols = torch.arange(grid.nb)
+    p, rest = cols // (grid.N * grid.N), cols % (grid.N * grid.N)
+    cells = grid.encode(p, torch.full_like(p, k), rest // grid.N, rest % grid.N)
+    _, _, xf, _ = grid.cell_geometry(cells)
+    xo = xf[:, 1]
+    rh = xo / torch.linalg.norm(xo, dim=-1, keepdim=True)
+    lam = torch.zeros(9, grid.ncells, dtype=DT)
+    lam[1:4, cells] = rh.T / grid.nb
+    return lam
+
+
+def step_map_sensitivity(grid: Grid, U0, br, prm, D0, nsteps: int, lam, want_grad: bool = True):
+    """L = <lam, U_n> after n steps of U <- U - (D0 + J(U, b))^{-1} R(U, b) from U0,
+    with D0 a fixed per-cell diagonal (the implicit step of Section 2.1 with
+    exact solves, V/dt held at its initial value), and dL/db.
+
+    The Jacobian is formed densely by reverse mode, each step solves the dense
+    system, and the gradient is reverse mode through everything: residuals,
+    Jacobians (second derivatives included) and solves.  Returns (L, dL/db)
+    (dL/db is None when want_grad is False)."""
+    n = 9 * grid.ncells
+    D = torch.as_tensor(D0, dtype=DT).detach()
+    b = br.detach().clone().requires_grad_(want_grad)
+    U = U0.detach().clone()
+    for _ in range(nsteps):
+        def f(u):
+            return mhd.residual(grid, u, b, prm)
+        R = f(U)
+        J = torch.autograd.functional.jacobian(f, U, create_graph=want_grad, vectorize=True)
+        A = J.reshape(n, n) + torch.diag(D.repeat(9))
+        x = torch.linalg.solve(A, -R.reshape(n))
+        U = U + x.reshape(9, grid.ncells)
+    L = (lam * U).sum()
+    if not want_grad:
+        return float(L), None
+    gb, = torch.autograd.grad(L, b)
+    return float(L.detach()), gb

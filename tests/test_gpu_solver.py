@@ -85,6 +85,46 @@ def test_be_step_medium_history_is_the_true_residual():
     assert abs(true_rel - hist[-1]) <= 1e-6 * hist[-1]
 
 
+@pytest.mark.parametrize("psi_noise", [False, True])
+def test_br_sensitivity_matches_the_oracle_exact_gradient(psi_noise):
+    """Two implicit steps on a 48-cell grid: the objective equals the
+    oracle's (dense solves), the tangent sweep equals the oracle's exact
+    gradient (reverse mode through dense Jacobians and solves), and so does
+    the adjoint, tightly once psi is not identically zero: with psi = 0 every
+    cell sits on the psi limiter's kink at step 0, where the adjoint's
+    central difference along the step is direction-dependent."""
+    from paper_2209_04481_amd.sensitivity import Sensitivity
+    print(f"case: sensitivity vs oracle, psi noise {psi_noise}", flush=True)
+    inst = ci.make_instance(2, 2, "log", lmax=2, seed=5)
+    U0n = inst.U.copy()
+    if psi_noise:
+        U0n[8] = np.random.default_rng(6).standard_normal(inst.ncells) * 1e-3 * np.abs(inst.U[4:7]).max()
+    ctx = context(inst)
+    U0 = torch.from_numpy(U0n).cuda()
+    br = torch.from_numpy(inst.br).cuda()
+    sens = Sensitivity(ctx, U0, cfl=1.0, nsteps=2, every=1, max_restarts=40, rtol=1e-14, layer=0)
+    L, gb = sens.gradient(br)
+    assert sens.max_rel <= 1e-13
+    og = OGrid(2, 2, inst.r_nodes)
+    prm = mhd.Params()
+    U0o, bro = torch.from_numpy(U0n), torch.from_numpy(inst.br)
+    D0 = solve.local_dt_diag(og, U0o, bro, prm, 1.0)
+    Lo, gbo = solve.step_map_sensitivity(og, U0o, bro, prm, D0, 2, solve.layer_objective(og, 0))
+    print(f"  L {L:.15e} oracle {Lo:.15e}")
+    assert abs(L - Lo) <= 1e-12 * abs(Lo)
+    rel_adj = float((gb.cpu() - gbo).norm() / gbo.norm())
+    print(f"  adjoint vs oracle gradient: {rel_adj:.2e}")
+    # the central differences of the step's second-order terms carry about
+    # 1e-6 (rounding at a 1e-6 relative step); the psi kink adds about 2e-5
+    assert rel_adj <= (5e-6 if psi_noise else 1e-4)
+    for q, d in enumerate(_map_dirs(ctx, br, 3)):
+        _, tg = sens.tangent(br, d)
+        ex = float((gbo * d.cpu()).sum())
+        scale = float(gbo.norm() * d.cpu().norm())
+        print(f"  dir {q}: tangent {tg:.12e} oracle {ex:.12e} error / (|g| |d|) {abs(tg - ex) / scale:.1e}")
+        assert abs(tg - ex) <= 1e-5 * scale
+
+
 def _map_dirs(ctx, br, k, seed=99):
     rng = np.random.default_rng(seed)
     return [torch.from_numpy(rng.standard_normal(ctx.grid.nb)).cuda() * float(br.abs().max()) * 1e-2

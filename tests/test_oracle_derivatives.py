@@ -103,3 +103,45 @@ def test_eq2_monitor():
     b = torch.tensor([[1.0, 2.0, 2.0], [3.0, 4.0, 1.0]], dtype=DT)
     out = solve.eq2(a, b)
     assert torch.allclose(out, torch.tensor([0.0, np.log10(5.0)], dtype=DT))
+
+
+def test_step_map_gradient_matches_central_differences():
+    """The oracle's exact B_r gradient after two implicit steps (dense
+    Jacobians, reverse mode through the solves) against central differences
+    of the objective at two step sizes, with the diagonal held fixed."""
+    import numpy as np
+    import coronal_inputs as ci
+    inst = ci.make_instance(2, 2, "log", lmax=2, seed=5)
+    g = Grid(2, 2, inst.r_nodes)
+    prm = mhd.Params()
+    U0, br = torch.from_numpy(inst.U), torch.from_numpy(inst.br)
+    D0 = solve.local_dt_diag(g, U0, br, prm, 1.0)
+    lam = solve.layer_objective(g, 0)
+    L, gb = solve.step_map_sensitivity(g, U0, br, prm, D0, 2, lam)
+    rng = np.random.default_rng(1)
+    for _ in range(2):
+        d = torch.from_numpy(rng.standard_normal(g.nb)) * float(br.abs().max()) * 1e-2
+        fd = []
+        for h in (1e-3, 1e-4):
+            Lp, _ = solve.step_map_sensitivity(g, U0, br + h * d, prm, D0, 2, lam, want_grad=False)
+            Lm, _ = solve.step_map_sensitivity(g, U0, br - h * d, prm, D0, 2, lam, want_grad=False)
+            fd.append((Lp - Lm) / (2 * h))
+        ad = float((gb * d).sum())
+        assert abs(fd[0] - fd[1]) <= 1e-6 * abs(fd[0])
+        assert abs(ad - fd[1]) <= 1e-6 * abs(fd[1])
+
+
+def test_layer_objective_weights():
+    """lam picks rho v . r_hat at the upper face centroid of every cell of
+    the layer, each with weight 1/(6N^2)."""
+    g = Grid(3, 4, torch.linspace(1.0, 2.0, 5, dtype=torch.float64))
+    lam = solve.layer_objective(g, 2)
+    U = torch.zeros(9, g.ncells, dtype=torch.float64)
+    cells = torch.arange(g.ncells)
+    p, k, j, i = g.decode(cells)
+    _, _, xf, _ = g.cell_geometry(cells)
+    rh = xf[:, 1] / torch.linalg.norm(xf[:, 1], dim=-1, keepdim=True)
+    U[1:4] = rh.T  # unit radial momentum at every cell
+    assert abs(float((lam * U).sum()) - 1.0) < 1e-14
+    assert float(lam[:, k != 2].abs().max()) == 0.0
+    assert float(lam[[0, 4, 5, 6, 7, 8]].abs().max()) == 0.0
