@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=327680)
+    ap.add_argument("--cpu-sample", type=int, default=786432)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 1 GiB buffer twice (reference dispatches for HBM counters)")

@@ -104,8 +104,18 @@ __device__ __forceinline__ int find_instance(const int64_t* __restrict__ off, in
   return lo;
 }
 
+// Wavefronts per SIMD each pass is compiled for (register budget 512 / n per
+// lane; the LDS of n workgroups must fit in 160 KB).  Measured on the 13.3M-
+// cell shell: the residual passes run 25-30% faster at 2 than at 1 despite a
+// few hundred bytes of spills, and slower at 3 or 4; the JVP flux pass needs
+// 148 KB of LDS and stays at 1.
 template <class T, bool Flux>
-__global__ __launch_bounds__(kNT) void march_ensemble_kernel(EnsembleLaunch e) {
+struct MarchOccupancy {
+  static constexpr int value = (Flux && sizeof(T) != sizeof(double)) ? 1 : 2;
+};
+
+template <class T, bool Flux>
+__global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_ensemble_kernel(EnsembleLaunch e) {
   constexpr int kL = Flux ? FluxWG<T>::kLds : GradWG<T>::kLds;
   __shared__ double lds[kL];
   __shared__ int slot;
