@@ -137,6 +137,35 @@ def test_parity_log_grid_ragged(limiter):
         assert float(rel_err_per_var(a, b).max()) <= TOL
 
 
+# Non-default physics: adiabatic gamma, a slower cleaning speed, no gravity,
+# another inner density, temperature and outflow, a zero-gradient psi ghost.
+PARAM_SETS = {
+    "gamma5/3": dict(gamma=5.0 / 3.0),
+    "c_h0.3": dict(c_h=0.3),
+    "no_gravity": dict(G=0.0),
+    "inner_state": dict(rho_b=2.5, T_b=0.05, vr_star=0.02),
+    "psi_neumann": dict(outer_psi_zero=False, outer_vr_mass=False),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PARAM_SETS))
+def test_parity_other_parameters(name):
+    print(f"case: parameters {name}", flush=True)
+    inst = ci.make_instance(5, 7, "log", lmax=3, seed=40 + len(name))
+    inst.U[8] = 1e-3 * np.random.default_rng(len(name)).standard_normal(inst.ncells)   # psi != 0
+    c = Case(inst, mhd.Params(**PARAM_SETS[name]))
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(7))
+    v = torch.tensor(ci.scaled_direction(inst.U, 8))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, 8))
+    R = c.ctx.residual(c.Ud).cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda()).cpu()
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    Jo, Ro = solve.jvp(c.og, c.U, c.br, c.op, v, dbr)
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w)
+    for a, b in ((R, Ro), (Jv, Jo), (gU.cpu(), gUo), (gbr.cpu()[None], gbro[None])):
+        assert float(rel_err_per_var(a, b).max()) <= TOL
+
+
 @pytest.mark.parametrize("case", range(1, 10))
 def test_parity_every_table2_outer_law(case):
     print(f"case: Table 2 outer law {case}", flush=True)
