@@ -96,7 +96,7 @@ def cpu_baseline(inst, ncells_sample: int):
                       f"{dt:.1f} s"}
 
 
-def bench_ensemble(reps: int):
+def bench_ensemble(reps: int, solve_reps: int = 2):
     """64 uneven instances (29.95M cells): residual + JVP of all of them as one
     captured graph of two persistent launches, against 64 single-instance
     launches in sequence on the same stream (not captured)."""
@@ -148,11 +148,50 @@ def bench_ensemble(reps: int):
         b.synchronize()
     sequential = a.elapsed_time(b) / reps
     print(f"[bench] ensemble: batched {batched:.3f} ms, sequential {sequential:.3f} ms", file=sys.stderr, flush=True)
+    solve = bench_ensemble_solve(ens, ctxs, U, s, solve_reps) if solve_reps > 0 else None
     return {"instances": len(ctxs), "cells": cells, "op": "residual + JVP per instance",
             "batched_graph_ms": round(batched, 4), "sequential_ms": round(sequential, 4),
             "speedup": round(sequential / batched, 3), "repeats": reps,
             "batched_mcells_per_s": round(cells / (batched * 1e-3) / 1e6, 1),
-            "tuning": best.as_dict(), "autotune_ms": {k: round(x, 4) for k, x in ms.items()}}
+            "tuning": best.as_dict(), "autotune_ms": {k: round(x, 4) for k, x in ms.items()},
+            "solve": solve}
+
+
+def bench_ensemble_solve(ens, ctxs, U, s, reps: int, cfl: float = 1e3, m: int = 30):
+    """One backward-Euler step (GMRES(30), CFL 1e3) of all instances: one
+    captured graph of the lockstep device solve, against cfv_be_step of each
+    instance in sequence (one host synchronisation per GMRES iteration)."""
+    import torch
+    U_new = [torch.empty_like(u) for u in U]
+    hist = torch.zeros(len(ctxs), m, dtype=torch.float64, device="cuda")
+    ens.bind_be_step(U, U_new, cfl, m, hist)
+    ens.capture(s)
+    ens.replay(s)
+    s.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        ens.replay(s)
+    b.record(s)
+    b.synchronize()
+    batched = a.elapsed_time(b) / reps
+    with torch.cuda.stream(s):
+        outs = [torch.empty_like(u) for u in U]
+        for c, u, o in zip(ctxs, U, outs):
+            c.be_step(u, cfl=cfl, m=m, out=o)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for c, u, o in zip(ctxs, U, outs):
+                c.be_step(u, cfl=cfl, m=m, out=o)
+        s.synchronize()
+        sequential = (time.perf_counter() - t0) * 1e3 / reps
+    diff = max(float(((x - u) - (y - u)).norm() / (y - u).norm()) for x, y, u in zip(U_new, outs, U))
+    print(f"[bench] ensemble solve: batched {batched:.1f} ms, sequential {sequential:.1f} ms", file=sys.stderr,
+          flush=True)
+    return {"op": f"backward-Euler step, GMRES({m}), CFL {cfl:g}, per instance", "batched_graph_ms": round(batched, 2),
+            "sequential_ms": round(sequential, 2), "speedup": round(sequential / batched, 3), "repeats": reps,
+            "max_rel_step_difference": diff}
 
 
 def main():
@@ -167,6 +206,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 1 GiB buffer twice (reference dispatches for HBM counters)")
     ap.add_argument("--ensemble-reps", type=int, default=50)
+    ap.add_argument("--solve-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -275,7 +315,7 @@ def main():
     if not args.no_ensemble:
         del ctx, U, v, w, R, Jv, gU
         torch.cuda.empty_cache()
-        out["ensemble"] = bench_ensemble(args.ensemble_reps)
+        out["ensemble"] = bench_ensemble(args.ensemble_reps, args.solve_reps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample)

@@ -199,12 +199,26 @@ cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* bl
  * Jv and dbr NULL.  Drops a captured graph. */
 cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const double* const* v,
                              const double* const* dbr, double* const* R, double* const* Jv);
-/* Run the bound ensemble on stream s (two persistent launches). */
+/* Bind a backward-Euler step of every instance (the ensemble form of
+ * cfv_be_step with max_restarts = 0 and rtol = 0): U_new[q] = U[q] + x_q with
+ * (V/dt + J) x_q = -R(U[q]) solved by GMRES(m) from x = 0 with modified
+ * Gram-Schmidt, all instances in lockstep.  Every scalar of the solve (norms,
+ * Gram-Schmidt coefficients, Givens rotations, the least-squares solve) stays
+ * on the device, so a run needs no host synchronisation and can be captured.
+ * hist (device, nullable, n x m) receives each instance's relative residual
+ * after every iteration (an instance that breaks down or converges exactly
+ * repeats its last value).  The Krylov workspace ((m + 2) state vectors per
+ * instance) is owned by the ensemble.  U_new[q] must not alias U[q].  Drops a
+ * captured graph; cfv_ensemble_run / _graph_capture then run the step. */
+cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, double* const* U_new, double cfl,
+                                     int32_t m, double* hist);
+/* Run what is bound on stream s: the residual / JVP (two persistent
+ * launches) or the backward-Euler step. */
 cfv_status cfv_ensemble_run(cfv_ensemble* e, hipStream_t s);
 /* Bind (no map directions) and run. */
 cfv_status cfv_ensemble_residual_jvp(cfv_ensemble* e, const double* const* U, const double* const* v,
                                      double* const* R, double* const* Jv, hipStream_t s);
-/* Capture one run of the bound ensemble into a HIP graph (s must be a created
+/* Capture one run of what is bound into a HIP graph (s must be a created
  * stream, not the null stream) and replay it.  The graph holds kernel nodes
  * only (the queue counters are cleared by a kernel, not a memset). */
 cfv_status cfv_ensemble_graph_capture(cfv_ensemble* e, hipStream_t s);

@@ -72,6 +72,7 @@ def lib():
         "cfv_ensemble_items": ([P, P, P], c_int32),
         "cfv_ensemble_bind": ([P, P, P, P, P, P], c_int32),
         "cfv_ensemble_run": ([P, P], c_int32),
+        "cfv_ensemble_bind_be_step": ([P, P, P, c_double, c_int32, P], c_int32),
         "cfv_ensemble_residual_jvp": ([P, P, P, P, P, P], c_int32),
         "cfv_ensemble_graph_capture": ([P, P], c_int32),
         "cfv_ensemble_graph_launch": ([P, P], c_int32),
@@ -362,6 +363,27 @@ class Ensemble:
         self._keep = (U, v, dbr, R, Jv)
         check(lib().cfv_ensemble_bind(self._h, _ptr_array(U, "U"), _ptr_array(v, "v"), _ptr_array(dbr, "dbr"),
                                       _ptr_array(R, "R"), _ptr_array(Jv, "Jv")))
+
+    def bind_be_step(self, U, U_new, cfl=1e3, m=30, hist=None):
+        """Bind one backward-Euler step of every instance (GMRES(m), on the
+        device); hist: optional (n, m) float64 CUDA tensor for the histories."""
+        st = lambda c: (9, c.grid.ncells)
+        self._check(U, "U", st)
+        self._check(U_new, "U_new", st)
+        if hist is not None and tuple(hist.shape) != (len(self.contexts), int(m)):
+            raise CfvError(f"hist must have shape ({len(self.contexts)}, {int(m)})")
+        self._keep = (U, U_new, hist)
+        check(lib().cfv_ensemble_bind_be_step(self._h, _ptr_array(U, "U"), _ptr_array(U_new, "U_new"), float(cfl),
+                                              int(m), _ptr(hist)))
+
+    def be_step(self, U, cfl=1e3, m=30, stream=None):
+        """Bind and run one step; returns (U_new list, (n, m) history tensor)."""
+        import torch
+        U_new = [torch.empty_like(u) for u in U]
+        hist = torch.zeros(len(self.contexts), int(m), dtype=torch.float64, device="cuda")
+        self.bind_be_step(U, U_new, cfl, m, hist)
+        self.run(stream)
+        return U_new, hist
 
     def run(self, stream=None):
         check(lib().cfv_ensemble_run(self._h, _stream(stream)))

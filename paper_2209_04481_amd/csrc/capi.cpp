@@ -15,6 +15,7 @@
 
 #include "cfv_kernels.hpp"
 #include "cfv_march.hpp"
+#include "cfv_step.hpp"
 
 namespace cfv {
 int reduce_partials_per_vector();
@@ -742,6 +743,15 @@ struct cfv_ensemble {
   hipGraphExec_t exec = nullptr;
   EventTimer timer;
   bool timing = false;
+  // backward-Euler step mode (cfv_ensemble_bind_be_step)
+  int mode = 0;                          // 0: residual / JVP, 1: backward-Euler step
+  cfv::MarchArgs* step_args = nullptr;   // (m + 1) x n: residual table, then one JVP table per Krylov vector
+  size_t step_args_n = 0;
+  cfv::StepVec* step_sv = nullptr;       // n
+  double* step_arena = nullptr;          // Krylov vectors, work vectors, diagonals, scalars
+  size_t step_arena_n = 0;
+  double* step_part = nullptr;           // n x kStepBlocks partial sums
+  cfv::StepLaunch step;
 };
 
 namespace {
@@ -791,10 +801,24 @@ unsigned ensemble_blocks(const cfv_ensemble* e) {
   return unsigned(b);
 }
 
+constexpr int kStepBlocks = 128;  // vector blocks per instance in the step's reductions
+
 cfv_status ensemble_launch(cfv_ensemble* e, hipStream_t s, bool timed) {
-  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, int(e->ctx.size()), e->total, e->tune.queue,
-                        ensemble_blocks(e)};
-  CFV_HIP(cfv::launch_march_ensemble(L, e->dual, s, timed && e->timing ? &e->timer : nullptr));
+  cfv::KernelTimer* t = timed && e->timing ? &e->timer : nullptr;
+  const int n = int(e->ctx.size());
+  if (e->mode == 1) {
+    cfv::StepLaunch& L = e->step;
+    L.res = cfv::EnsembleLaunch{e->step_args, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue,
+                                ensemble_blocks(e)};
+    for (int j = 0; j < L.m; ++j) {
+      L.jvp[size_t(j)] = L.res;
+      L.jvp[size_t(j)].args = e->step_args + size_t(1 + j) * n;
+    }
+    CFV_HIP(cfv::launch_ensemble_step(L, s, t));
+    return CFV_OK;
+  }
+  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue, ensemble_blocks(e)};
+  CFV_HIP(cfv::launch_march_ensemble(L, e->dual, s, t));
   return CFV_OK;
 }
 }  // namespace
@@ -845,7 +869,7 @@ cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning
 void cfv_ensemble_destroy(cfv_ensemble* e) {
   if (!e) return;
   drop_graph(e);
-  void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt};
+  void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt, e->step_args, e->step_sv, e->step_arena, e->step_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -885,7 +909,92 @@ cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const doub
   CFV_HIP(hipMemcpy(e->dargs, h.data(), n * sizeof(cfv::MarchArgs), hipMemcpyHostToDevice));
   e->dual = dual;
   e->bound = true;
+  e->mode = 0;
   drop_graph(e);
+  return CFV_OK;
+}
+
+cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, double* const* U_new, double cfl,
+                                     int32_t m, double* hist) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!U || !U_new) return fail(CFV_ERR_ARG, "null state arrays");
+  if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
+  if (m < 1 || m > 200) return fail(CFV_ERR_ARG, "need 1 <= m <= 200");
+  const size_t n = e->ctx.size();
+  for (size_t q = 0; q < n; ++q) {
+    if (!U[q] || !U_new[q]) return fail(CFV_ERR_ARG, "null pointer for instance " + std::to_string(q));
+    if (U[q] == U_new[q]) return fail(CFV_ERR_ARG, "U_new aliases U for instance " + std::to_string(q));
+  }
+  const cfv::StepLayout Y(m);
+  size_t need = 0;
+  for (size_t q = 0; q < n; ++q) {
+    const size_t nc = size_t(e->ctx[q]->grid->g.ncells);
+    need += size_t(m + 2) * 9 * nc + nc + size_t(Y.size);
+  }
+  drop_graph(e);
+  cfv_status st;
+  if (need > e->step_arena_n) {
+    if (e->step_arena) (void)hipFree(e->step_arena);
+    e->step_arena = nullptr;
+    e->step_arena_n = 0;
+    if ((st = dmalloc(&e->step_arena, need))) return st;
+    e->step_arena_n = need;
+  }
+  const size_t nargs = size_t(m + 1) * n;
+  if (nargs > e->step_args_n) {
+    if (e->step_args) (void)hipFree(e->step_args);
+    e->step_args = nullptr;
+    e->step_args_n = 0;
+    if ((st = dmalloc(&e->step_args, nargs))) return st;
+    e->step_args_n = nargs;
+  }
+  if (!e->step_sv && (st = dmalloc(&e->step_sv, n))) return st;
+  if (!e->step_part && (st = dmalloc(&e->step_part, n * kStepBlocks))) return st;
+  std::vector<cfv::StepVec> sv(n);
+  std::vector<cfv::MarchArgs> args(nargs);
+  cfv::StepLaunch& L = e->step;
+  L.n = int(n);
+  L.m = m;
+  L.blocks = kStepBlocks;
+  L.cfl = cfl;
+  L.sv = e->step_sv;
+  L.part = e->step_part;
+  L.hist = hist;
+  L.jvp.assign(size_t(m), cfv::EnsembleLaunch{});
+  L.dev.clear();
+  L.Uh.clear();
+  L.diagh.clear();
+  L.Wh.clear();
+  double* p = e->step_arena;
+  for (size_t q = 0; q < n; ++q) {
+    cfv_ctx* c = e->ctx[q];
+    const int64_t nc = c->grid->g.ncells, n9 = 9 * nc;
+    cfv::StepVec& v = sv[q];
+    v.U = U[q];
+    v.Unew = U_new[q];
+    v.V = p;
+    p += size_t(m + 1) * n9;
+    v.w = p;
+    p += n9;
+    double* diag = p;
+    p += nc;
+    v.diag = diag;
+    v.sm = p;
+    p += Y.size;
+    v.nc = nc;
+    const cfv::DevGrid d = c->dev();
+    args[q] = cfv::MarchArgs{d, U[q], nullptr, nullptr, c->W, nullptr, U_new[q], nullptr};
+    for (int j = 0; j < m; ++j)
+      args[size_t(1 + j) * n + q] = cfv::MarchArgs{d, U[q], v.V + size_t(j) * n9, nullptr, c->W, c->Wd, nullptr, v.w};
+    L.dev.push_back(d);
+    L.Uh.push_back(U[q]);
+    L.diagh.push_back(diag);
+    L.Wh.push_back(c->W);
+  }
+  CFV_HIP(hipMemcpy(e->step_sv, sv.data(), n * sizeof(cfv::StepVec), hipMemcpyHostToDevice));
+  CFV_HIP(hipMemcpy(e->step_args, args.data(), nargs * sizeof(cfv::MarchArgs), hipMemcpyHostToDevice));
+  e->mode = 1;
+  e->bound = true;
   return CFV_OK;
 }
 

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import coronal_inputs as ci
+from helpers import rel_err_per_var
 
 pytestmark = pytest.mark.gpu
 
@@ -146,3 +147,38 @@ def test_ensemble_64_instances_sampled(setup):
         j = ctxs[q].jvp(U[q], v[q], R=r)
         torch.cuda.synchronize()
         assert _same(R[q], r) and _same(J[q], j), f"instance {q} ({insts[q].N}, {insts[q].Nr})"
+
+
+def test_ensemble_be_step_matches_single_instance_steps(setup):
+    """One backward-Euler step (CFL 1e3, GMRES(12)) of every instance in
+    lockstep on the device equals cfv_be_step of each instance: the same
+    arithmetic except the order of the reductions and where the Givens
+    rotations are applied (device vs host)."""
+    from paper_2209_04481_amd import Ensemble, Tuning
+    ctxs, U, v, dbr, R1, J1, R0 = setup
+    print("case: ensemble backward-Euler step", flush=True)
+    ens = Ensemble(ctxs, Tuning(1, 2, 1))
+    Un, hist = ens.be_step(U, cfl=1e3, m=12)
+    torch.cuda.synchronize()
+    for q in range(len(U)):
+        Us, hs = ctxs[q].be_step(U[q], cfl=1e3, m=12)
+        hb = hist[q].cpu().numpy()
+        k = len(hs)
+        assert k >= 1
+        assert np.all(np.abs(hb[:k] - hs) <= 1e-9 * np.abs(hs) + 1e-300), f"history of instance {q} {SHAPES[q]}"
+        dx, dxs = (Un[q] - U[q]).cpu(), (Us - U[q]).cpu()
+        assert float(rel_err_per_var(dx, dxs).max()) <= 1e-8, f"step of instance {q} {SHAPES[q]}"
+    # captured: replays equal the eager run
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    ref = [u.clone() for u in Un]
+    href = hist.clone()
+    ens.capture(s)
+    for rep in range(2):
+        for u in Un:
+            u.fill_(float("nan"))
+        hist.zero_()
+        torch.cuda.synchronize()
+        ens.replay(s)
+        s.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(Un, ref)) and torch.equal(hist, href), f"replay {rep}"
