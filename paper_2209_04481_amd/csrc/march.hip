@@ -107,11 +107,12 @@ __device__ __forceinline__ int find_instance(const int64_t* __restrict__ off, in
 // Wavefronts per SIMD each pass is compiled for (register budget 512 / n per
 // lane; the LDS of n workgroups must fit in 160 KB).  Measured on the 13.3M-
 // cell shell: the residual passes run 25-30% faster at 2 than at 1 despite a
-// few hundred bytes of spills, and slower at 3 or 4; the JVP flux pass needs
-// 148 KB of LDS and stays at 1.
+// few hundred bytes of spills, and slower at 3 or 4; the JVP gradient pass
+// is 3% slower at 2 (456 bytes of spills) and the JVP flux pass needs 148 KB
+// of LDS, so both JVP passes stay at 1.
 template <class T, bool Flux>
 struct MarchOccupancy {
-  static constexpr int value = (Flux && sizeof(T) != sizeof(double)) ? 1 : 2;
+  static constexpr int value = sizeof(T) == sizeof(double) ? 2 : 1;
 };
 
 template <class T, bool Flux>

@@ -53,10 +53,12 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 
 // Pass 2 for cell c.  No local array is indexed by a run-time value (such
 // arrays would live in scratch memory): face loops either unroll or branch on
-// the face id before touching per-face arrays.
+// the face id before touching per-face arrays.  lq (stride st, an LDS column
+// per thread) keeps the primitives of the six face neighbours (or ghosts) that
+// the flux adjoints load, for the reconstruction adjoint that follows.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, double* __restrict__ A,
-                                             double* __restrict__ gbr, int64_t c) {
+                                             double* __restrict__ gbr, int64_t c, double* lq, int st) {
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
   decode(d.g, c, p, k, j, i);
@@ -71,25 +73,10 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const int64_t col = column_of(d.g, p, j, i);
   const double brc = d.br[col];
 
-  // ---- geometry, neighbour ids and ghost states
-  V3 dx[6], dxf[6];
-  int64_t nid[6];
+  // ---- ghost states, then per face: geometry once and the flux adjoint for
+  // this cell's side (and the ghost side); the face loop is unrolled so that
+  // per-face arrays are indexed statically and faces can overlap
   double qGin[9], qGout[9];
-#pragma unroll
-  for (int lf = 0; lf < 6; ++lf) {
-    const Nbr nb = neighbour(d.g, p, k, j, i, lf);
-    V3 S, xf;
-    bool own;
-    canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
-    dxf[lf] = xf - xc;
-    nid[lf] = nb.id;
-    V3 xn;
-    if (nb.id >= nc)
-      xn = ghost_centre(xc, S, xf);
-    else
-      xn = cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
-    dx[lf] = xn - xc;
-  }
   if (bin) {
     V3 xG;
     ghost_prims(d, p, k, j, i, 0, Pc, xc, brc, qGin, xG);
@@ -98,22 +85,27 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     V3 xG;
     ghost_prims(d, p, k, j, i, 1, Pc, xc, 0.0, qGout, xG);
   }
-  const LsqWeights Lw(dx);
-
-  // ---- flux adjoints of the six faces: own side (and the ghost side)
+  V3 dx[6], dxf[6];
   double Pb[9], Gb[27], PbGin[9], PbGout[9];
 #pragma unroll
   for (int v = 0; v < 9; ++v) Pb[v] = PbGin[v] = PbGout[v] = 0.0;
 #pragma unroll
   for (int v = 0; v < 27; ++v) Gb[v] = 0.0;
-#pragma unroll 1
+#pragma unroll
   for (int lf = 0; lf < 6; ++lf) {
     const Nbr nb = neighbour(d.g, p, k, j, i, lf);
     V3 S, xf;
     bool own;
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
     const V3 ds = xf - xc;
+    dxf[lf] = ds;
     const bool ghost = nb.id >= nc;
+    V3 xn;
+    if (ghost)
+      xn = ghost_centre(xc, S, xf);
+    else
+      xn = cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
+    dx[lf] = xn - xc;
     double qs[9], qo[9], wb[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v)
@@ -124,14 +116,17 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       for (int v = 0; v < 9; ++v) {
         qo[v] = lf == 0 ? qGin[v] : qGout[v];
         wb[v] = wc[v];  // the ghost carries no residual
+        lq[(9 * lf + v) * st] = qo[v];
       }
     } else {
       const int64_t o = nb.id;
-      const V3 dn = xf - cell_centre(d.G, d.g, nb.p, nb.k, nb.j, nb.i);
+      const V3 dn = xf - xn;
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        qo[v] = W[v * nc + o] + (W[(9 + 3 * v) * nc + o] * dn.x + W[(10 + 3 * v) * nc + o] * dn.y +
-                                 W[(11 + 3 * v) * nc + o] * dn.z);
+        const double Pn = W[v * nc + o];
+        lq[(9 * lf + v) * st] = Pn;
+        qo[v] = Pn + (W[(9 + 3 * v) * nc + o] * dn.x + W[(10 + 3 * v) * nc + o] * dn.y +
+                      W[(11 + 3 * v) * nc + o] * dn.z);
         const double wn = w[v * nc + o];
         wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
       }
@@ -157,6 +152,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       }
     }
   }
+  const LsqWeights Lw(dx);
 
   // ---- per variable: recompute the gradient and limiter choice, then their
   // adjoint; contributions to the six neighbours are stored at once
@@ -164,11 +160,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   for (int v = 0; v < 9; ++v) {
     double qn[6];
 #pragma unroll
-    for (int lf = 0; lf < 6; ++lf) {
-      if (lf == 0 && bin) qn[lf] = qGin[v];
-      else if (lf == 1 && bout) qn[lf] = qGout[v];
-      else qn[lf] = W[v * nc + nid[lf]];
-    }
+    for (int lf = 0; lf < 6; ++lf) qn[lf] = lq[(9 * lf + v) * st];
     const double qc = Pc[v];
     double gx = 0.0, gy = 0.0, gz = 0.0, qmax = qc, qmin = qc;
     int amax = -1, amin = -1;
@@ -284,9 +276,10 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, double* __restrict__ A,
                                                           double* __restrict__ gbr) {
+  __shared__ double lq[54 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c < d.g.ncells) adjoint_cell(d, w, W, A, gbr, c);
+  if (c < d.g.ncells) adjoint_cell(d, w, W, A, gbr, c, lq + threadIdx.x, kVBlock);
 }
 
 __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double* __restrict__ U,
