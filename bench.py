@@ -96,6 +96,45 @@ def cpu_baseline(inst, ncells_sample: int):
                       f"{dt:.1f} s"}
 
 
+def bench_solver(with_sensitivity: bool):
+    """The implicit step on the 1.66M-cell workload: one backward-Euler step
+    (CFL 1e3, GMRES(30), no restart) and, optionally, the 20-step B_r
+    sensitivity (CFL 0.05, tight solves, checkpoints every 5 steps)."""
+    import torch
+
+    import coronal_inputs as ci
+    from paper_2209_04481_amd import Context, Grid, Params
+
+    inst = ci.workload("medium")
+    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes), Params())
+    ctx.set_inner_br(torch.from_numpy(inst.br).cuda())
+    U = torch.from_numpy(inst.U).cuda()
+    out = torch.empty_like(U)
+    ctx.be_step(U, cfl=1e3, m=30, out=out)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, hist = ctx.be_step(U, cfl=1e3, m=30, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    res = {"workload": f"medium: 6x{inst.N}x{inst.N}x{inst.Nr} ({inst.ncells} cells)",
+           "be_step_ms": round(ms, 2), "gmres_iterations": int(len(hist)),
+           "ms_per_gmres_iteration": round(ms / max(len(hist), 1), 3), "final_relative_residual": float(hist[-1])}
+    print(f"[bench] backward-Euler step: {ms:.1f} ms", file=sys.stderr, flush=True)
+    if with_sensitivity:
+        from paper_2209_04481_amd.sensitivity import Sensitivity
+        br = torch.from_numpy(inst.br).cuda()
+        sens = Sensitivity(ctx, U, cfl=0.05, nsteps=20, every=5, max_restarts=16, layer=2)
+        t0 = time.perf_counter()
+        sens.gradient(br)
+        torch.cuda.synchronize()
+        res["sensitivity_s"] = round(time.perf_counter() - t0, 2)
+        res["sensitivity"] = "dL/dB_r after 20 steps (CFL 0.05, solves to 1e-12, checkpoints every 5)"
+        print(f"[bench] sensitivity: {res['sensitivity_s']} s", file=sys.stderr, flush=True)
+    return res
+
+
 def bench_ensemble(reps: int, solve_reps: int = 2):
     """64 uneven instances (29.95M cells): residual + JVP of all of them as one
     captured graph of two persistent launches, against 64 single-instance
@@ -207,6 +246,8 @@ def main():
                     help="also copy a 1 GiB buffer twice (reference dispatches for HBM counters)")
     ap.add_argument("--ensemble-reps", type=int, default=50)
     ap.add_argument("--solve-reps", type=int, default=2)
+    ap.add_argument("--no-solver", action="store_true")
+    ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 70 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -305,6 +346,8 @@ def main():
             for op, f in vrec["flop_per_cell"].items()}
         out["fp64_valu_note"] = (f"executed FP64 flops per cell from rocprofv3 counters ({vsrc}) over the measured "
                                  f"operation times; peak {FP64_PEAK_TFLOPS} TFLOP/s")
+    if not args.no_solver:
+        out["solver"] = bench_solver(args.sensitivity)
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
