@@ -23,7 +23,7 @@ hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* ou
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, hipStream_t s, KernelTimer* t);
+                      double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
 hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y, hipStream_t s);
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
@@ -398,7 +398,7 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
 cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
-  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, s, c->tm()));
   return CFV_OK;
 }
 
@@ -454,7 +454,7 @@ static cfv_status ensure_krylov(cfv_ctx* c, int m) {
 static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag, int transpose, const double* x,
                                  double* w, hipStream_t s) {
   if (transpose) {
-    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, s, c->tm()));
+    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
     CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
@@ -635,10 +635,10 @@ cfv_status cfv_vjp_dir(cfv_ctx* c, const double* U, const double* w, const doubl
   // + side into the outputs, - side into the workspace
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, s, c->tm()));
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, s, c->tm()));
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, gU2, s));
   if (gbr2) CFV_HIP(cfv::launch_axpby(nb, -ih, gbm, ih, gbr2, s));

@@ -18,6 +18,7 @@ struct MarchArgs {
   double* Gd;         // their tangents (Dual only)
   double* R;          // residual (nullable for Dual)
   double* Rd;         // tangent of the residual (Dual only)
+  double* P = nullptr;  // primitives [9][ncells] written by the gradient pass (nullable)
 };
 
 struct TileMap {
@@ -175,6 +176,10 @@ struct GradWG {
     T* L = lds_as<T>(lds);
     const int me = plane_pos(ti, tj);
     for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
+    if (a.P) {
+      const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+      for (int v = 0; v < 9; ++v) a.P[v * g.ncells + c] = val(st.P0[v]);
+    }
     for (int q = 0; q < 4; ++q) {
       if (!(st.remote & (1u << q))) continue;
       int dx, dy;
@@ -474,6 +479,9 @@ struct FluxWG {
 // One instance; slot: device memory for one descriptor, owned by the caller
 // (calls sharing a slot must be ordered on one stream).
 hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t);
+// The gradient pass alone (double): limited gradients into a.G and, when
+// a.P is set, the primitives into a.P.
+hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, hipStream_t s, KernelTimer* t);
 
 // Ensemble launch: n instances described by args[n] (device), with
 // item_off[n + 1] (device) the prefix sums of march_logical_blocks per

@@ -182,4 +182,13 @@ hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStrea
   return hipGetLastError();
 }
 
+hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, hipStream_t s, KernelTimer* t) {
+  hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
+  const int64_t total = march_logical_blocks(a.d.g);
+  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
+  TimedScope ts(t, "grad_march_fwd", s);
+  hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  return hipGetLastError();
+}
+
 }  // namespace cfv

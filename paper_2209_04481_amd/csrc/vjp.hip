@@ -18,6 +18,7 @@
 //           gravity source adjoint.
 #include "cfv_adjoint.hpp"
 #include "cfv_kernels.hpp"
+#include "cfv_march.hpp"
 
 namespace cfv {
 
@@ -290,10 +291,13 @@ __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double
 }
 
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, hipStream_t s, KernelTimer* t) {
+                      double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
-  hipError_t e = launch_grad_limit_forward(d, U, W, s, t);
+  // pass 1: the forward gradient march writes the primitives (rows 0..8) and
+  // the limited gradients (rows 9..35) of W
+  MarchArgs fa{d, U, nullptr, nullptr, W + 9 * nc, nullptr, nullptr, nullptr, W};
+  hipError_t e = launch_march_grad(fa, slot, s, t);
   if (e != hipSuccess) return e;
   {
     TimedScope ts(t, "adjoint", s);
