@@ -54,22 +54,35 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 
 // Pass 2 for cell c.  No local array is indexed by a run-time value (such
 // arrays would live in scratch memory): face loops either unroll or branch on
-// the face id before touching per-face arrays.  lq (stride st, an LDS column
-// per thread) keeps the primitives of the six face neighbours (or ghosts) that
-// the flux adjoints load, for the reconstruction adjoint that follows.
+// the face id before touching per-face arrays.  The workgroup's 256
+// consecutive cells [c0, c0 + 256) have their workspace rows and weights in
+// LDS (lW, lw); neighbours inside that window are read from there (nearly
+// all of the i +- 1 and most of the j +- 1 neighbours), the others from
+// global memory.  Most of this pass's time is neighbour loads at one
+// wavefront per SIMD.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, double* __restrict__ A,
-                                             double* __restrict__ gbr, int64_t c, double* lq, int st) {
+                                             double* __restrict__ gbr, int64_t c, const double* lW,
+                                             const double* lw, int64_t c0) {
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
   decode(d.g, c, p, k, j, i);
   const bool bin = k == 0, bout = k == d.g.Nr - 1;
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
+  // rows of cells in the workgroup's window [c0, c0 + kVBlock) come from LDS
+  auto Wr = [&](int row, int64_t id) -> double {
+    const int64_t l = id - c0;
+    return (l >= 0 && l < kVBlock) ? lW[row * kVBlock + l] : W[row * nc + id];
+  };
+  auto wr = [&](int row, int64_t id) -> double {
+    const int64_t l = id - c0;
+    return (l >= 0 && l < kVBlock) ? lw[row * kVBlock + l] : w[row * nc + id];
+  };
   double Pc[9], wc[9];
 #pragma unroll
   for (int v = 0; v < 9; ++v) {
-    Pc[v] = W[v * nc + c];
-    wc[v] = w[v * nc + c];
+    Pc[v] = Wr(v, c);
+    wc[v] = wr(v, c);
   }
   const int64_t col = column_of(d.g, p, j, i);
   const double brc = d.br[col];
@@ -87,6 +100,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     ghost_prims(d, p, k, j, i, 1, Pc, xc, 0.0, qGout, xG);
   }
   V3 dx[6], dxf[6];
+  int64_t nid[6];
   double Pb[9], Gb[27], PbGin[9], PbGout[9];
 #pragma unroll
   for (int v = 0; v < 9; ++v) Pb[v] = PbGin[v] = PbGout[v] = 0.0;
@@ -100,6 +114,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     canon_face(d.G, d.g, p, k, j, i, lf, nb, c, S, xf, own);
     const V3 ds = xf - xc;
     dxf[lf] = ds;
+    nid[lf] = nb.id;
     const bool ghost = nb.id >= nc;
     V3 xn;
     if (ghost)
@@ -110,25 +125,20 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     double qs[9], qo[9], wb[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v)
-      qs[v] = Pc[v] + (W[(9 + 3 * v) * nc + c] * ds.x + W[(10 + 3 * v) * nc + c] * ds.y +
-                       W[(11 + 3 * v) * nc + c] * ds.z);
+      qs[v] = Pc[v] + (Wr(9 + 3 * v, c) * ds.x + Wr(10 + 3 * v, c) * ds.y + Wr(11 + 3 * v, c) * ds.z);
     if (ghost) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
         qo[v] = lf == 0 ? qGin[v] : qGout[v];
         wb[v] = wc[v];  // the ghost carries no residual
-        lq[(9 * lf + v) * st] = qo[v];
       }
     } else {
       const int64_t o = nb.id;
       const V3 dn = xf - xn;
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        const double Pn = W[v * nc + o];
-        lq[(9 * lf + v) * st] = Pn;
-        qo[v] = Pn + (W[(9 + 3 * v) * nc + o] * dn.x + W[(10 + 3 * v) * nc + o] * dn.y +
-                      W[(11 + 3 * v) * nc + o] * dn.z);
-        const double wn = w[v * nc + o];
+        qo[v] = Wr(v, o) + (Wr(9 + 3 * v, o) * dn.x + Wr(10 + 3 * v, o) * dn.y + Wr(11 + 3 * v, o) * dn.z);
+        const double wn = wr(v, o);
         wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
       }
     }
@@ -161,7 +171,11 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   for (int v = 0; v < 9; ++v) {
     double qn[6];
 #pragma unroll
-    for (int lf = 0; lf < 6; ++lf) qn[lf] = lq[(9 * lf + v) * st];
+    for (int lf = 0; lf < 6; ++lf) {
+      if (lf == 0 && bin) qn[lf] = qGin[v];
+      else if (lf == 1 && bout) qn[lf] = qGout[v];
+      else qn[lf] = Wr(v, nid[lf]);
+    }
     const double qc = Pc[v];
     double gx = 0.0, gy = 0.0, gz = 0.0, qmax = qc, qmin = qc;
     int amax = -1, amin = -1;
@@ -277,10 +291,18 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, double* __restrict__ A,
                                                           double* __restrict__ gbr) {
-  __shared__ double lq[54 * kVBlock];
+  __shared__ double lW[36 * kVBlock];
+  __shared__ double lw[9 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c < d.g.ncells) adjoint_cell(d, w, W, A, gbr, c, lq + threadIdx.x, kVBlock);
+  const int64_t nc = d.g.ncells;
+  const int64_t c0 = int64_t(blockIdx.x) * kVBlock, c = c0 + threadIdx.x;
+  if (c < nc) {
+    for (int r = 0; r < 36; ++r) lW[r * kVBlock + threadIdx.x] = W[r * nc + c];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = w[r * nc + c];
+  }
+  __syncthreads();
+  if (c < nc) adjoint_cell(d, w, W, A, gbr, c, lW, lw, c0);
 }
 
 __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double* __restrict__ U,
