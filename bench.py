@@ -250,7 +250,7 @@ def main():
     ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 70 s)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
