@@ -222,6 +222,22 @@ def br_map(N: int, lmax: int, seed: int, peak_gauss: float = 5.0) -> np.ndarray:
     return br_dip + 0.5 * (lo + hi) * h
 
 
+def btheta_map(N: int) -> np.ndarray:
+    """Inner-boundary B_theta of the dipole at the same directions as br_map,
+    order (p, j, i), nondimensional: the B_theta a potential-field model gives
+    for a dipole source.  theta-hat = (x z/(rho r), y z/(rho r), -rho/r) with
+    rho = sqrt(x^2 + y^2); on the polar axis its phi = 0 limit,
+    (cos theta, 0, -sin theta)."""
+    d = nominal_directions(N).reshape(-1, 3)
+    B = dipole_field(d)
+    rho = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2)
+    axis = rho <= 1e-12
+    rs = np.where(axis, 1.0, rho)
+    th = np.stack([d[:, 0] * d[:, 2] / rs, d[:, 1] * d[:, 2] / rs, -rho], axis=-1)
+    th[axis] = np.stack([d[axis, 2], np.zeros(int(axis.sum())), np.zeros(int(axis.sum()))], axis=-1)
+    return np.sum(B * th, axis=-1)
+
+
 def primitive_state(N: int, Nr: int, r_nodes: np.ndarray, seed: int,
                     noise: float = 0.01) -> np.ndarray:
     """(9, ncells) primitives [rho, v(3), B(3), p, psi] of the noisy wind."""

@@ -13,6 +13,10 @@ What is computed (paper Section 2.1 and Eqs. 14-17, Sections 3.2 and 4.1):
   magnetogram, B_theta and B_phi Neumann, the boundary velocity parallel to
   the boundary field so that V_b x B_b = 0, with radial part V_r* B_r^2/|B|^2
   (V_r* of Eq. 22), rho and p Dirichlet, psi_b = 0 (Section 3.3).
+* Inner boundary "large E" (Section 3.2, Eqs. 20-24, the Wind-Predict law,
+  selected by inner_mode = 1): B_r and B_theta Dirichlet (the magnetogram
+  and an imposed B_theta map, which a potential-field model supplies),
+  B_phi Neumann, V = V_par (B_r, B_theta, 0) with V_par = V_r* B_r / B_pol^2.
 * Outer boundary: Table 2 ghost laws in r and rho, per variable exponents.
 * Second-order reconstruction: unweighted least squares gradient over the six
   face neighbours (ghosts at mirrored centres), optional Barth-Jespersen
@@ -67,6 +71,10 @@ class Params:
     outer_exp: tuple = (2.5, 2.0, 0.0, 1.0, 0.0, 0.0, 1.0, 2.5)
     outer_vr_mass: bool = True
     outer_psi_zero: bool = True
+    # inner boundary: 0 low-E (Eq. 25), 1 large-E (Eqs. 20-24) with the
+    # imposed B_theta map inner_btheta (6 N^2, order (p, j, i))
+    inner_mode: int = 0
+    inner_btheta: torch.Tensor | None = None
 
     @staticmethod
     def table2(case: int, **kw) -> "Params":
@@ -187,6 +195,31 @@ def inner_ghost(PI, xf, br, prm: Params):
     Bb = br[..., None] * rhat + Bth[..., None] * that + Bph[..., None] * phat
     Bb2 = dot(Bb, Bb)
     Vb = (prm.vr_star * br / torch.where(Bb2 > 1e-30, Bb2, torch.full_like(Bb2, 1e-30)))[..., None] * Bb
+    rho = 2.0 * prm.rho_b - PI[..., 0]
+    v = 2.0 * Vb - PI[..., 1:4]
+    Bg = 2.0 * Bb - B
+    p = 2.0 * prm.rho_b * prm.T_b - PI[..., 7]
+    psi = -PI[..., 8]
+    return torch.cat([rho[..., None], v, Bg, p[..., None], psi[..., None]], dim=-1)
+
+
+def inner_ghost_large_e(PI, xf, br, bth, prm: Params):
+    """Large-E inner ghost state (Section 3.2, Eqs. 20-24: the Wind-Predict
+    boundary).
+
+    B_r takes the map value and B_theta the imposed value (Dirichlet: face
+    average), B_phi keeps the interior value (Neumann).  The velocity removes
+    the poloidal flux: with B_pol^2 = B_r^2 + B_theta^2 and
+    V_par = V_r* B_r / B_pol^2, V_r = V_par B_r, V_theta = V_par B_theta,
+    V_phi = 0 (Dirichlet).  rho, p and psi as in the low-E law.
+    """
+    rhat, that, phat = spherical_basis(xf)
+    B = PI[..., 4:7]
+    Bph = dot(B, phat)
+    Bb = br[..., None] * rhat + bth[..., None] * that + Bph[..., None] * phat
+    Bpol2 = br * br + bth * bth
+    Vpar = prm.vr_star * br / torch.where(Bpol2 > 1e-30, Bpol2, torch.full_like(Bpol2, 1e-30))
+    Vb = (Vpar * br)[..., None] * rhat + (Vpar * bth)[..., None] * that
     rho = 2.0 * prm.rho_b - PI[..., 0]
     v = 2.0 * Vb - PI[..., 1:4]
     Bg = 2.0 * Bb - B
@@ -344,7 +377,12 @@ def face_states(grid: Grid, U: torch.Tensor, br: torch.Tensor, prm: Params,
     inner = ~st.gouter
     PG = torch.zeros(st.ghosts.numel(), 9, dtype=U.dtype)
     if bool(inner.any()):
-        PG = PG.index_put((ar[inner],), inner_ghost(PI[inner], xfb[inner], br[st.gcol[inner]], prm))
+        if prm.inner_mode == 1:
+            bth = torch.as_tensor(prm.inner_btheta, dtype=U.dtype)
+            PGi = inner_ghost_large_e(PI[inner], xfb[inner], br[st.gcol[inner]], bth[st.gcol[inner]], prm)
+        else:
+            PGi = inner_ghost(PI[inner], xfb[inner], br[st.gcol[inner]], prm)
+        PG = PG.index_put((ar[inner],), PGi)
     if bool(st.gouter.any()):
         PG = PG.index_put((ar[st.gouter],), outer_ghost(PI[st.gouter], st.xc[lI[st.gouter]],
                                                         st.xg[st.gouter], xfb[st.gouter], prm))

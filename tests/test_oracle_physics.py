@@ -9,6 +9,7 @@ import torch
 from conftest import read_golden
 from oracle import constants as K
 from oracle import mhd
+import coronal_inputs as ci
 
 DT = torch.float64
 
@@ -195,6 +196,75 @@ def test_inner_low_e_ghost_eq25_and_dirichlet_laws():
     assert torch.allclose(0.5 * (PG[:, 0] + PI[:, 0]), torch.full((80,), prm.rho_b, dtype=DT), rtol=1e-15)
     assert torch.allclose(0.5 * (PG[:, 7] + PI[:, 7]), torch.full((80,), prm.rho_b * prm.T_b, dtype=DT), rtol=1e-14)
     assert torch.equal(PG[:, 8], -PI[:, 8])
+
+
+def test_inner_large_e_ghost_removes_poloidal_flux():
+    """Large-E law (Eqs. 20-24), checked through properties of the face
+    average: B_r and B_theta take the imposed values, B_phi is Neumann, the
+    velocity lies along the poloidal field (B_r, B_theta) with no azimuthal
+    part and radial part V_r* B_r^2/B_pol^2, so its electric field V x B_b is
+    -V_par B_phi (B_r theta-hat - B_theta r-hat) and vanishes only without
+    B_phi; rho, p and psi as the low-E law."""
+    prm = mhd.Params()
+    xf, g = boundary_face_sample(80, 5)
+    PI = random_prims(80, 14)
+    br = torch.randn(80, dtype=DT, generator=g)
+    bth = torch.randn(80, dtype=DT, generator=g)
+    PG = mhd.inner_ghost_large_e(PI, xf, br, bth, prm)
+    Vb = 0.5 * (PG[:, 1:4] + PI[:, 1:4])
+    Bb = 0.5 * (PG[:, 4:7] + PI[:, 4:7])
+    rh, th, ph = mhd.spherical_basis(xf)
+    comp = lambda a, b: (a * b).sum(-1)
+    tol = lambda x: 1e-13 * (x.abs() + PI[:, 1:7].norm(dim=-1))
+    assert bool(((comp(Bb, rh) - br).abs() <= tol(br)).all())
+    assert bool(((comp(Bb, th) - bth).abs() <= tol(bth)).all())
+    assert bool(((comp(PG[:, 4:7], ph) - comp(PI[:, 4:7], ph)).abs() <= tol(comp(PI[:, 4:7], ph))).all())
+    vphi = comp(Vb, ph)
+    assert float(vphi.abs().max()) <= 1e-13 * float(PI[:, 1:4].abs().max())
+    # along the poloidal field: V_r B_theta - V_theta B_r = 0
+    vr, vt = comp(Vb, rh), comp(Vb, th)
+    assert bool(((vr * bth - vt * br).abs() <= 1e-13 * (vr.abs() + vt.abs() + PI[:, 1:4].norm(dim=-1))
+                 * (br.abs() + bth.abs())).all())
+    pol2 = br ** 2 + bth ** 2
+    assert bool(((vr - prm.vr_star * br ** 2 / pol2).abs() <= tol(vr)).all())
+    assert bool((vr >= -1e-15).all())
+    # the boundary electric field comes from B_phi alone
+    E = torch.linalg.cross(Vb, Bb)
+    vpar = prm.vr_star * br / pol2
+    E_expect = -(vpar * comp(Bb, ph))[:, None] * (br[:, None] * th - bth[:, None] * rh)
+    # (the face average carries the rounding of 2 V_b - V_I, relative to |V_I|)
+    scale = (Vb.norm(dim=-1) + PI[:, 1:4].norm(dim=-1)) * Bb.norm(dim=-1)
+    assert bool(((E - E_expect).norm(dim=-1) <= 1e-14 * scale).all())
+    assert torch.allclose(0.5 * (PG[:, 0] + PI[:, 0]), torch.full((80,), prm.rho_b, dtype=DT), rtol=1e-15)
+    assert torch.allclose(0.5 * (PG[:, 7] + PI[:, 7]), torch.full((80,), prm.rho_b * prm.T_b, dtype=DT), rtol=1e-14)
+    assert torch.equal(PG[:, 8], -PI[:, 8])
+
+
+def test_large_e_equals_low_e_without_azimuthal_field():
+    """With no interior B_phi and the imposed B_theta equal to the interior
+    one, the boundary field is poloidal, so the large-E velocity (along the
+    poloidal field) and the low-E velocity (along B_b) coincide."""
+    prm = mhd.Params()
+    xf, g = boundary_face_sample(60, 8)
+    PI = random_prims(60, 15)
+    rh, th, ph = mhd.spherical_basis(xf)
+    B = PI[:, 4:7]
+    PI[:, 4:7] = B - (B * ph).sum(-1, keepdim=True) * ph
+    br = torch.randn(60, dtype=DT, generator=g)
+    bth = (PI[:, 4:7] * th).sum(-1)
+    a = mhd.inner_ghost_large_e(PI, xf, br, bth, prm)
+    b = mhd.inner_ghost(PI, xf, br, prm)
+    assert float(((a - b).abs() / (b.abs() + 1e-12)).max()) < 1e-12
+
+
+def test_btheta_map_is_the_dipole_polar_component():
+    """The B_theta input of the large-E boundary for the dipole: B_eq sin(theta)
+    at r = 1 (standard dipole, B_r = 2 B_eq cos(theta))."""
+    for N in (4, 5):
+        d = ci.nominal_directions(N).reshape(-1, 3)
+        th = np.arccos(np.clip(d[:, 2], -1, 1))
+        assert np.allclose(ci.btheta_map(N), ci.GAUSS * np.sin(th), rtol=1e-12, atol=1e-15)
+        assert np.allclose(ci.br_map(N, 0, 0), 2 * ci.GAUSS * np.cos(th), rtol=1e-12, atol=1e-15)
 
 
 @pytest.mark.parametrize("case", range(1, 10))

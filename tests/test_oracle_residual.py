@@ -43,13 +43,15 @@ def test_free_stream_preservation():
         assert float(R[:, inner].abs().max()) < 1e-13 * scale
 
 
-def test_discrete_conservation_telescopes_to_boundary_fluxes():
+@pytest.mark.parametrize("inner_mode", [0, 1])
+def test_discrete_conservation_telescopes_to_boundary_fluxes(inner_mode):
     """Without gravity, sum over all cells of R equals the sum of the
-    boundary-face fluxes: interior fluxes cancel pairwise."""
+    boundary-face fluxes: interior fluxes cancel pairwise (low-E and large-E
+    inner boundaries)."""
     inst = ci.make_instance(4, 6, "log", lmax=0, seed=5)
     g = Grid(inst.N, inst.Nr, inst.r_nodes)
     U, br = torch.tensor(inst.U), torch.tensor(inst.br)
-    prm = mhd.Params(G=0.0)
+    prm = mhd.Params(G=0.0, inner_mode=inner_mode, inner_btheta=torch.tensor(ci.btheta_map(inst.N)))
     R = mhd.residual(g, U, br, prm)
     st = mhd._Stencil(g, torch.arange(g.ncells))
     fs = mhd.face_states(g, U, br, prm, torch.arange(g.ncells), st)
