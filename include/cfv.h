@@ -62,7 +62,10 @@ typedef struct {
   double rho_b;      /* inner boundary density */
   double T_b;        /* inner boundary temperature as p/rho */
   int32_t limiter;   /* 0: none, 1: Barth-Jespersen */
-  int32_t inner_mode;/* 0: low-E inner boundary (Section 3.2, Eq. 25) */
+  int32_t inner_mode;/* 0: low-E inner boundary (Section 3.2, Eq. 25);
+                        1: large-E (Wind-Predict) boundary (Section 3.2,
+                        Eqs. 20-24), with the B_theta map of
+                        cfv_set_inner_btheta */
   double outer_exp[8]; /* outer ghost powers e in G = I (r_I/r_G)^e for
                           rho, B_r, B_theta, B_phi, V_r, V_theta, V_phi, p (Table 2) */
   int32_t outer_vr_mass;  /* 1: V_r r^2 rho = const instead of outer_exp[4] */
@@ -94,6 +97,13 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
 void cfv_ctx_destroy(cfv_ctx* ctx);
 /* Copy the inner-boundary B_r map (device array of n = 6N^2 values). */
 cfv_status cfv_set_inner_br(cfv_ctx* ctx, const double* br_dev, int64_t n, hipStream_t s);
+
+/* Copy the inner-boundary B_theta map (device array of n = 6N^2 values, the
+ * order of the B_r map) used by the large-E law (inner_mode = 1): the
+ * Dirichlet value of B_theta on each inner face, which a potential-field
+ * model supplies (Eq. 21).  Zero until set; a constant of the operator (no
+ * derivative is taken with respect to it). */
+cfv_status cfv_set_inner_btheta(cfv_ctx* ctx, const double* bth_dev, int64_t n, hipStream_t s);
 
 /* Geometry as the kernels see it (device outputs): cell centroids xc[3c+d],
  * volumes vol[c], and per (cell, local face) the face centroid xf[(6c+f)*3+d]

@@ -54,6 +54,7 @@ def lib():
         "cfv_ctx_create": ([P, ctypes.POINTER(CfvParams), ctypes.POINTER(P)], c_int32),
         "cfv_ctx_destroy": ([P], None),
         "cfv_set_inner_br": ([P, P, c_int64, P], c_int32),
+        "cfv_set_inner_btheta": ([P, P, c_int64, P], c_int32),
         "cfv_geometry": ([P, P, P, P, P, P], c_int32),
         "cfv_residual": ([P, P, P, P], c_int32),
         "cfv_jvp": ([P, P, P, P, P, P, P], c_int32),
@@ -201,6 +202,10 @@ class Context:
     # ---- entry points
     def set_inner_br(self, br, stream=None):
         check(lib().cfv_set_inner_br(self._h, _ptr(br), br.numel(), _stream(stream)))
+
+    def set_inner_btheta(self, bth, stream=None):
+        """B_theta map of the large-E inner boundary (inner_mode = 1)."""
+        check(lib().cfv_set_inner_btheta(self._h, _ptr(bth), bth.numel(), _stream(stream)))
 
     def geometry(self, stream=None):
         nc = self.grid.ncells

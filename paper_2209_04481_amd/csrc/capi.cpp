@@ -101,6 +101,7 @@ struct cfv_ctx {
   int32_t* dcn = nullptr;
   double* dr = nullptr;
   double* dbr = nullptr;
+  double* dbth = nullptr;  // inner B_theta map (large-E law), zero until set
   double* W = nullptr;     // 36 ncells: primitives + limited gradients
   double* Wd = nullptr;    // 36 ncells: their tangents
   double* A = nullptr;     // adjoint workspace
@@ -129,6 +130,7 @@ struct cfv_ctx {
     d.G.ncol = grid->g.nb;
     d.pr = pr;
     d.br = dbr;
+    d.bth = dbth;
     return d;
   }
 };
@@ -308,7 +310,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (!(prm->gamma > 1.0) || !(prm->c_h > 0.0) || prm->G < 0.0 || !(prm->rho_b > 0.0) || !(prm->T_b > 0.0))
     return fail(CFV_ERR_ARG, "need gamma > 1, c_h > 0, G >= 0, rho_b > 0, T_b > 0");
   if (prm->limiter != 0 && prm->limiter != 1) return fail(CFV_ERR_ARG, "limiter must be 0 or 1");
-  if (prm->inner_mode != 0) return fail(CFV_ERR_ARG, "inner_mode: only the low-E boundary (0) is provided");
+  if (prm->inner_mode != 0 && prm->inner_mode != 1)
+    return fail(CFV_ERR_ARG, "inner_mode must be 0 (low-E) or 1 (large-E)");
   cfv_ctx* c = new (std::nothrow) cfv_ctx;
   if (!c) return fail(CFV_ERR_ALLOC, "host allocation");
   c->grid = g;
@@ -329,7 +332,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   c->part_vectors = 32;
   if ((st = dmalloc(&c->dcg, g->cg.size())) || (st = dmalloc(&c->dcn, g->cn.size())) ||
       (st = dmalloc(&c->dr, g->r.size())) ||
-      (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->W, size_t(36) * nc)) ||
+      (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->dbth, size_t(g->g.nb))) ||
+      (st = dmalloc(&c->W, size_t(36) * nc)) ||
       (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
       (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector())) ||
@@ -341,6 +345,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (e == hipSuccess) e = hipMemcpy(c->dcn, g->cn.data(), g->cn.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dr, g->r.data(), g->r.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->dbr, 0, size_t(g->g.nb) * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->dbth, 0, size_t(g->g.nb) * sizeof(double));
   if (e != hipSuccess) {
     cfv_ctx_destroy(c);
     return hip_fail(e, "uploading grid tables");
@@ -351,7 +356,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
 
 void cfv_ctx_destroy(cfv_ctx* c) {
   if (!c) return;
-  double* bufs[] = {c->dcg, c->dr, c->dbr, c->W, c->Wd, c->A, c->part};
+  double* bufs[] = {c->dcg, c->dr, c->dbr, c->dbth, c->W, c->Wd, c->A, c->part};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->dcn) (void)hipFree(c->dcn);
@@ -368,6 +373,14 @@ cfv_status cfv_set_inner_br(cfv_ctx* c, const double* br, int64_t n, hipStream_t
   if (!br) return fail(CFV_ERR_ARG, "null B_r map");
   if (n != c->grid->g.nb) return fail(CFV_ERR_SIZE, "B_r map length must be 6 N^2");
   CFV_HIP(hipMemcpyAsync(c->dbr, br, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_set_inner_btheta(cfv_ctx* c, const double* bth, int64_t n, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!bth) return fail(CFV_ERR_ARG, "null B_theta map");
+  if (n != c->grid->g.nb) return fail(CFV_ERR_SIZE, "B_theta map length must be 6 N^2");
+  CFV_HIP(hipMemcpyAsync(c->dbth, bth, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   return CFV_OK;
 }
 

@@ -14,6 +14,7 @@ struct DevGrid {
   GeomRef G;
   Params pr;
   const double* br;  // inner-boundary B_r map, 6N^2, order (p, j, i)
+  const double* bth = nullptr;  // inner-boundary B_theta map (large-E law), same order
 };
 
 // The first kernel argument read in place from the kernel-argument segment:
@@ -43,10 +44,14 @@ __host__ __device__ __forceinline__ void ghost_prims(const DevGrid& d, int p, in
   V3 S, xf;
   face_geom(d.G, d.g, p, k, j, i, lf, S, xf);
   xG = ghost_centre(xI, S, xf);
-  if (lf == 0)
-    inner_ghost(qI, xf, br, qG, d.pr);
-  else
+  if (lf == 0) {
+    if (d.pr.inner_mode == 1)
+      inner_ghost_large_e(qI, xf, br, d.bth[column_of(d.g, p, j, i)], qG, d.pr);
+    else
+      inner_ghost(qI, xf, br, qG, d.pr);
+  } else {
     outer_ghost(qI, xI, xG, xf, qG, d.pr);
+  }
 }
 
 // Optional per-launch timer: brackets each kernel launch with events on the

@@ -224,6 +224,33 @@ __host__ __device__ __forceinline__ void inner_ghost(const T qI[9], V3 xf, T br,
   qG[8] = -qI[8];
 }
 
+// Inner large-E ghost (Section 3.2, Eqs. 20-24): B_r and B_theta imposed
+// (Dirichlet), B_phi Neumann; the velocity V_par (B_r, B_theta, 0) with
+// V_par = V_r* B_r / (B_r^2 + B_theta^2); rho, p, psi as the low-E law.
+template <class T>
+__host__ __device__ __forceinline__ void inner_ghost_large_e(const T qI[9], V3 xf, T br, double bth, T qG[9],
+                                                             const Params& pr) {
+  V3 rh, th, ph;
+  sph_basis(xf, rh, th, ph);
+  const T bph = qI[4] * ph.x + qI[5] * ph.y + qI[6] * ph.z;
+  const T bbx = br * rh.x + bth * th.x + bph * ph.x;
+  const T bby = br * rh.y + bth * th.y + bph * ph.y;
+  const T bbz = br * rh.z + bth * th.z + bph * ph.z;
+  T pol2 = br * br + bth * bth;
+  if (val(pol2) <= 1e-30) pol2 = T(1e-30);
+  const T vpar = pr.vr_star * br / pol2;
+  const T vr = vpar * br, vt = vpar * bth;
+  qG[0] = 2.0 * pr.rho_b - qI[0];
+  qG[1] = 2.0 * (vr * rh.x + vt * th.x) - qI[1];
+  qG[2] = 2.0 * (vr * rh.y + vt * th.y) - qI[2];
+  qG[3] = 2.0 * (vr * rh.z + vt * th.z) - qI[3];
+  qG[4] = 2.0 * bbx - qI[4];
+  qG[5] = 2.0 * bby - qI[5];
+  qG[6] = 2.0 * bbz - qI[6];
+  qG[7] = 2.0 * (pr.rho_b * pr.T_b) - qI[7];
+  qG[8] = -qI[8];
+}
+
 // Outer ghost: Table 2 laws G = I (r_I/r_G)^e in spherical components at the
 // face centroid, V_r by V_r r^2 rho = const when selected, psi_b = 0 or G = I.
 template <class T>

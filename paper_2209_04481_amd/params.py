@@ -43,7 +43,7 @@ class Params:
     rho_b: float = 1.0
     T_b: float = _KB_OVER_MP * 1.5e6 / (0.6 * _V_REF ** 2)
     limiter: int = 1
-    inner_mode: int = 0
+    inner_mode: int = 0      # 0: low-E inner boundary; 1: large-E (needs Context.set_inner_btheta)
     outer_exp: tuple = (2.5, 2.0, 0.0, 1.0, 0.0, 0.0, 1.0, 2.5)
     outer_vr_mass: bool = True
     outer_psi_zero: bool = True

@@ -31,7 +31,7 @@ def lib_params(op):
     from paper_2209_04481_amd import Params
     return Params(gamma=op.gamma, c_h=op.c_h, G=op.G, vr_star=op.vr_star, rho_b=op.rho_b, T_b=op.T_b,
                   limiter=op.limiter, outer_exp=tuple(op.outer_exp), outer_vr_mass=op.outer_vr_mass,
-                  outer_psi_zero=op.outer_psi_zero)
+                  outer_psi_zero=op.outer_psi_zero, inner_mode=op.inner_mode)
 
 
 class Case:
@@ -46,6 +46,8 @@ class Case:
         self.ctx = Context(self.grid, lib_params(self.op))
         self.Ud = self.U.cuda()
         self.ctx.set_inner_br(self.br.cuda())
+        if self.op.inner_mode == 1:
+            self.ctx.set_inner_btheta(torch.as_tensor(self.op.inner_btheta).cuda())
 
 
 def small_inst(seed=3):
@@ -164,6 +166,30 @@ def test_parity_other_parameters(name):
     gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w)
     for a, b in ((R, Ro), (Jv, Jo), (gU.cpu(), gUo), (gbr.cpu()[None], gbro[None])):
         assert float(rel_err_per_var(a, b).max()) <= TOL
+
+
+@pytest.mark.parametrize("N,Nr,lmax", [(6, 10, 0), (7, 9, 4), (5, 1, 2)])
+def test_parity_large_e_inner_boundary(N, Nr, lmax):
+    """The large-E inner boundary (Eqs. 20-24) with the dipole's B_theta:
+    residual, JVP with a B_r direction, VJP and B_r gradient (pure dipole,
+    a map with harmonics, odd N with polar-axis faces, one layer)."""
+    print(f"case: large-E N={N} Nr={Nr} lmax={lmax}", flush=True)
+    inst = ci.make_instance(N, Nr, "log", lmax=lmax, seed=60 + N)
+    inst.U[8] = 1e-3 * np.random.default_rng(N).standard_normal(inst.ncells)   # psi != 0
+    c = Case(inst, mhd.Params(inner_mode=1, inner_btheta=torch.tensor(ci.btheta_map(N))))
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(N))
+    v = torch.tensor(ci.scaled_direction(inst.U, N))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, N))
+    R = c.ctx.residual(c.Ud).cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda()).cpu()
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    Jo, Ro = solve.jvp(c.og, c.U, c.br, c.op, v, dbr)
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w)
+    for a, b in ((R, Ro), (Jv, Jo), (gU.cpu(), gUo), (gbr.cpu()[None], gbro[None])):
+        assert float(rel_err_per_var(a, b).max()) <= TOL
+    # the two laws differ: the large-E boundary residual is not the low-E one
+    c0 = Case(inst)
+    assert not torch.allclose(c0.ctx.residual(c0.Ud).cpu(), R)
 
 
 @pytest.mark.parametrize("case", range(1, 10))
