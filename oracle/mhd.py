@@ -26,6 +26,11 @@ What is computed (paper Section 2.1 and Eqs. 14-17, Sections 3.2 and 4.1):
 * R_c = sum over faces of the outward numerical flux times |S| minus
   V_c S(U_c): the integrated residual, so dU/dt = -R/V.
 
+* Diagnostics (Sections 2.2 and 3.1): the ideal-MHD electric field
+  E = -V x B at the cell centroids in spherical components, its per-component
+  maximum and volume-weighted RMS, and the E-free state whose velocity keeps
+  only its component along B (V0 x B = 0, the paper's first remedy).
+
 The function ``residual`` evaluates R on any subset of cells; it gathers the
 distance-2 stencil it needs.  It is one vectorised code path for both the full
 grid and sampled cells.
@@ -450,3 +455,35 @@ def residual(grid: Grid, U: torch.Tensor, br: torch.Tensor, prm: Params,
     if return_speeds:
         return R.transpose(0, 1), (s, torch.linalg.norm(fs["S"], dim=-1))
     return R.transpose(0, 1)
+
+
+def efield(grid, U, prm: Params):
+    """Electric field of ideal MHD, E = -V x B (Section 2.2, Eqs. E1-E2), at
+    the cell centroids in spherical components (E_r, E_theta, E_phi) (3,
+    ncells), and the volume-weighted statistics the paper reads: per
+    component and for |E|, the maximum and the root mean square
+    sqrt(sum_c V_c E^2 / sum_c V_c); returns (E, max4, rms4)."""
+    cells = torch.arange(grid.ncells)
+    xc, V, _, _ = grid.cell_geometry(cells)
+    P = cons_to_prim(U.transpose(0, 1), prm.gamma)
+    E = -torch.linalg.cross(P[:, 1:4], P[:, 4:7])
+    rh, th, ph = spherical_basis(xc)
+    Es = torch.stack([dot(E, rh), dot(E, th), dot(E, ph)], dim=0)
+    mag = torch.linalg.norm(E, dim=-1)
+    comps = torch.cat([Es, mag[None]], dim=0)
+    mx = comps.abs().amax(dim=1)
+    rms = torch.sqrt((comps ** 2 * V[None]).sum(1) / V.sum())
+    return Es, mx, rms
+
+
+def efree_state(U, prm: Params):
+    """The E-free initial state of Section 3.1 (fix 1): the velocity keeps
+    only its component along B, V0 = (V . B) B / |B|^2 (unchanged where B = 0),
+    so that V0 x B = 0; rho, B, p and psi are kept (E is recomputed)."""
+    P = cons_to_prim(U.transpose(0, 1), prm.gamma)
+    v, B = P[:, 1:4], P[:, 4:7]
+    B2 = dot(B, B)
+    par = torch.where(B2 > 0, dot(v, B) / torch.where(B2 > 0, B2, torch.ones_like(B2)), torch.zeros_like(B2))
+    v0 = torch.where((B2 > 0)[:, None], par[:, None] * B, v)
+    P0 = torch.cat([P[:, :1], v0, P[:, 4:]], dim=1)
+    return prim_to_cons(P0, prm.gamma).transpose(0, 1)
