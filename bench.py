@@ -135,6 +135,38 @@ def bench_solver(with_sensitivity: bool):
     return res
 
 
+def bench_efield(ctx, U, reps: int = 20):
+    """The E-field diagnostic and the E-free state on the bench state: kernel
+    times from HIP events on the launch stream, and algorithmic HBM rates
+    (stats only: rho, rho v, B read, 56 B/cell; with the field also written,
+    80 B/cell; E-free state: 9 rows read and written, 144 B/cell)."""
+    import torch
+    nc = U.shape[1]
+    st = torch.empty(8, dtype=torch.float64, device="cuda")
+    E = torch.empty(3, nc, dtype=torch.float64, device="cuda")
+    U0 = torch.empty_like(U)
+    out = {}
+    for name, fn, kern, bpc in (("stats", lambda: ctx.efield(U, field=False, stats=st), "efield", 56),
+                                ("field", lambda: ctx.efield(U, stats=st, E=E), "efield", 80),
+                                ("efree", lambda: ctx.efree_state(U, out=U0), "efree", 144)):
+        fn()
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
+        ctx.timing_read()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms, n = ctx.timing_read()[kern]
+        ctx.timing_enable(False)
+        avg = ms / n
+        gbs = bpc * nc / (avg * 1e-3) / 1e9
+        out[name] = {"avg_ms": round(avg, 4), "alg_bytes_per_cell": bpc, "GB/s": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    out["max_abs_E_r_theta_phi_mag"] = [float(x) for x in st[:4].cpu()]
+    out["rms_E_r_theta_phi_mag"] = [float(x) for x in st[4:].cpu()]
+    return out
+
+
 def bench_ensemble(reps: int, solve_reps: int = 2):
     """64 uneven instances (29.95M cells): residual + JVP of all of them as one
     captured graph of two persistent launches, against 64 single-instance
@@ -346,6 +378,7 @@ def main():
             for op, f in vrec["flop_per_cell"].items()}
         out["fp64_valu_note"] = (f"executed FP64 flops per cell from rocprofv3 counters ({vsrc}) over the measured "
                                  f"operation times; peak {FP64_PEAK_TFLOPS} TFLOP/s")
+    out["efield"] = bench_efield(ctx, U)
     if not args.no_solver:
         out["solver"] = bench_solver(args.sensitivity)
     if args.copy_calibration:

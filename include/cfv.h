@@ -124,6 +124,24 @@ cfv_status cfv_vjp(cfv_ctx* ctx, const double* U, const double* w, double* gU, d
 /* Backward-Euler diagonal V_c/dt_c = sum_f s_f |S_f| / cfl (s_f Rusanov speed). */
 cfv_status cfv_local_dt(cfv_ctx* ctx, const double* U, double cfl, double* diag, hipStream_t s);
 
+/* -------------------------------------------------------- E-field --
+ * The ideal-MHD electric field E = -V x B (Section 2.2), the diagnostic the
+ * paper reads for the quality of an inner boundary law (Section 3.1: its
+ * azimuthal part should stay small).  At every cell centroid E is projected
+ * on the unit vectors r, theta, phi there (Eqs. 20-21; on the polar axis the
+ * meridian phi = 0 is taken).  E3 (device, nullable) receives the field as 3
+ * rows of ncells: E_r, E_theta, E_phi.  stats8 (device, 8 doubles) receives
+ * max_c |E_r|, |E_theta|, |E_phi|, |E| and then the volume-weighted RMS of
+ * the same four, sqrt(sum_c V_c E^2 / sum_c V_c).  Fixed reduction order
+ * (deterministic).  U is the conservative state, 9 rows of ncells. */
+cfv_status cfv_efield(cfv_ctx* ctx, const double* U, double* E3, double* stats8_dev, hipStream_t s);
+/* The E-free state (Section 3.1, the first remedy: V0 x B0 = 0): U_out is U
+ * with each cell's velocity replaced by its component along B,
+ * (V . B / |B|^2) B, and the total energy recomputed from the unchanged
+ * density, field and pressure; psi is kept; a cell with B = 0 is copied.
+ * U_out may equal U (in place); other overlaps are not allowed. */
+cfv_status cfv_efree_state(cfv_ctx* ctx, const double* U, double* U_out, hipStream_t s);
+
 /* --------------------------------------------------------- reductions --
  * out9[v] = sqrt(sum_c (a - b)^2) per variable (b may be NULL): the Eq. 2
  * monitor before the log10.  Fixed reduction order (deterministic). */

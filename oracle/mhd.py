@@ -457,13 +457,16 @@ def residual(grid: Grid, U: torch.Tensor, br: torch.Tensor, prm: Params,
     return R.transpose(0, 1)
 
 
-def efield(grid, U, prm: Params):
+def efield(grid, U, prm: Params, cells=None):
     """Electric field of ideal MHD, E = -V x B (Section 2.2, Eqs. E1-E2), at
     the cell centroids in spherical components (E_r, E_theta, E_phi) (3,
     ncells), and the volume-weighted statistics the paper reads: per
     component and for |E|, the maximum and the root mean square
-    sqrt(sum_c V_c E^2 / sum_c V_c); returns (E, max4, rms4)."""
-    cells = torch.arange(grid.ncells)
+    sqrt(sum_c V_c E^2 / sum_c V_c); returns (E, max4, rms4).  With cells
+    given, U holds those cells' states (9, len(cells)) and the statistics
+    are over them."""
+    if cells is None:
+        cells = torch.arange(grid.ncells)
     xc, V, _, _ = grid.cell_geometry(cells)
     P = cons_to_prim(U.transpose(0, 1), prm.gamma)
     E = -torch.linalg.cross(P[:, 1:4], P[:, 4:7])

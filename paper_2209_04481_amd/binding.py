@@ -60,6 +60,8 @@ def lib():
         "cfv_jvp": ([P, P, P, P, P, P, P], c_int32),
         "cfv_vjp": ([P, P, P, P, P, P], c_int32),
         "cfv_local_dt": ([P, P, c_double, P, P], c_int32),
+        "cfv_efield": ([P, P, P, P, P], c_int32),
+        "cfv_efree_state": ([P, P, P, P], c_int32),
         "cfv_norms": ([P, P, P, P, P], c_int32),
         "cfv_dots": ([P, P, c_int32, P, P, P], c_int32),
         "cfv_axpby": ([P, c_int64, c_double, P, c_double, P, P], c_int32),
@@ -254,6 +256,31 @@ class Context:
         d = out if out is not None else self._new(self.grid.ncells)
         check(lib().cfv_local_dt(self._h, self._state(U, "U"), float(cfl), _ptr(d), _stream(stream)))
         return d
+
+    def efield(self, U, field=True, stats=None, E=None, stream=None):
+        """E = -V x B in spherical components and its statistics (cfv_efield).
+
+        Returns (E, stats): E is [3, ncells] (E_r, E_theta, E_phi), or None
+        when field is False; stats holds max |E_r|, |E_theta|, |E_phi|, |E|
+        and then the volume-weighted RMS of the same four."""
+        o = stats if stats is not None else self._new(8)
+        if o.numel() < 8:
+            raise CfvError("stats needs 8 entries")
+        e = None
+        if field:
+            e = E if E is not None else self._new(3, self.grid.ncells)
+            if tuple(e.shape) != (3, self.grid.ncells):
+                raise CfvError(f"E must have shape (3, {self.grid.ncells})")
+        check(lib().cfv_efield(self._h, self._state(U, "U"), None if e is None else _ptr(e), _ptr(o),
+                               _stream(stream)))
+        return e, o
+
+    def efree_state(self, U, out=None, stream=None):
+        """U with its velocity projected on B (V x B = 0), cfv_efree_state;
+        out may be U itself."""
+        o = out if out is not None else self._new(9, self.grid.ncells)
+        check(lib().cfv_efree_state(self._h, self._state(U, "U"), self._state(o, "out"), _stream(stream)))
+        return o
 
     def norms(self, a, b=None, out=None, stream=None):
         o = out if out is not None else self._new(9)

@@ -19,6 +19,10 @@
 
 namespace cfv {
 int reduce_partials_per_vector();
+hipError_t launch_efield(const DevGrid& d, const double* U, double* E3, double* stats8, double* part, hipStream_t s,
+                         KernelTimer* t);
+hipError_t launch_efree(int64_t nc, double gamma, const double* U, double* Uo, hipStream_t s, KernelTimer* t);
+int efield_partials();
 hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s);
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -420,6 +424,24 @@ cfv_status cfv_local_dt(cfv_ctx* c, const double* U, double cfl, double* diag, h
   if (!U || !diag) return fail(CFV_ERR_ARG, "null state or output");
   if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, diag, c->W, s, c->tm()));
+  return CFV_OK;
+}
+
+cfv_status cfv_efield(cfv_ctx* c, const double* U, double* E3, double* stats8, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !stats8) return fail(CFV_ERR_ARG, "null state or statistics output");
+  if (cfv::efield_partials() > c->part_vectors * cfv::reduce_partials_per_vector())
+    return fail(CFV_ERR_ALLOC, "reduction workspace too small");
+  CFV_HIP(cfv::launch_efield(c->dev(), U, E3, stats8, c->part, s, c->tm()));
+  return CFV_OK;
+}
+
+cfv_status cfv_efree_state(cfv_ctx* c, const double* U, double* U_out, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !U_out) return fail(CFV_ERR_ARG, "null state or output");
+  const int64_t n = 9 * c->grid->g.ncells;
+  if (U != U_out && U_out < U + n && U < U_out + n) return fail(CFV_ERR_ARG, "U_out partially overlaps U");
+  CFV_HIP(cfv::launch_efree(c->grid->g.ncells, c->pr.gamma, U, U_out, s, c->tm()));
   return CFV_OK;
 }
 

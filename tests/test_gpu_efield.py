@@ -1,0 +1,120 @@
+"""GPU parity of the E-field diagnostic and the E-free state (Sections 2.2
+and 3.1) through the C ABI against the oracle.
+
+Bar: the field per component max_c |gpu - oracle| / max_c |oracle| <= 1e-12;
+the maxima and RMS values relative 1e-12 (the sums fold in another order);
+the E-free state per variable <= 1e-13 relative to the variable's maximum.
+"""
+import numpy as np
+import pytest
+import torch
+
+import coronal_inputs as ci
+from helpers import rel_err_per_var
+from oracle import mhd
+from oracle.grid import Grid as OGrid
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def make(N, Nr, seed, lmax=5, name=None):
+    from paper_2209_04481_amd import Context, Grid
+    inst = ci.workload(name) if name else ci.make_instance(N, Nr, "log", lmax=lmax, seed=seed)
+    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes))
+    return inst, ctx
+
+
+# plane N^2 below one tile, several tiles with a ragged tail, odd N with
+# centroids on the polar axis, one shell
+@pytest.mark.parametrize("N,Nr", [(5, 3), (17, 4), (7, 9), (24, 1)])
+def test_efield_parity(N, Nr):
+    print(f"case: efield N={N} Nr={Nr}", flush=True)
+    inst, ctx = make(N, Nr, 70 + N)
+    U = torch.tensor(inst.U)
+    E, st = ctx.efield(U.cuda())
+    E, st = E.cpu(), st.cpu()
+    Eo, mxo, rmso = mhd.efield(OGrid(inst.N, inst.Nr, inst.r_nodes), U, mhd.Params())
+    assert float(rel_err_per_var(E, Eo).max()) <= TOL
+    assert torch.allclose(st[:4], mxo, rtol=TOL, atol=0)
+    assert torch.allclose(st[4:], rmso, rtol=TOL, atol=0)
+    # statistics alone (no field output) are the same numbers, bitwise
+    none, st2 = ctx.efield(U.cuda(), field=False)
+    assert none is None and torch.equal(st2.cpu(), st)
+
+
+def test_efield_of_the_efree_state_vanishes():
+    inst, ctx = make(8, 6, 81)
+    U = torch.tensor(inst.U).cuda()
+    _, before = ctx.efield(U, field=False)
+    U0 = ctx.efree_state(U)
+    E0, after = ctx.efield(U0)
+    assert float(after[3]) <= 1e-12 * float(before[3])
+    assert float(E0.abs().max()) <= 1e-12 * float(before[3])
+
+
+@pytest.mark.parametrize("N,Nr", [(5, 3), (16, 7)])
+def test_efree_parity(N, Nr):
+    print(f"case: efree N={N} Nr={Nr}", flush=True)
+    inst, ctx = make(N, Nr, 90 + N)
+    U = torch.tensor(inst.U)
+    U[:7, 2] = torch.tensor([1.0, 0.2, -0.1, 0.0, 0.0, 0.0, 0.0], dtype=torch.float64)   # a cell with B = 0
+    U0 = ctx.efree_state(U.cuda()).cpu()
+    U0o = mhd.efree_state(U, mhd.Params())
+    assert float(rel_err_per_var(U0, U0o).max()) <= 1e-13
+    for q in (0, 4, 5, 6, 8):   # density, field and psi are copied
+        assert torch.equal(U0[q], U[q])
+    assert torch.equal(U0[:, 2], U[:, 2])
+    # in place gives the same bits
+    Ud = U.cuda()
+    ctx.efree_state(Ud, out=Ud)
+    assert torch.equal(Ud.cpu(), U0)
+
+
+def test_efield_efree_bad_arguments():
+    from paper_2209_04481_amd.binding import CfvError
+    inst, ctx = make(4, 2, 3)
+    U = torch.tensor(inst.U).cuda()
+    with pytest.raises(CfvError):
+        ctx.efield(U[:, 1:].contiguous())
+    with pytest.raises(CfvError):
+        ctx.efield(U, E=torch.empty(3, 5, dtype=torch.float64, device="cuda"))
+    big = torch.zeros(10 * inst.ncells, dtype=torch.float64, device="cuda")
+    a = big[:9 * inst.ncells].view(9, inst.ncells)
+    b = big[inst.ncells:].view(9, inst.ncells)
+    with pytest.raises(CfvError, match="overlap"):
+        ctx.efree_state(a, out=b)
+
+
+@pytest.mark.parametrize("name", ["medium", "large"])
+def test_efield_full_size_sampled(name):
+    """At the medium (1.66M) and large (13.3M cells) sizes: the field on
+    sampled cells against the oracle, the maxima against the field, the RMS
+    against a float64 torch sum over the field and the kernel volumes."""
+    print(f"case: efield {name}", flush=True)
+    inst, ctx = make(0, 0, 0, name=name)
+    U = torch.from_numpy(inst.U).cuda()
+    E, st = ctx.efield(U)
+    torch.cuda.synchronize()
+    g = OGrid(inst.N, inst.Nr, inst.r_nodes)
+    rng = np.random.default_rng(5)
+    cells = torch.from_numpy(np.unique(np.concatenate([
+        rng.integers(0, inst.ncells, 4000), [0, inst.ncells - 1],
+        np.arange(inst.N * inst.N) + (inst.Nr - 1) * inst.N * inst.N])))
+    Eo, _, _ = mhd.efield(g, torch.from_numpy(inst.U[:, cells.numpy()]), mhd.Params(), cells=cells)
+    Es = E[:, cells.cuda()].cpu()
+    scale = E.abs().amax(dim=1).cpu()
+    assert float(((Es - Eo).abs().amax(dim=1) / scale).max()) <= TOL
+    mag = torch.linalg.norm(E, dim=0)
+    comps = torch.cat([E.abs(), mag[None]], dim=0)
+    assert torch.equal(st[:3].cpu(), E.abs().amax(dim=1).cpu())
+    assert float(st[3]) == pytest.approx(float(mag.max()), rel=1e-15)
+    _, vol, _, _ = ctx.geometry()
+    rms = torch.sqrt((comps ** 2 * vol[None]).sum(1) / vol.sum())
+    assert torch.allclose(st[4:].cpu(), rms.cpu(), rtol=1e-11, atol=0)
