@@ -67,8 +67,9 @@ WORKLOADS = {
 
 
 def radial_nodes(Nr: int, radial: str = "log", ratio: float = 1.2,
-                 r0: float = 1.0, r1: float = 21.5) -> np.ndarray:
-    """Nr+1 strictly increasing radii from r0 to r1."""
+                 r0: float = 1.0, r1: float = 21.5, r_ext: float = 25.0, edge: float = 0.01) -> np.ndarray:
+    """Nr+1 strictly increasing radii from r0 to r1 ("geometric", "log"), or
+    from r0 to r_ext with a last layer of width edge ("bcind")."""
     if radial == "geometric":
         dr0 = (r1 - r0) * (ratio - 1.0) / (ratio ** Nr - 1.0)
         r = np.empty(Nr + 1)
@@ -82,6 +83,16 @@ def radial_nodes(Nr: int, radial: str = "log", ratio: float = 1.2,
     if radial == "log":
         r = r0 * (r1 / r0) ** (np.arange(Nr + 1) / Nr)
         r[0], r[-1] = r0, r1
+        return r
+    if radial == "bcind":
+        # the extended grid of the outer-boundary study: log spacing out to
+        # r_ext - edge, then one very thin last layer of width edge, so the
+        # outer ghost centre sits edge/2 beyond the boundary (r1 is ignored)
+        if Nr < 2:
+            raise ValueError("the extended grid needs at least two layers")
+        r = np.empty(Nr + 1)
+        r[:Nr] = r0 * ((r_ext - edge) / r0) ** (np.arange(Nr) / (Nr - 1))
+        r[0], r[Nr - 1], r[Nr] = r0, r_ext - edge, r_ext
         return r
     raise ValueError(radial)
 

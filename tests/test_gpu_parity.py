@@ -208,6 +208,26 @@ def test_parity_every_table2_outer_law(case):
     assert float(rel_err_per_var(gU.cpu(), solve.vjp(c.og, c.U, c.br, c.op, w)[0]).max()) <= TOL
 
 
+@pytest.mark.parametrize("case", [1, 9])
+def test_parity_bc_independent_grid(case):
+    """The extended grid of Section 4.4 (out to 25 solar radii, a last layer
+    0.01 thick: cells with a radial aspect ratio of about 100 next to ones of
+    about 1) under the two most different Table 2 outer laws."""
+    print(f"case: bc-independent grid, outer law {case}", flush=True)
+    N, Nr = 6, 12
+    inst = ci.make_instance(N, Nr, "bcind", lmax=5, seed=30 + case)
+    assert inst.r_nodes[-1] == 25.0 and abs(inst.r_nodes[-1] - inst.r_nodes[-2] - 0.01) < 1e-12
+    c = Case(inst, mhd.Params.table2(case))
+    w = torch.randn(9, inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(case))
+    v = torch.tensor(ci.scaled_direction(inst.U, case))
+    R = c.ctx.residual(c.Ud).cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda()).cpu()
+    gU, _ = c.ctx.vjp(c.Ud, w.cuda())
+    assert float(rel_err_per_var(R, mhd.residual(c.og, c.U, c.br, c.op)).max()) <= TOL
+    assert float(rel_err_per_var(Jv, solve.jvp(c.og, c.U, c.br, c.op, v)[0]).max()) <= TOL
+    assert float(rel_err_per_var(gU.cpu(), solve.vjp(c.og, c.U, c.br, c.op, w)[0]).max()) <= TOL
+
+
 @pytest.mark.parametrize("N,Nr", [(2, 3), (3, 1), (7, 2)])
 def test_degenerate_shapes(N, Nr):
     """Smallest panels, a single radial layer (both ghosts on one cell)."""

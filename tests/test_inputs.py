@@ -48,3 +48,13 @@ def test_workload_shapes():
     assert abs(inst.r_nodes[1] - inst.r_nodes[0] - 0.2344408) < 1e-6
     specs = ci.ensemble_specs()
     assert len(specs) == 64 and sum(6 * N * N * Nr for N, Nr, _ in specs) == 29952000
+
+
+def test_bc_independent_radii():
+    r = ci.radial_nodes(40, "bcind", edge=0.01)
+    assert r.shape == (41,) and r[0] == 1.0 and r[-1] == 25.0
+    assert np.all(np.diff(r) > 0)
+    assert abs((r[-1] - r[-2]) - 0.01) < 1e-12
+    # log spacing below the thin edge layer, and 21.5 inside the domain
+    q = np.diff(np.log(r[:-1]))
+    assert np.allclose(q, q[0], rtol=1e-10) and r[-2] > 21.5

@@ -178,3 +178,24 @@ def test_subset_evaluation_equals_full_grid():
     sub = torch.tensor([0, 7, 63, 64, 1000, 1023, 2048, 4095, 5000, 6143])
     Rs = mhd.residual(g, U, br, mhd.Params(), cells=sub)
     assert torch.equal(Rs, R[:, sub])
+
+
+def test_outer_law_difference_scales_with_ghost_distance():
+    """On the extended grid with a thin last layer (Section 4.4), the outer
+    ghost lies edge/2 beyond the boundary, so two Table 2 laws (cases 1 and
+    9, the most different) give ghosts that differ to first order in edge:
+    the residual difference in the last layer halves with edge, and no cell
+    beyond the stencil's reach of the boundary sees the law at all."""
+    N, Nr = 4, 6
+    d_last = []
+    for edge in (0.02, 0.01, 0.005):
+        r = ci.radial_nodes(Nr, "bcind", edge=edge)
+        U = torch.from_numpy(ci.to_conservative(ci.primitive_state(N, Nr, r, 5)))
+        br = torch.from_numpy(ci.br_map(N, 3, 5))
+        g = Grid(N, Nr, r)
+        d = (mhd.residual(g, U, br, mhd.Params.table2(1)) -
+             mhd.residual(g, U, br, mhd.Params.table2(9))).abs().reshape(9, 6, Nr, N, N)
+        assert float(d[:, :, :Nr - 2].max()) == 0.0
+        d_last.append(float(d[:, :, Nr - 1].max()))
+    assert d_last[0] / d_last[1] == pytest.approx(2.0, rel=0.05)
+    assert d_last[1] / d_last[2] == pytest.approx(2.0, rel=0.05)
