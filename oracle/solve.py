@@ -11,6 +11,9 @@
 * ``gmres``: unrestarted GMRES(m), x0 = 0, modified Gram-Schmidt, Givens
   least squares, for the implicit step (D + J) x = -R (Section 2.1: backward
   Euler with large CFL).
+* ``cfl_law``, ``eq2_prim`` and ``steady``: the march to a steady state,
+  backward-Euler steps under the CFL law of Section 4.1 with the Eq. 2
+  monitor of the primitive quantities and its stopping threshold.
 * ``layer_objective`` and ``step_map_sensitivity``: an objective on the state
   after n implicit steps with a fixed diagonal, and its exact gradient with
   respect to the inner B_r map, by reverse mode through the unrolled steps
@@ -128,6 +131,47 @@ def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None):
 
     x, hist = gmres(A, -R, m)
     return U + x, hist, R
+
+
+def cfl_law(it: int, cfl0: float = 2.0, cfl_max: float = 128.0, every: int = 200) -> float:
+    """CFL of pseudo-time iteration it (from 0): cfl0 doubled after every
+    `every` iterations and capped at cfl_max (Section 4.1: from 2, doubling
+    every few hundred iterations, up to 128; Section 2.1: up to 1000 or more)."""
+    cfl = cfl0
+    for _ in range(it // every):
+        if cfl >= cfl_max:
+            break
+        cfl *= 2.0
+    return min(cfl, cfl_max)
+
+
+def eq2_prim(Ua, Ub, gamma):
+    """Eq. 2 on the physical quantities: per primitive variable (rho, V, B,
+    p, psi), log10 sqrt(sum over cells of (a^t - a^{t+1})^2)."""
+    Pa = mhd.cons_to_prim(Ua.transpose(0, 1), gamma).transpose(0, 1)
+    Pb = mhd.cons_to_prim(Ub.transpose(0, 1), gamma).transpose(0, 1)
+    return eq2(Pa, Pb)
+
+
+def steady(grid: Grid, U, br, prm, iters: int, cfl0: float = 2.0, cfl_max: float = 128.0, every: int = 200,
+           m: int = 30, monitor: int = 1, target: float = -math.inf):
+    """Pseudo-time marching to a steady state (Sections 2.1, 4.1): backward-
+    Euler steps at the CFL of ``cfl_law``; after each step the Eq. 2 monitor
+    of the primitives between the old and new state is recorded, and the
+    march stops once the monitored variable (default 1, V_x) is below
+    target, or after iters steps.  Returns (U, monitor history (n, 9),
+    CFL per step)."""
+    hist, cfls = [], []
+    for it in range(iters):
+        cfl = cfl_law(it, cfl0, cfl_max, every)
+        Un, _, _ = be_step(grid, U, br, prm, cfl, m)
+        res = eq2_prim(U, Un, prm.gamma)
+        hist.append(res)
+        cfls.append(cfl)
+        U = Un
+        if float(res[monitor]) < target:
+            break
+    return U, torch.stack(hist), cfls
 
 
 def layer_objective(grid: Grid, layer=None):
