@@ -122,6 +122,24 @@ def bench_solver(with_sensitivity: bool):
            "be_step_ms": round(ms, 2), "gmres_iterations": int(len(hist)),
            "ms_per_gmres_iteration": round(ms / max(len(hist), 1), 3), "final_relative_residual": float(hist[-1])}
     print(f"[bench] backward-Euler step: {ms:.1f} ms", file=sys.stderr, flush=True)
+    # the march to a steady state: 8 steps under the CFL law from 2, doubling every step up to 128
+    Us = U.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    from paper_2209_04481_amd.binding import CfvNonPhysical
+    try:
+        mh, cfls = ctx.steady(Us, 8, cfl0=2.0, cfl_max=128.0, every=1, m=30)
+        stop = "completed"
+    except CfvNonPhysical as e:
+        mh, cfls, stop = e.hist, e.cfls, "non-finite state"
+    torch.cuda.synchronize()
+    ms_st = (time.perf_counter() - t0) * 1e3 / max(len(cfls), 1)
+    res["steady_march"] = {"steps": int(len(cfls)), "ms_per_step": round(ms_st, 2), "end": stop,
+                           "cfl": [float(c) for c in cfls],
+                           "log10_monitor_V_x": [round(float(x), 3) for x in mh[:, 1]],
+                           "log10_monitor_rho": [round(float(x), 3) for x in mh[:, 0]]}
+    print(f"[bench] steady march: {ms_st:.1f} ms per step", file=sys.stderr, flush=True)
+    del Us
     if with_sensitivity:
         from paper_2209_04481_amd.sensitivity import Sensitivity
         br = torch.from_numpy(inst.br).cuda()

@@ -176,6 +176,41 @@ cfv_status cfv_be_step(cfv_ctx* ctx, const double* U, double cfl, int32_t m, int
                        double* U_new, double* hist, int32_t hist_len, int32_t* iters, double* final_rel,
                        hipStream_t s);
 
+/* ------------------------------------------------------ steady march --
+ * The Eq. 2 monitor on the physical quantities: out9 (device) receives, per
+ * primitive variable (rho, V_x, V_y, V_z, B_x, B_y, B_z, p, psi), the 2-norm
+ * over the cells of the change between the states a and b,
+ * sqrt(sum_c (a_c - b_c)^2), before the log10.  Deterministic. */
+cfv_status cfv_monitor(cfv_ctx* ctx, const double* a, const double* b, double* out9_dev, hipStream_t s);
+
+/* Pseudo-time march to a steady state (Sections 2.1 and 4.1). */
+typedef struct {
+  double cfl0;          /* CFL of the first step (the paper starts at 2) */
+  double cfl_max;       /* cap (128 in the paper's CFL law; up to 1000 or more) */
+  int32_t every;        /* steps between doublings of the CFL (>= 1) */
+  int32_t max_iters;    /* at most this many steps (>= 0) */
+  int32_t monitor;      /* primitive variable of the stopping rule, 0..8 (1 = V_x) */
+  double target;        /* stop once log10 of its Eq. 2 value is below this */
+  int32_t m;            /* GMRES(m) per step, 1..200 */
+  int32_t max_restarts; /* restarts of the linear solve per step */
+  double rtol;          /* relative tolerance of the linear solve (0: all iterations) */
+} cfv_steady_cfg;
+
+/* Backward-Euler steps (cfv_be_step) from the state U (device, updated in
+ * place) with CFL_i = min(cfl0 2^floor(i / every), cfl_max) at step i, until
+ * log10 of the Eq. 2 monitor (cfv_monitor between the states before and after
+ * a step) of variable `monitor` falls below target, or max_iters steps.
+ * hist (host, nullable, 9 max_iters) receives the nine log10 monitor values
+ * of every step, cfl_hist (host, nullable, max_iters) the CFL used, iters the
+ * number of steps taken.  The stream is synchronised once per step for the
+ * monitor (and once per GMRES iteration inside the solve).  A second state
+ * buffer is owned by the context (allocated on first use).  If a step
+ * produces a non-finite monitor value the march stops, U keeps the state
+ * before that step, the step is counted in iters and recorded in hist, and
+ * CFV_ERR_NONPHYSICAL is returned. */
+cfv_status cfv_steady(cfv_ctx* ctx, double* U, const cfv_steady_cfg* cfg, double* hist, double* cfl_hist,
+                      int32_t* iters, hipStream_t s);
+
 /* ------------------------------------------------- second derivatives --
  * Directional derivatives of the linearisations, for the second-order terms
  * of the adjoint of the implicit step map (the Newton linearisation of

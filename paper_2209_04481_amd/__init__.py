@@ -7,5 +7,5 @@ its exact Jacobian-vector product and its adjoint, written as HIP kernels
 for gfx950 behind a C ABI (include/cfv.h) and bound here with ctypes.
 """
 from .params import Params, OUTER_CASES, V_REF  # noqa: F401
-from .binding import CfvError, Context, Ensemble, Grid, Tuning, lib  # noqa: F401
+from .binding import CfvError, CfvNonPhysical, Context, Ensemble, Grid, Tuning, lib  # noqa: F401
 from .autograd import MHDResidual, residual  # noqa: F401

@@ -29,8 +29,23 @@ class CfvTuning(ctypes.Structure):
     _fields_ = [("queue", c_int32), ("blocks_per_cu", c_int32), ("order", c_int32)]
 
 
+class CfvSteadyCfg(ctypes.Structure):
+    _fields_ = [("cfl0", c_double), ("cfl_max", c_double), ("every", c_int32), ("max_iters", c_int32),
+                ("monitor", c_int32), ("target", c_double), ("m", c_int32), ("max_restarts", c_int32),
+                ("rtol", c_double)]
+
+
 class CfvError(RuntimeError):
     pass
+
+
+class CfvNonPhysical(CfvError):
+    """A march that produced a non-finite state; hist and cfls hold the steps
+    taken (the last one the failing step) and the state is the one before it."""
+
+    def __init__(self, msg, hist, cfls):
+        super().__init__(msg)
+        self.hist, self.cfls = hist, cfls
 
 
 _lib = None
@@ -62,6 +77,8 @@ def lib():
         "cfv_local_dt": ([P, P, c_double, P, P], c_int32),
         "cfv_efield": ([P, P, P, P, P], c_int32),
         "cfv_efree_state": ([P, P, P, P], c_int32),
+        "cfv_monitor": ([P, P, P, P, P], c_int32),
+        "cfv_steady": ([P, P, ctypes.POINTER(CfvSteadyCfg), P, P, P, P], c_int32),
         "cfv_norms": ([P, P, P, P, P], c_int32),
         "cfv_dots": ([P, P, c_int32, P, P, P], c_int32),
         "cfv_axpby": ([P, c_int64, c_double, P, c_double, P, P], c_int32),
@@ -281,6 +298,30 @@ class Context:
         o = out if out is not None else self._new(9, self.grid.ncells)
         check(lib().cfv_efree_state(self._h, self._state(U, "U"), self._state(o, "out"), _stream(stream)))
         return o
+
+    def monitor(self, a, b, out=None, stream=None):
+        """Eq. 2 monitor of the primitives before the log10 (cfv_monitor): 9 norms."""
+        o = out if out is not None else self._new(9)
+        check(lib().cfv_monitor(self._h, self._state(a, "a"), self._state(b, "b"), _ptr(o), _stream(stream)))
+        return o
+
+    def steady(self, U, max_iters, cfl0=2.0, cfl_max=128.0, every=200, monitor=1, target=-np.inf, m=30,
+               max_restarts=0, rtol=0.0, stream=None):
+        """March U (updated in place) toward a steady state (cfv_steady).
+
+        Returns (log10 monitor history [iters, 9], CFL per step [iters])."""
+        cfg = CfvSteadyCfg(float(cfl0), float(cfl_max), int(every), int(max_iters), int(monitor), float(target),
+                           int(m), int(max_restarts), float(rtol))
+        hist = np.zeros((max(int(max_iters), 1), 9))
+        cfls = np.zeros(max(int(max_iters), 1))
+        it = c_int32()
+        st = lib().cfv_steady(self._h, self._state(U, "U"), ctypes.byref(cfg), hist.ctypes.data_as(c_void_p),
+                              cfls.ctypes.data_as(c_void_p), ctypes.byref(it), _stream(stream))
+        if st == 4:
+            raise CfvNonPhysical(f"cfv status 4: {lib().cfv_last_error().decode()}", hist[:it.value],
+                                 cfls[:it.value])
+        check(st)
+        return hist[:it.value], cfls[:it.value]
 
     def norms(self, a, b=None, out=None, stream=None):
         o = out if out is not None else self._new(9)

@@ -23,6 +23,9 @@ hipError_t launch_efield(const DevGrid& d, const double* U, double* E3, double* 
                          KernelTimer* t);
 hipError_t launch_efree(int64_t nc, double gamma, const double* U, double* Uo, hipStream_t s, KernelTimer* t);
 int efield_partials();
+hipError_t launch_prim_delta_norms(int64_t nc, double gamma, const double* a, const double* b, double* out9,
+                                   double* part, hipStream_t s, KernelTimer* t);
+int monitor_partials();
 hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s);
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
@@ -125,6 +128,9 @@ struct cfv_ctx {
   double* dir_g = nullptr;    // 9 ncells: second evaluation
   double* dir_b = nullptr;    // 3 x 6N^2: shifted maps and the second B_r gradient
   double* dir_s = nullptr;    // 32 device scalars
+  // steady-march workspace (allocated on first use)
+  double* st_u = nullptr;     // 9 ncells: the other state of the march
+  double* st_m = nullptr;     // 9 device scalars: the monitor
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -366,7 +372,7 @@ void cfv_ctx_destroy(cfv_ctx* c) {
   if (c->dcn) (void)hipFree(c->dcn);
   if (c->slot) (void)hipFree(c->slot);
   double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
-                  c->dir_u, c->dir_g, c->dir_b, c->dir_s};
+                  c->dir_u, c->dir_g, c->dir_b, c->dir_s, c->st_u, c->st_m};
   for (double* b : kb)
     if (b) (void)hipFree(b);
   delete c;
@@ -618,6 +624,73 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   CFV_HIP(hipMemcpyAsync(U_new, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, 1.0, c->kry_x, 1.0, U_new, s));
   return CFV_OK;
+}
+
+// ------------------------------------------------------ steady march
+cfv_status cfv_monitor(cfv_ctx* c, const double* a, const double* b, double* out9, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!a || !b || !out9) return fail(CFV_ERR_ARG, "null state or output");
+  if (cfv::monitor_partials() > c->part_vectors * cfv::reduce_partials_per_vector())
+    return fail(CFV_ERR_ALLOC, "reduction workspace too small");
+  CFV_HIP(cfv::launch_prim_delta_norms(c->grid->g.ncells, c->pr.gamma, a, b, out9, c->part, s, c->tm()));
+  return CFV_OK;
+}
+
+cfv_status cfv_steady(cfv_ctx* c, double* U, const cfv_steady_cfg* cfg, double* hist, double* cfl_hist,
+                      int32_t* iters, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (!U || !cfg) return fail(CFV_ERR_ARG, "null state or configuration");
+  if (!(cfg->cfl0 > 0.0) || !(cfg->cfl_max >= cfg->cfl0)) return fail(CFV_ERR_ARG, "need 0 < cfl0 <= cfl_max");
+  if (cfg->every < 1 || cfg->max_iters < 0) return fail(CFV_ERR_ARG, "need every >= 1 and max_iters >= 0");
+  if (cfg->monitor < 0 || cfg->monitor > 8) return fail(CFV_ERR_ARG, "monitor must be a variable 0..8");
+  if (cfg->m < 1 || cfg->m > 200 || cfg->max_restarts < 0) return fail(CFV_ERR_ARG, "need 1 <= m <= 200");
+  if (iters) *iters = 0;
+  const int64_t n = 9 * c->grid->g.ncells;
+  if (!c->st_u) {
+    cfv_status st;
+    if ((st = dmalloc(&c->st_u, size_t(n))) || (st = dmalloc(&c->st_m, 9))) {
+      if (c->st_u) (void)hipFree(c->st_u);
+      c->st_u = c->st_m = nullptr;
+      return st;
+    }
+  }
+  double* cur = U;
+  double* nxt = c->st_u;
+  cfv_status out = CFV_OK;
+  int32_t done = 0;
+  while (done < cfg->max_iters) {
+    const double cfl = std::min(std::ldexp(cfg->cfl0, done / cfg->every), cfg->cfl_max);
+    out = cfv_be_step(c, cur, cfl, cfg->m, cfg->max_restarts, cfg->rtol, nxt, nullptr, 0, nullptr, nullptr, s);
+    if (out == CFV_OK) out = cfv_monitor(c, cur, nxt, c->st_m, s);
+    double mon[9];
+    if (out == CFV_OK) {
+      hipError_t e = hipMemcpyAsync(mon, c->st_m, sizeof(mon), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) out = hip_fail(e, "monitor read-back");
+    }
+    if (out != CFV_OK) break;
+    bool finite = true;
+    for (int v = 0; v < 9; ++v) {
+      mon[v] = std::log10(mon[v]);
+      if (std::isnan(mon[v]) || (std::isinf(mon[v]) && mon[v] > 0.0)) finite = false;
+      if (hist) hist[int64_t(done) * 9 + v] = mon[v];
+    }
+    if (cfl_hist) cfl_hist[done] = cfl;
+    ++done;
+    if (!finite) {
+      out = fail(CFV_ERR_NONPHYSICAL, "the march produced a non-finite state");
+      break;
+    }
+    std::swap(cur, nxt);
+    if (mon[cfg->monitor] < cfg->target) break;
+  }
+  if (iters) *iters = done;
+  // the last accepted state back into U (also after an error)
+  if (cur != U) {
+    const hipError_t e = hipMemcpyAsync(U, cur, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess && out == CFV_OK) out = hip_fail(e, "state copy-back");
+  }
+  return out;
 }
 
 // ------------------------------------------------- second derivatives

@@ -36,3 +36,29 @@ def polytropic_parker(r, gamma, G, rc, rho_c):
     v = 0.5 * (lo + hi)
     rho = Mdot / (v * r * r)
     return v, rho, Kp * rho ** gamma
+
+
+def perturbed_parker(N=4, Nr=6, gam=1.05, amp=1e-3, seed=1):
+    """Transonic polytropic wind with a radial monopole field (an exact steady
+    state of the equations) at the cell centroids, perturbed by uniform noise
+    of relative size amp: (oracle grid, U (9, ncells), inner B_r map)."""
+    import coronal_inputs as ci
+    from oracle import constants as K
+    from oracle.grid import Grid
+    g = Grid(N, Nr, ci.radial_nodes(Nr))
+    xc, _, _, _ = g.cell_geometry(torch.arange(g.ncells))
+    r = xc.norm(dim=-1)
+    rh = xc / r[:, None]
+    v, rho, p = (torch.tensor(a) for a in polytropic_parker(r.numpy(), gam, K.G, 3.0, 0.05))
+    P = torch.zeros(g.ncells, 9, dtype=torch.float64)
+    P[:, 0], P[:, 1:4], P[:, 7] = rho, v[:, None] * rh, p
+    P[:, 4:7] = 0.5 * rh / r[:, None] ** 2
+    gen = torch.Generator().manual_seed(seed)
+    P[:, :8] *= 1 + amp * (2 * torch.rand(g.ncells, 8, generator=gen, dtype=torch.float64) - 1)
+    U = torch.empty(9, g.ncells, dtype=torch.float64)
+    U[0] = P[:, 0]
+    U[1:4] = (P[:, 0:1] * P[:, 1:4]).T
+    U[4:7] = P[:, 4:7].T
+    U[7] = P[:, 7] / (gam - 1) + 0.5 * P[:, 0] * (P[:, 1:4] ** 2).sum(1) + 0.5 * (P[:, 4:7] ** 2).sum(1)
+    U[8] = 0.0
+    return g, U, torch.full((g.nb,), 0.5, dtype=torch.float64)

@@ -1,0 +1,110 @@
+"""GPU parity of the march to a steady state (Sections 2.1, 4.1) through the
+C ABI: the Eq. 2 monitor on primitives, the CFL law, the stopping rule, and
+the march itself against the oracle.
+
+Bars: the monitor's norms 1e-13 relative; the march (8 backward-Euler steps
+with unconverged GMRES(20)) follows the oracle to 1e-8 per variable relative
+to the variable's maximum, and its log10 monitor history to 1e-6 absolute
+(rounding differences of the Krylov solves grow over the steps)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import coronal_inputs as ci
+from helpers import perturbed_parker, rel_err_per_var
+from oracle import mhd, solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def context(g, br, gam, limiter):
+    from paper_2209_04481_amd import Context, Grid, Params
+    ctx = Context(Grid(g.N, g.Nr, g.r.numpy()), Params(gamma=gam, limiter=limiter))
+    ctx.set_inner_br(br.cuda())
+    return ctx
+
+
+def test_monitor_parity():
+    inst = ci.make_instance(5, 4, "log", lmax=3, seed=12)
+    from paper_2209_04481_amd import Context, Grid
+    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes))
+    a = torch.tensor(inst.U)
+    b = a.clone()
+    b[1:4] *= 1.01
+    b[7] *= 0.99
+    b[0] *= 1.002
+    got = ctx.monitor(a.cuda(), b.cuda()).cpu()
+    want = 10.0 ** solve.eq2_prim(a, b, mhd.Params().gamma)
+    assert torch.allclose(got, want, rtol=1e-13, atol=0)
+    # identical states: zero up to the rounding of two inlined conversions
+    P = mhd.cons_to_prim(a.T, mhd.Params().gamma).T
+    scale = P.abs().amax(dim=1) * P.shape[1] ** 0.5
+    assert bool((ctx.monitor(a.cuda(), a.cuda()).cpu() <= 1e-15 * scale).all())
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_steady_march_matches_oracle(limiter):
+    print(f"case: steady march, perturbed Parker wind 6x4x4x6, limiter {limiter}", flush=True)
+    g, U, br = perturbed_parker()
+    prm = mhd.Params(gamma=1.05, limiter=limiter)
+    ctx = context(g, br, 1.05, limiter)
+    Ud = U.cuda()
+    hist, cfls = ctx.steady(Ud, 8, cfl0=2.0, cfl_max=128.0, every=2, m=20)
+    Uo, ho, co = solve.steady(g, U, br, prm, 8, cfl0=2.0, cfl_max=128.0, every=2, m=20)
+    assert list(cfls) == co
+    assert float(rel_err_per_var(Ud.cpu(), Uo).max()) <= 1e-8
+    assert float(np.abs(hist - ho.numpy()).max()) <= 1e-6
+    # the march settles: the last density update is much smaller than the first
+    assert hist[-1, 0] < hist[0, 0] - 1.0
+
+
+def test_steady_stopping_rule_and_cfl_cap():
+    g, U, br = perturbed_parker(seed=2)
+    ctx = context(g, br, 1.05, 0)
+    hist, cfls = ctx.steady(U.cuda(), 6, cfl0=2.0, cfl_max=5.0, every=1, m=10)
+    assert list(cfls) == [2.0, 4.0, 5.0, 5.0, 5.0, 5.0]
+    assert hist[2, 0] < hist[1, 0] < hist[0, 0]
+    tgt = 0.5 * (hist[1, 0] + hist[2, 0])
+    Ud = U.cuda()
+    hs, cs = ctx.steady(Ud, 6, cfl0=2.0, cfl_max=5.0, every=1, m=10, monitor=0, target=tgt)
+    assert hs.shape == (3, 9) and np.array_equal(hs, hist[:3]) and list(cs) == [2.0, 4.0, 5.0]
+    # zero steps leave the state alone
+    U0 = Ud.clone()
+    h0, c0 = ctx.steady(Ud, 0)
+    assert h0.shape == (0, 9) and torch.equal(Ud, U0)
+
+
+def test_steady_bad_configuration():
+    from paper_2209_04481_amd.binding import CfvError
+    g, U, br = perturbed_parker(N=2, Nr=2)
+    ctx = context(g, br, 1.05, 0)
+    Ud = U.cuda()
+    for kw in ({"cfl0": 0.0}, {"cfl0": 4.0, "cfl_max": 2.0}, {"every": 0}, {"monitor": 9}, {"m": 0}):
+        with pytest.raises(CfvError):
+            ctx.steady(Ud, 2, **kw)
+    assert torch.equal(Ud.cpu(), U)
+
+
+def test_steady_step_is_the_backward_euler_step_medium():
+    """At 1.66M cells: one march step equals cfv_be_step at cfl0 bit for bit,
+    and its recorded monitor equals cfv_monitor of the two states."""
+    print("case: steady march medium", flush=True)
+    from paper_2209_04481_amd import Context, Grid, Params
+    inst = ci.workload("medium")
+    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes), Params())
+    ctx.set_inner_br(torch.from_numpy(inst.br).cuda())
+    U0 = torch.from_numpy(inst.U).cuda()
+    U1 = U0.clone()
+    hist, cfls = ctx.steady(U1, 1, cfl0=2.0, m=30)
+    Ube, _ = ctx.be_step(U0, cfl=2.0, m=30)
+    assert torch.equal(U1, Ube)
+    mon = [math.log10(x) for x in ctx.monitor(U0, U1).cpu().tolist()]
+    assert hist[0].tolist() == mon and list(cfls) == [2.0]

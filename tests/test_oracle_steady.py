@@ -8,8 +8,7 @@ import pytest
 import torch
 
 import coronal_inputs as ci
-from helpers import polytropic_parker
-from oracle import constants as K
+from helpers import perturbed_parker
 from oracle import mhd, solve
 from oracle.grid import Grid
 
@@ -37,22 +36,6 @@ def test_eq2_monitor_on_primitives_by_hand():
             math.log10(1.25), -math.inf]
     for a, b in zip(out.tolist(), want):
         assert a == b or a == pytest.approx(b, rel=1e-14)
-
-
-def perturbed_parker(N=4, Nr=6, gam=1.05, amp=1e-3, seed=1):
-    """Transonic polytropic wind with a radial monopole field (an exact steady
-    state of the equations), perturbed by uniform noise of relative size amp."""
-    g = Grid(N, Nr, ci.radial_nodes(Nr))
-    xc, _, _, _ = g.cell_geometry(torch.arange(g.ncells))
-    r = xc.norm(dim=-1)
-    rh = xc / r[:, None]
-    v, rho, p = (torch.tensor(a) for a in polytropic_parker(r.numpy(), gam, K.G, 3.0, 0.05))
-    P = torch.zeros(g.ncells, 9, dtype=DT)
-    P[:, 0], P[:, 1:4], P[:, 7] = rho, v[:, None] * rh, p
-    P[:, 4:7] = 0.5 * rh / r[:, None] ** 2
-    gen = torch.Generator().manual_seed(seed)
-    P[:, :8] *= 1 + amp * (2 * torch.rand(g.ncells, 8, generator=gen, dtype=DT) - 1)
-    return g, mhd.prim_to_cons(P, gam).T.contiguous(), torch.full((g.nb,), 0.5, dtype=DT)
 
 
 def test_march_drives_perturbed_wind_toward_equilibrium():
