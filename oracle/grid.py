@@ -148,17 +148,45 @@ class Grid:
         step = (math.pi / 2) / N
         i = torch.floor((torch.atan(a) + math.pi / 4) / step).long().clamp(0, N - 1)
         j = torch.floor((torch.atan(b) + math.pi / 4) / step).long().clamp(0, N - 1)
-        # radial: compare |y| with the radii of the column's radial faces
-        # along the ray (the quads sit at r_k * |mean of the corner dirs|).
-        cm = (self.corner[p, j, i] + self.corner[p, j, i + 1]
-              + self.corner[p, j + 1, i] + self.corner[p, j + 1, i + 1]) / 4.0
-        yr = torch.linalg.norm(y, dim=-1) / torch.linalg.norm(cm, dim=-1)
+        # radial: the column's radial faces are the bilinear patches r_k B(s, t)
+        # through its four corner directions; the ray through y meets them at
+        # radii r_k |B(s*, t*)|, with (s*, t*) where B is parallel to y.
+        yr = torch.linalg.norm(y, dim=-1) / self._patch_norm_along(p, j, i, y, a, b, step)
         k = torch.searchsorted(self.r, yr.contiguous()) - 1
         out = self.encode(p, k.clamp(0, Nr - 1), j, i)
         g = (p * N + j) * N + i
         out = torch.where(k < 0, self.ncells + g, out)
         out = torch.where(k >= Nr, self.ncells + self.nb + g, out)
         return out
+
+    def _patch_norm_along(self, p, j, i, y, a, b, step, iters: int = 8):
+        """|B(s, t)| at the point of the column's unit bilinear patch
+        B(s, t) = (1-s)(1-t) c00 + s(1-t) c01 + (1-s)t c10 + st c11 (corner
+        directions c_ji) that lies on the ray through y: Gauss-Newton on the
+        component of B normal to the ray, from the angular position."""
+        c00, c01 = self.corner[p, j, i], self.corner[p, j, i + 1]
+        c10, c11 = self.corner[p, j + 1, i], self.corner[p, j + 1, i + 1]
+        yh = y / torch.linalg.norm(y, dim=-1, keepdim=True)
+        s = (torch.atan(a) + math.pi / 4) / step - i
+        t = (torch.atan(b) + math.pi / 4) / step - j
+        for _ in range(iters):
+            B = ((1 - s) * (1 - t))[..., None] * c00 + (s * (1 - t))[..., None] * c01 \
+                + ((1 - s) * t)[..., None] * c10 + (s * t)[..., None] * c11
+            Bs = (1 - t)[..., None] * (c01 - c00) + t[..., None] * (c11 - c10)
+            Bt = (1 - s)[..., None] * (c10 - c00) + s[..., None] * (c11 - c01)
+
+            def perp(v):
+                return v - (v * yh).sum(-1, keepdim=True) * yh
+            r, Js, Jt = perp(B), perp(Bs), perp(Bt)
+            # 2x2 normal equations of min |r + Js ds + Jt dt|
+            a11, a12, a22 = (Js * Js).sum(-1), (Js * Jt).sum(-1), (Jt * Jt).sum(-1)
+            g1, g2 = -(Js * r).sum(-1), -(Jt * r).sum(-1)
+            det = a11 * a22 - a12 * a12
+            s = s + (a22 * g1 - a12 * g2) / det
+            t = t + (a11 * g2 - a12 * g1) / det
+        B = ((1 - s) * (1 - t))[..., None] * c00 + (s * (1 - t))[..., None] * c01 \
+            + ((1 - s) * t)[..., None] * c10 + (s * t)[..., None] * c11
+        return torch.linalg.norm(B, dim=-1)
 
     def is_ghost(self, ids: torch.Tensor) -> torch.Tensor:
         return ids >= self.ncells

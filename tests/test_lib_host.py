@@ -40,7 +40,8 @@ def test_library_exports_every_declared_symbol(built):
 
 
 @pytest.mark.parametrize("N,Nr,radial", [(8, 16, "geometric"), (5, 7, "log"), (12, 3, "log"),
-                                         (3, 1, "log"), (3, 2, "log"), (4, 1, "log"), (2, 2, "log")])
+                                         (3, 1, "log"), (3, 2, "log"), (4, 1, "log"), (2, 2, "log"),
+                                         (6, 12, "bcind"), (5, 3, "bcind")])
 def test_face_list_bit_exact_vs_geometric_matching(built, N, Nr, radial):
     """Library adjacency (closed-form panel-edge table) vs the oracle's
     point-location derivation: identical canonical face lists."""

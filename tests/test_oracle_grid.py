@@ -40,10 +40,13 @@ def test_neighbour_reciprocity_and_degree():
     assert bool((s[:, 1:] != s[:, :-1]).all())
 
 
-def test_point_location_matches_centroid_matching():
+@pytest.mark.parametrize("radial", ["log", "bcind"])
+def test_point_location_matches_centroid_matching(radial):
     """Independent derivation: pair faces by coincident centroids (brute force
-    on the sorted rounded coordinates) and compare with point location."""
-    g = small_grid(4, 5)
+    on the sorted rounded coordinates) and compare with point location; also
+    on the extended grid whose last layer (0.01 thick at r = 25) is thinner
+    than the curvature of its angular faces."""
+    g = Grid(4, 5, ci.radial_nodes(5, radial))
     cells = torch.arange(g.ncells)
     xc, V, xf, S = g.cell_geometry(cells)
     nb = g.neighbours(cells)
