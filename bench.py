@@ -297,6 +297,7 @@ def main():
     ap.add_argument("--ensemble-reps", type=int, default=50)
     ap.add_argument("--solve-reps", type=int, default=2)
     ap.add_argument("--no-solver", action="store_true")
+    ap.add_argument("--efield-reps", type=int, default=20)
     ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 70 s)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -396,7 +397,7 @@ def main():
             for op, f in vrec["flop_per_cell"].items()}
         out["fp64_valu_note"] = (f"executed FP64 flops per cell from rocprofv3 counters ({vsrc}) over the measured "
                                  f"operation times; peak {FP64_PEAK_TFLOPS} TFLOP/s")
-    out["efield"] = bench_efield(ctx, U)
+    out["efield"] = bench_efield(ctx, U, args.efield_reps)
     if not args.no_solver:
         out["solver"] = bench_solver(args.sensitivity)
     if args.copy_calibration:
