@@ -291,6 +291,26 @@ cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on);
 cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, double* total_ms, int64_t* count,
                                     int32_t* n);
 
+/* Batched march to a steady state (Sections 2.1 and 4.1) of every instance
+ * of the ensemble: lockstep backward-Euler steps with GMRES(m) (the step of
+ * cfv_ensemble_bind_be_step, captured in a graph when s is a created stream
+ * and captured again whenever the CFL law changes the CFL), the Eq. 2
+ * monitor of each instance after each step (cfv_monitor), and the CFL law
+ * and stopping rule of cfv_steady (cfg->max_restarts and cfg->rtol are not
+ * used: the lockstep step runs its m iterations).  An instance stops once
+ * its monitored variable is below target: later steps of the others still
+ * compute it (the graph is shared) but its state is no longer updated.
+ * U (device, per instance, updated in place) and U_work (device, per
+ * instance, the step's output) are 9 ncells each and must not alias.
+ * hist (host, nullable, n x max_iters x 9) receives the log10 monitors, NaN
+ * after an instance stopped; steps (host, nullable, n) the steps each
+ * instance took; iters the lockstep steps run.  An instance whose step gives
+ * a non-finite monitor keeps its previous state and stops; the call then
+ * returns CFV_ERR_NONPHYSICAL after the others finish.  The ensemble's
+ * binding is replaced by the step binding. */
+cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const* U_work, const cfv_steady_cfg* cfg,
+                               double* hist, int32_t* steps, int32_t* iters, hipStream_t s);
+
 /* ------------------------------------------------------------ profiling --
  * While enabled, every kernel launch of the context is bracketed by a pair of
  * HIP events on its launch stream.  cfv_timing_read synchronises on the

@@ -94,6 +94,7 @@ def lib():
         "cfv_ensemble_run": ([P, P], c_int32),
         "cfv_ensemble_bind_be_step": ([P, P, P, c_double, c_int32, P], c_int32),
         "cfv_ensemble_residual_jvp": ([P, P, P, P, P, P], c_int32),
+        "cfv_ensemble_steady": ([P, P, P, ctypes.POINTER(CfvSteadyCfg), P, P, P, P], c_int32),
         "cfv_ensemble_graph_capture": ([P, P], c_int32),
         "cfv_ensemble_graph_launch": ([P, P], c_int32),
         "cfv_ensemble_timing_enable": ([P, c_int32], c_int32),
@@ -460,6 +461,33 @@ class Ensemble:
 
     def run(self, stream=None):
         check(lib().cfv_ensemble_run(self._h, _stream(stream)))
+
+    def steady(self, U, max_iters, cfl0=2.0, cfl_max=128.0, every=200, monitor=1, target=-np.inf, m=30,
+               U_work=None, stream=None):
+        """March every instance (U, updated in place) toward a steady state in
+        lockstep (cfv_ensemble_steady); a graph is captured when stream is a
+        created stream.  Returns (log10 monitor history [n, max_iters, 9], NaN
+        after an instance stopped; steps per instance)."""
+        import torch
+        st = lambda c: (9, c.grid.ncells)
+        self._check(U, "U", st)
+        U_work = U_work if U_work is not None else [torch.empty_like(u) for u in U]
+        self._check(U_work, "U_work", st)
+        self._keep = (U, U_work)
+        n = len(self.contexts)
+        cfg = CfvSteadyCfg(float(cfl0), float(cfl_max), int(every), int(max_iters), int(monitor), float(target),
+                           int(m), 0, 0.0)
+        hist = np.zeros((n, max(int(max_iters), 1), 9))
+        steps = np.zeros(n, dtype=np.int32)
+        it = c_int32()
+        rc = lib().cfv_ensemble_steady(self._h, _ptr_array(U, "U"), _ptr_array(U_work, "U_work"), ctypes.byref(cfg),
+                                       hist.ctypes.data_as(c_void_p), steps.ctypes.data_as(c_void_p),
+                                       ctypes.byref(it), _stream(stream))
+        hist = hist[:, :int(max_iters)]
+        if rc == 4:
+            raise CfvNonPhysical(f"cfv status 4: {lib().cfv_last_error().decode()}", hist, steps)
+        check(rc)
+        return hist, steps
 
     def residual_jvp(self, U, v, R=None, Jv=None, stream=None):
         """Bind and run; returns (R, Jv) lists (allocated when not given)."""

@@ -860,6 +860,7 @@ struct cfv_ensemble {
   size_t step_arena_n = 0;
   double* step_part = nullptr;           // n x kStepBlocks partial sums
   cfv::StepLaunch step;
+  double* mon = nullptr;                 // 9 n device scalars: monitors of the batched march
 };
 
 namespace {
@@ -977,7 +978,8 @@ cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning
 void cfv_ensemble_destroy(cfv_ensemble* e) {
   if (!e) return;
   drop_graph(e);
-  void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt, e->step_args, e->step_sv, e->step_arena, e->step_part};
+  void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt, e->step_args, e->step_sv, e->step_arena, e->step_part,
+                  e->mon};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -1142,6 +1144,80 @@ cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s) {
   if (!e->exec) return fail(CFV_ERR_ARG, "no captured graph (capture after the last bind or tuning change)");
   CFV_HIP(hipGraphLaunch(e->exec, s));
   return CFV_OK;
+}
+
+cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const* U_work, const cfv_steady_cfg* cfg,
+                               double* hist, int32_t* steps, int32_t* iters, hipStream_t s) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (!U || !U_work || !cfg) return fail(CFV_ERR_ARG, "null state arrays or configuration");
+  if (!(cfg->cfl0 > 0.0) || !(cfg->cfl_max >= cfg->cfl0)) return fail(CFV_ERR_ARG, "need 0 < cfl0 <= cfl_max");
+  if (cfg->every < 1 || cfg->max_iters < 0) return fail(CFV_ERR_ARG, "need every >= 1 and max_iters >= 0");
+  if (cfg->monitor < 0 || cfg->monitor > 8) return fail(CFV_ERR_ARG, "monitor must be a variable 0..8");
+  if (cfg->m < 1 || cfg->m > 200) return fail(CFV_ERR_ARG, "need 1 <= m <= 200");
+  const size_t n = e->ctx.size();
+  for (size_t q = 0; q < n; ++q) {
+    if (!U[q] || !U_work[q]) return fail(CFV_ERR_ARG, "null pointer for instance " + std::to_string(q));
+    if (U[q] == U_work[q]) return fail(CFV_ERR_ARG, "U_work aliases U for instance " + std::to_string(q));
+  }
+  if (!e->mon)
+    if (cfv_status st = dmalloc(&e->mon, 9 * n)) return st;
+  std::vector<char> active(n, 1);
+  std::vector<int32_t> taken(n, 0);
+  std::vector<double> mon(9 * n);
+  if (hist)
+    for (size_t a = 0; a < n * size_t(cfg->max_iters) * 9; ++a) hist[a] = std::nan("");
+  cfv_status out = CFV_OK;
+  int nonphys = -1;  // first instance that produced a non-finite state
+  double bound_cfl = -1.0;
+  int32_t done = 0;
+  size_t live = n;
+  while (done < cfg->max_iters && live > 0) {
+    const double cfl = std::min(std::ldexp(cfg->cfl0, done / cfg->every), cfg->cfl_max);
+    if (cfl != bound_cfl) {  // the step's diagonal depends on the CFL: bind (and capture) again
+      if ((out = cfv_ensemble_bind_be_step(e, U, U_work, cfl, cfg->m, nullptr))) break;
+      if (s && (out = cfv_ensemble_graph_capture(e, s))) break;
+      bound_cfl = cfl;
+    }
+    out = s ? cfv_ensemble_graph_launch(e, s) : cfv_ensemble_run(e, s);
+    for (size_t q = 0; q < n && out == CFV_OK; ++q)
+      if (active[q]) out = cfv_monitor(e->ctx[q], U[q], U_work[q], e->mon + 9 * q, s);
+    if (out == CFV_OK) {
+      hipError_t he = hipMemcpyAsync(mon.data(), e->mon, 9 * n * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) out = hip_fail(he, "monitor read-back");
+    }
+    if (out != CFV_OK) break;
+    for (size_t q = 0; q < n; ++q) {
+      if (!active[q]) continue;
+      bool finite = true;
+      for (int v = 0; v < 9; ++v) {
+        const double x = std::log10(mon[9 * q + v]);
+        if (std::isnan(x) || (std::isinf(x) && x > 0.0)) finite = false;
+        if (hist) hist[(q * size_t(cfg->max_iters) + size_t(done)) * 9 + v] = x;
+      }
+      ++taken[q];
+      if (!finite) {  // keep the state before this step and stop the instance
+        if (nonphys < 0) nonphys = int(q);
+        active[q] = 0;
+        --live;
+        continue;
+      }
+      const size_t bytes = size_t(9) * size_t(e->ctx[q]->grid->g.ncells) * sizeof(double);
+      const hipError_t he = hipMemcpyAsync(U[q], U_work[q], bytes, hipMemcpyDeviceToDevice, s);
+      if (he != hipSuccess) return hip_fail(he, "state update");
+      if (std::log10(mon[9 * q + cfg->monitor]) < cfg->target) {
+        active[q] = 0;
+        --live;
+      }
+    }
+    ++done;
+  }
+  if (steps)
+    for (size_t q = 0; q < n; ++q) steps[q] = taken[q];
+  if (iters) *iters = done;
+  if (out == CFV_OK && nonphys >= 0)
+    out = fail(CFV_ERR_NONPHYSICAL, "instance " + std::to_string(nonphys) + " produced a non-finite state");
+  return out;
 }
 
 cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on) {

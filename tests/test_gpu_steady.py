@@ -108,3 +108,52 @@ def test_steady_step_is_the_backward_euler_step_medium():
     assert torch.equal(U1, Ube)
     mon = [math.log10(x) for x in ctx.monitor(U0, U1).cpu().tolist()]
     assert hist[0].tolist() == mon and list(cfls) == [2.0]
+
+
+def ensemble_cases():
+    cases = [perturbed_parker(4, 6, seed=1), perturbed_parker(3, 5, seed=4), perturbed_parker(5, 4, seed=6)]
+    return [(g, U, br, context(g, br, 1.05, 0)) for g, U, br in cases]
+
+
+def test_ensemble_steady_matches_single_instance_marches():
+    """The batched march (lockstep steps, captured graph) follows each
+    instance's own march: states 1e-8, log10 monitors 1e-8 (one lockstep step
+    agrees with cfv_be_step to about 4e-15; six unconverged GMRES(12) steps
+    grow that to about 2e-10 in psi, the smallest variable); the eager path
+    (default stream) gives the graph path's bits; instances stop on their own."""
+    print("case: ensemble steady march, 3 perturbed Parker winds", flush=True)
+    from paper_2209_04481_amd import Ensemble
+    cases = ensemble_cases()
+    kw = dict(cfl0=2.0, cfl_max=128.0, every=2, m=12)
+    singles = []
+    for g, U, br, ctx in cases:
+        Us = U.cuda()
+        h, _ = ctx.steady(Us, 6, **kw)
+        singles.append((Us, h))
+    ens = Ensemble([c[3] for c in cases])
+    Ue = [c[1].cuda() for c in cases]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        he, steps = ens.steady(Ue, 6, stream=side, **kw)
+    side.synchronize()
+    assert list(steps) == [6, 6, 6]
+    for q, (Us, h) in enumerate(singles):
+        assert float(rel_err_per_var(Ue[q].cpu(), Us.cpu()).max()) <= 1e-8
+        assert float(np.abs(he[q] - h).max()) <= 1e-8
+    # eager path on the default stream: the same bits as the captured graph
+    Ug = [c[1].cuda() for c in cases]
+    hg, _ = ens.steady(Ug, 6, **kw)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Ug, Ue)) and np.array_equal(hg, he)
+    # per-instance stopping on the density monitor: each stops where its own march does
+    tgt = float(np.median(he[:, 2, 0]))
+    Ut = [c[1].cuda() for c in cases]
+    ht, st = ens.steady(Ut, 6, monitor=0, target=tgt, **kw)
+    torch.cuda.synchronize()
+    for q, (g, U, br, ctx) in enumerate(cases):
+        Us = U.cuda()
+        h, _ = ctx.steady(Us, 6, monitor=0, target=tgt, **kw)
+        assert st[q] == len(h)
+        assert float(rel_err_per_var(Ut[q].cpu(), Us.cpu()).max()) <= 1e-8
+        assert np.isnan(ht[q, st[q]:]).all() and not np.isnan(ht[q, :st[q]]).any()
+    assert len(set(st.tolist())) > 1
