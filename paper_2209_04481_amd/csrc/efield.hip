@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kEB) void efield_kernel(DevGrid d, const double* __
     const int64_t col = (t - layer * nchunk) * kEB + threadIdx.x;
     if (col >= plane) continue;
     const int p = int(layer / d.g.Nr), k = int(layer - int64_t(p) * d.g.Nr);
-    const int j = int(col / d.g.N), i = int(col - int64_t(j) * d.g.N);
+    const int col32 = int(col);  // a column index of one panel: below N^2
+    const int j = col32 / d.g.N, i = col32 - j * d.g.N;
     const int64_t c = layer * plane + col;
     const double rho = U[c];
     const V3 v = mk(U[nc + c] / rho, U[2 * nc + c] / rho, U[3 * nc + c] / rho);
@@ -146,7 +147,7 @@ hipError_t launch_efield(const DevGrid& d, const double* U, double* E3, double* 
 
 hipError_t launch_efree(int64_t nc, double gamma, const double* U, double* Uo, hipStream_t s, KernelTimer* t) {
   int64_t blocks = (nc + kEB - 1) / kEB;
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > 65535) blocks = 65535;
   if (blocks < 1) blocks = 1;
   TimedScope ts(t, "efree", s);
   hipLaunchKernelGGL(efree_kernel, dim3(unsigned(blocks)), dim3(kEB), 0, s, nc, gamma, U, Uo);

@@ -62,3 +62,5 @@ def test_grid_sizes_and_argument_errors(built):
         Grid(6, 4, np.array([1.0, 2.0, 2.0, 3.0, 4.0]))   # not strictly increasing
     with pytest.raises(CfvError):
         Grid(1, 4, ci.radial_nodes(4, "log"))
+    with pytest.raises(CfvError, match="16384"):
+        Grid(16385, 1, ci.radial_nodes(1, "log"))
