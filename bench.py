@@ -355,6 +355,17 @@ def main():
     ctx.timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
 
+    # per-operation spread: the same steps again, the library's event times read after each one
+    ctx.timing_enable(True)
+    ctx.timing_read()
+    per_step = {op: [] for op in OP_KERNELS}
+    for _ in range(args.steps):
+        step()
+        t_step = ctx.timing_read()
+        for op, ks in OP_KERNELS.items():
+            per_step[op].append(sum(t_step[k][0] for k in ks if k in t_step))
+    ctx.timing_enable(False)
+
     nc = inst.ncells
     per_kernel = {k: {"avg_ms": ms / n, "launches": n} for k, (ms, n) in times.items()}
     op_ms = {}
@@ -387,6 +398,8 @@ def main():
         "jvp_per_s": round(1e3 / op_ms["jvp"], 2),
         "vjp_per_s": round(1e3 / op_ms["vjp"], 2),
         "op_ms": {k: round(x, 4) for k, x in op_ms.items()},
+        "op_ms_p10_p50_p90": {op: [round(float(np.percentile(v, q)), 4) for q in (10, 50, 90)]
+                              for op, v in per_step.items()},
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
     }
