@@ -19,6 +19,7 @@ struct MarchArgs {
   double* R;          // residual (nullable for Dual)
   double* Rd;         // tangent of the residual (Dual only)
   double* P = nullptr;  // primitives [9][ncells] written by the gradient pass (nullable)
+  double* Q = nullptr;  // face states [6 x 9][ncells] (row 9 lf + v) written by the face-state gradient pass
 };
 
 struct TileMap {
@@ -193,6 +194,10 @@ struct GradWG {
     }
   }
 
+  // Faces: also write the reconstructed face states to a.Q (the VJP's
+  // forward pass; a separate instantiation so that the residual's pass does
+  // not carry the stores' registers)
+  template <bool Faces = false>
   __host__ __device__ static void compute(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
                                           double* lds) {
     if (!st.act) return;
@@ -248,6 +253,11 @@ struct GradWG {
       stT(a.G, a.Gd, (3 * v) * g.ncells + c, gx);
       stT(a.G, a.Gd, (3 * v + 1) * g.ncells + c, gy);
       stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
+      if constexpr (Faces) {  // the reconstructed state at each face centroid
+#pragma unroll
+        for (int lf = 0; lf < 6; ++lf)
+          a.Q[(9 * lf + v) * g.ncells + c] = val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z));
+      }
     }
     for (int v = 0; v < 9; ++v) {
       st.Pm[v] = st.P0[v];

@@ -26,7 +26,7 @@ namespace cfv {
 // --------------------------------------------------------------- device glue
 // One (tile, chunk) of each pass; the single-instance kernels run one per
 // workgroup, the ensemble kernels (ensemble.hip) loop over a queue of them.
-template <class T>
+template <class T, bool Faces = false>
 __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMap& tm, double* lds) {
   const int t = threadIdx.x;
   GState<T> st;
@@ -34,7 +34,7 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   for (int k = tm.k0; k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
     __syncthreads();
-    GradWG<T>::compute(a, tm, st, t, k, lds);
+    GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
     __syncthreads();
   }
 }
@@ -115,7 +115,7 @@ struct MarchOccupancy {
   static constexpr int value = sizeof(T) == sizeof(double) ? 2 : 1;
 };
 
-template <class T, bool Flux>
+template <class T, bool Flux, bool Faces = false>
 __global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_ensemble_kernel(EnsembleLaunch e) {
   constexpr int kL = Flux ? FluxWG<T>::kLds : GradWG<T>::kLds;
   __shared__ double lds[kL];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_e
     if (Flux)
       flux_march_tile<T>(a, tm, lds);
     else
-      grad_march_tile<T>(a, tm, lds);
+      grad_march_tile<T, Faces>(a, tm, lds);
   }
 }
 
@@ -187,7 +187,10 @@ hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, hipStream_t s,
   const int64_t total = march_logical_blocks(a.d.g);
   EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
   TimedScope ts(t, "grad_march_fwd", s);
-  hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  if (a.Q)
+    hipLaunchKernelGGL((march_ensemble_kernel<double, false, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  else
+    hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
   return hipGetLastError();
 }
 

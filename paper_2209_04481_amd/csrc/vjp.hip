@@ -24,7 +24,8 @@ namespace cfv {
 
 static constexpr int kVBlock = 256;
 
-int64_t vjp_workspace_doubles(const Shape& g) { return int64_t(63) * g.ncells; }
+// 63 adjoint rows, then the 54 face-state rows of the forward pass
+int64_t vjp_workspace_doubles(const Shape& g) { return int64_t(63 + 54) * g.ncells; }
 
 // Adjoint of the ghost law for the ghost of boundary cell (p,k,j,i) across
 // face lf: accumulates (dqG/dqI)^T qGb into qIb and returns (dqG/dbr)^T qGb,
@@ -58,12 +59,14 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 // consecutive cells [c0, c0 + 256) have their workspace rows and weights in
 // LDS (lW, lw); neighbours inside that window are read from there (nearly
 // all of the i +- 1 and most of the j +- 1 neighbours), the others from
-// global memory.  Most of this pass's time is neighbour loads at one
-// wavefront per SIMD.
+// global memory, where the forward pass also left each cell's six
+// reconstructed face states (Q): 9 loads for the neighbour's state on a face
+// instead of its 36 primitives and gradients.  Most of this pass's time is
+// neighbour loads at one wavefront per SIMD.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
-                                             const double* __restrict__ W, double* __restrict__ A,
-                                             double* __restrict__ gbr, int64_t c, const double* lW,
-                                             const double* lw, int64_t c0) {
+                                             const double* __restrict__ W, const double* __restrict__ Q,
+                                             double* __restrict__ A, double* __restrict__ gbr, int64_t c,
+                                             const double* lW, const double* lw, int64_t c0) {
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
   decode(d.g, c, p, k, j, i);
@@ -134,10 +137,22 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       }
     } else {
       const int64_t o = nb.id;
-      const V3 dn = xf - xn;
+      // the neighbour's state on this face: reconstructed from the LDS window
+      // when the neighbour is in it, else as the forward pass stored it
+      const int64_t lo = o - c0;
+      if (lo >= 0 && lo < kVBlock) {
+        const V3 dn = xf - xn;
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+          qo[v] = lW[v * kVBlock + lo] + (lW[(9 + 3 * v) * kVBlock + lo] * dn.x +
+                                          lW[(10 + 3 * v) * kVBlock + lo] * dn.y +
+                                          lW[(11 + 3 * v) * kVBlock + lo] * dn.z);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 9; ++v) qo[v] = Q[(9 * nb.back + v) * nc + o];
+      }
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        qo[v] = Wr(v, o) + (Wr(9 + 3 * v, o) * dn.x + Wr(10 + 3 * v, o) * dn.y + Wr(11 + 3 * v, o) * dn.z);
         const double wn = wr(v, o);
         wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
       }
@@ -289,8 +304,8 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
 }
 
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
-                                                          const double* __restrict__ W, double* __restrict__ A,
-                                                          double* __restrict__ gbr) {
+                                                          const double* __restrict__ W, const double* __restrict__ Q,
+                                                          double* __restrict__ A, double* __restrict__ gbr) {
   __shared__ double lW[36 * kVBlock];
   __shared__ double lw[9 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
@@ -302,7 +317,7 @@ __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double*
     for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = w[r * nc + c];
   }
   __syncthreads();
-  if (c < nc) adjoint_cell(d, w, W, A, gbr, c, lW, lw, c0);
+  if (c < nc) adjoint_cell(d, w, W, Q, A, gbr, c, lW, lw, c0);
 }
 
 __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double* __restrict__ U,
@@ -317,13 +332,15 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
   // pass 1: the forward gradient march writes the primitives (rows 0..8) and
-  // the limited gradients (rows 9..35) of W
-  MarchArgs fa{d, U, nullptr, nullptr, W + 9 * nc, nullptr, nullptr, nullptr, W};
+  // the limited gradients (rows 9..35) of W, and the face states into the
+  // workspace's last 54 rows
+  double* Q = A + int64_t(63) * nc;
+  MarchArgs fa{d, U, nullptr, nullptr, W + 9 * nc, nullptr, nullptr, nullptr, W, Q};
   hipError_t e = launch_march_grad(fa, slot, s, t);
   if (e != hipSuccess) return e;
   {
     TimedScope ts(t, "adjoint", s);
-    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, A, gbr);
+    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, Q, A, gbr);
   }
   {
     TimedScope ts(t, "adjoint_gather", s);
