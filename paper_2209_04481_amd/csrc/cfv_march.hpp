@@ -194,9 +194,9 @@ struct GradWG {
     }
   }
 
-  // Faces: also write the reconstructed face states to a.Q (the VJP's
-  // forward pass; a separate instantiation so that the residual's pass does
-  // not carry the stores' registers)
+  // Faces: write the reconstructed face states to a.Q instead of the
+  // gradients to a.G (the VJP's forward pass; a separate instantiation so
+  // that the residual's pass does not carry the stores' registers)
   template <bool Faces = false>
   __host__ __device__ static void compute(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
                                           double* lds) {
@@ -250,10 +250,11 @@ struct GradWG {
       for (int q = 0; q < 4; ++q) qn[2 + q] = L[v * kPlane + pos[q]];
       T gx, gy, gz;
       limited_grad(W, dxf, a.d.pr.limiter, st.P0[v], qn, gx, gy, gz);
-      stT(a.G, a.Gd, (3 * v) * g.ncells + c, gx);
-      stT(a.G, a.Gd, (3 * v + 1) * g.ncells + c, gy);
-      stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
-      if constexpr (Faces) {  // the reconstructed state at each face centroid
+      if constexpr (!Faces) {
+        stT(a.G, a.Gd, (3 * v) * g.ncells + c, gx);
+        stT(a.G, a.Gd, (3 * v + 1) * g.ncells + c, gy);
+        stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
+      } else {  // instead of the gradient, the reconstructed state at each face centroid
 #pragma unroll
         for (int lf = 0; lf < 6; ++lf)
           a.Q[(9 * lf + v) * g.ncells + c] = val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z));

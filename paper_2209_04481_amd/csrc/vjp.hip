@@ -57,12 +57,12 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 // arrays would live in scratch memory): face loops either unroll or branch on
 // the face id before touching per-face arrays.  The workgroup's 256
 // consecutive cells [c0, c0 + 256) have their workspace rows and weights in
-// LDS (lW, lw); neighbours inside that window are read from there (nearly
-// all of the i +- 1 and most of the j +- 1 neighbours), the others from
-// global memory, where the forward pass also left each cell's six
-// reconstructed face states (Q): 9 loads for the neighbour's state on a face
-// instead of its 36 primitives and gradients.  Most of this pass's time is
-// neighbour loads at one wavefront per SIMD.
+// LDS (lW: primitives and the six reconstructed face states the forward pass
+// left in Q; lw: weights); neighbours inside that window are read from there
+// (nearly all of the i +- 1 and most of the j +- 1 neighbours), the others
+// from global memory.  A neighbour's state on a shared face is its stored
+// face state: 9 values instead of its 36 primitives and gradients.  Most of
+// this pass's time is neighbour loads at one wavefront per SIMD.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, const double* __restrict__ Q,
                                              double* __restrict__ A, double* __restrict__ gbr, int64_t c,
@@ -80,6 +80,11 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   auto wr = [&](int row, int64_t id) -> double {
     const int64_t l = id - c0;
     return (l >= 0 && l < kVBlock) ? lw[row * kVBlock + l] : w[row * nc + id];
+  };
+  // state of cell id on its local face lf, as the forward pass reconstructed it
+  auto Qr = [&](int lf, int v, int64_t id) -> double {
+    const int64_t l = id - c0;
+    return (l >= 0 && l < kVBlock) ? lW[(9 + 9 * lf + v) * kVBlock + l] : Q[(9 * lf + v) * nc + id];
   };
   double Pc[9], wc[9];
 #pragma unroll
@@ -127,8 +132,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     dx[lf] = xn - xc;
     double qs[9], qo[9], wb[9];
 #pragma unroll
-    for (int v = 0; v < 9; ++v)
-      qs[v] = Pc[v] + (Wr(9 + 3 * v, c) * ds.x + Wr(10 + 3 * v, c) * ds.y + Wr(11 + 3 * v, c) * ds.z);
+    for (int v = 0; v < 9; ++v) qs[v] = Qr(lf, v, c);
     if (ghost) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
@@ -137,22 +141,10 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       }
     } else {
       const int64_t o = nb.id;
-      // the neighbour's state on this face: reconstructed from the LDS window
-      // when the neighbour is in it, else as the forward pass stored it
-      const int64_t lo = o - c0;
-      if (lo >= 0 && lo < kVBlock) {
-        const V3 dn = xf - xn;
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-          qo[v] = lW[v * kVBlock + lo] + (lW[(9 + 3 * v) * kVBlock + lo] * dn.x +
-                                          lW[(10 + 3 * v) * kVBlock + lo] * dn.y +
-                                          lW[(11 + 3 * v) * kVBlock + lo] * dn.z);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 9; ++v) qo[v] = Q[(9 * nb.back + v) * nc + o];
-      }
+      // the neighbour's state on this face, as the forward pass reconstructed it
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
+        qo[v] = Qr(nb.back, v, o);
         const double wn = wr(v, o);
         wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
       }
@@ -306,13 +298,14 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, const double* __restrict__ Q,
                                                           double* __restrict__ A, double* __restrict__ gbr) {
-  __shared__ double lW[36 * kVBlock];
+  __shared__ double lW[63 * kVBlock];  // primitives (9 rows), then the face states (54)
   __shared__ double lw[9 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
   const int64_t nc = d.g.ncells;
   const int64_t c0 = int64_t(blockIdx.x) * kVBlock, c = c0 + threadIdx.x;
   if (c < nc) {
-    for (int r = 0; r < 36; ++r) lW[r * kVBlock + threadIdx.x] = W[r * nc + c];
+    for (int r = 0; r < 9; ++r) lW[r * kVBlock + threadIdx.x] = W[r * nc + c];
+    for (int r = 0; r < 54; ++r) lW[(9 + r) * kVBlock + threadIdx.x] = Q[r * nc + c];
 #pragma unroll
     for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = w[r * nc + c];
   }
@@ -331,11 +324,11 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
                       double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
-  // pass 1: the forward gradient march writes the primitives (rows 0..8) and
-  // the limited gradients (rows 9..35) of W, and the face states into the
-  // workspace's last 54 rows
+  // pass 1: the forward gradient march writes the primitives (rows 0..8 of
+  // W) and, instead of the limited gradients, the face states they give
+  // (the workspace's last 54 rows)
   double* Q = A + int64_t(63) * nc;
-  MarchArgs fa{d, U, nullptr, nullptr, W + 9 * nc, nullptr, nullptr, nullptr, W, Q};
+  MarchArgs fa{d, U, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, Q};
   hipError_t e = launch_march_grad(fa, slot, s, t);
   if (e != hipSuccess) return e;
   {
