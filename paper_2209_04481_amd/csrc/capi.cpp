@@ -32,11 +32,12 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* 
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
                       double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
-hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y, hipStream_t s);
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
 hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s);
 hipError_t launch_lincomb(int64_t n, int k, const double* y, const double* V, double* x, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s);
+hipError_t launch_axpy_dot(int64_t n, const double* coef, const double* x, double* w, const double* y, double* out,
+                           double* part, hipStream_t s);
 hipError_t launch_absmax(int64_t n, int nvar, const double* a, double* out, double* part, hipStream_t s);
 hipError_t launch_ratio_max(int64_t n, int nvar, const double* x, const double* u, const double* sv, double* out,
                             double* part, hipStream_t s);
@@ -555,12 +556,13 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
     for (int j = 0; j < m; ++j) {
       double* vj = V + size_t(j) * n;
       if (cfv_status st = apply_operator(c, U, diag, transpose, vj, w, s)) return st;
-      // modified Gram-Schmidt: coefficients stay on the device
-      for (int i = 0; i <= j; ++i) {
-        CFV_HIP(cfv::launch_dots(n, V + size_t(i) * n, 1, w, hd + i, c->part, s));
-        CFV_HIP(cfv::launch_axpy_dev(n, hd + i, -1.0, V + size_t(i) * n, w, s));
-      }
-      CFV_HIP(cfv::launch_norm2(n, w, hd + j + 1, c->part, s));
+      // modified Gram-Schmidt, coefficients on the device: h_0 = <w, V_0>, then
+      // each update w -= h_i V_i is fused with the next projection
+      // h_{i+1} = <w, V_{i+1}> (for i = j: the norm of w)
+      CFV_HIP(cfv::launch_dots(n, V, 1, w, hd, c->part, s));
+      for (int i = 0; i <= j; ++i)
+        CFV_HIP(cfv::launch_axpy_dot(n, hd + i, V + size_t(i) * n, w, i < j ? V + size_t(i + 1) * n : nullptr,
+                                     hd + i + 1, c->part, s));
       CFV_HIP(hipMemcpyAsync(col.data(), hd, size_t(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       CFV_HIP(hipStreamSynchronize(s));
       for (int i = 0; i <= j + 1; ++i) Hc(i, j) = col[i];

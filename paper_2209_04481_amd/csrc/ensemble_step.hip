@@ -100,13 +100,24 @@ __global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __res
   STEP_LOOP(n9) v.w[e] += v.diag[e % v.nc] * x[e];
 }
 
-// w -= sm[slot] V_i (modified Gram-Schmidt)
-__global__ __launch_bounds__(kSB) void step_axpy_kernel(const StepVec* __restrict__ sv, int i, int slot) {
+// w -= sm[slot] V_i fused with the next projection: partial sums of the
+// updated w times V_next (next >= 0) or times itself (next < 0, the norm)
+__global__ __launch_bounds__(kSB) void step_axpy_dot_kernel(const StepVec* __restrict__ sv, int i, int slot, int next,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[kSB / 64];
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const double h = v.sm[slot];
   const double* x = v.V + int64_t(i) * n9;
-  STEP_LOOP(n9) v.w[e] -= h * x[e];
+  const double* y = next >= 0 ? v.V + int64_t(next) * n9 : nullptr;
+  double s = 0.0;
+  STEP_LOOP(n9) {
+    const double wn = v.w[e] - h * x[e];
+    v.w[e] = wn;
+    s += (y ? y[e] : wn) * wn;
+  }
+  const double t = block_sum_step(s, sh);
+  if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
 }
 
 // column j of H is in sm[hcol + 0..j+1]: rotate it, append the new rotation,
@@ -195,13 +206,16 @@ hipError_t launch_ensemble_step(const StepLaunch& L, hipStream_t s, KernelTimer*
     }
     TimedScope ts(t, "step_krylov", s);
     hipLaunchKernelGGL(step_add_diag_kernel, vgrid, dim3(kSB), 0, s, L.sv, j);
+    // modified Gram-Schmidt: h_0 = <w, V_0>, then each update fused with the
+    // next projection (for i = j: the norm of w)
+    hipLaunchKernelGGL(step_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, 0, L.part);
+    hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol, 0);
     for (int i = 0; i <= j; ++i) {
-      hipLaunchKernelGGL(step_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, i, L.part);
-      hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol + i, 0);
-      hipLaunchKernelGGL(step_axpy_kernel, vgrid, dim3(kSB), 0, s, L.sv, i, Y.hcol + i);
+      hipLaunchKernelGGL(step_axpy_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, i, Y.hcol + i, i < j ? i + 1 : -1,
+                         L.part);
+      hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol + i + 1,
+                         i < j ? 0 : 1);
     }
-    hipLaunchKernelGGL(step_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, -1, L.part);
-    hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol + j + 1, 1);
     hipLaunchKernelGGL(step_scale_kernel, vgrid, dim3(kSB), 0, s, L.sv, j, Y.hcol + j + 1);
     hipLaunchKernelGGL(step_givens_kernel, dim3(tgrid), dim3(64), 0, s, L.sv, L.n, L.m, j, L.hist);
   }

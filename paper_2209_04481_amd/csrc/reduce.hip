@@ -129,12 +129,23 @@ __global__ __launch_bounds__(kRBlock) void axpby_kernel(int64_t n, double a, con
     y[c] = a * x[c] + b * y[c];
 }
 
-// y += sign * (*coef) * x   (coefficient read from device memory)
-__global__ __launch_bounds__(kRBlock) void axpy_dev_kernel(int64_t n, const double* __restrict__ coef, double sign,
-                                                           const double* __restrict__ x, double* __restrict__ y) {
-  const double a = sign * coef[0];
-  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(gridDim.x) * kRBlock)
-    y[c] += a * x[c];
+// One modified Gram-Schmidt update fused with the next projection:
+// w -= (*coef) x, and part[block] = sum over the block's entries of the
+// updated w times y (y null: times w itself, for the norm).  The entries of a
+// block are those of dot_partials, so the sums fold in the same order.
+__global__ __launch_bounds__(kRBlock) void axpy_dot_partials(int64_t n, const double* __restrict__ coef,
+                                                             const double* __restrict__ x, double* __restrict__ w,
+                                                             const double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double sh[kRBlock / 64];
+  const double a = -coef[0];
+  double s = 0.0;
+  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock) {
+    const double wn = w[c] + a * x[c];
+    w[c] = wn;
+    s += (y ? y[c] : wn) * wn;
+  }
+  const double t = block_sum<kRBlock>(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // y = x / (*den)
@@ -168,11 +179,6 @@ static unsigned stream_blocks(int64_t n) {
   if (b > 65536) b = 65536;
   if (b < 1) b = 1;
   return unsigned(b);
-}
-
-hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_dev_kernel, dim3(stream_blocks(n)), dim3(kRBlock), 0, s, n, coef, sign, x, y);
-  return hipGetLastError();
 }
 
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s) {
@@ -214,6 +220,13 @@ hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* ou
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s) {
   hipLaunchKernelGGL(dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, V, k, w, part);
   hipLaunchKernelGGL(fold_partials, dim3(k), dim3(kRBlock), 0, s, part, k, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dot(int64_t n, const double* coef, const double* x, double* w, const double* y, double* out,
+                           double* part, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, coef, x, w, y, part);
+  hipLaunchKernelGGL(fold_partials, dim3(1), dim3(kRBlock), 0, s, part, 1, out, y ? 0 : 1);
   return hipGetLastError();
 }
 
