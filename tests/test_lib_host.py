@@ -64,3 +64,13 @@ def test_grid_sizes_and_argument_errors(built):
         Grid(1, 4, ci.radial_nodes(4, "log"))
     with pytest.raises(CfvError, match="16384"):
         Grid(16385, 1, ci.radial_nodes(1, "log"))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(here, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
