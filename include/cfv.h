@@ -4,10 +4,12 @@
  * The library evaluates, on one GPU and in FP64, the finite-volume residual
  * of ideal MHD with hyperbolic divergence cleaning on a spherical shell (the
  * discretisation of Brchnelova et al., "To E or not to E", Section 2.1 and
- * Eqs. 14-17), with the paper's low-E inner boundary (Section 3.2, Eq. 25)
- * and the Table 2 outer ghost laws (Section 4.1), its exact Jacobian-vector
- * product and its adjoint (vector-Jacobian product), and the pieces of the
- * implicit backward-Euler pseudo-time step (Section 2.1).
+ * Eqs. 14-17), with the paper's low-E and large-E inner boundaries (Section
+ * 3.2, Eqs. 20-25) and the Table 2 outer ghost laws (Section 4.1), its exact
+ * Jacobian-vector product and its adjoint (vector-Jacobian product), the
+ * implicit backward-Euler pseudo-time step and the march to a steady state
+ * (Sections 2.1, 4.1), batched over ensembles of shells, and the E-field
+ * diagnostic and E-free state (Sections 2.2, 3.1).
  *
  * Conventions
  *  - Every function returns cfv_status (0 = CFV_OK).  On failure
@@ -16,8 +18,13 @@
  *  - Device buffers are owned by the caller and passed as plain pointers to
  *    FP64 data on the current device.  The library owns its grid tables, the
  *    B_r map copy and its workspaces (allocated at cfv_ctx_create).
- *  - All device work is enqueued asynchronously on the hipStream_t given;
- *    only the *_to_host functions synchronise.
+ *  - All device work is enqueued asynchronously on the hipStream_t given.
+ *    The *_to_host functions, the solver entry points (cfv_solve,
+ *    cfv_be_step, cfv_vjp_dir, cfv_jvp_dir, cfv_steady, cfv_ensemble_steady)
+ *    and cfv_timing_read synchronise that stream, as each one states.
+ *  - A context's workspaces are shared by all calls on it: calls on one
+ *    context (or on an ensemble and its contexts) must be ordered, by one
+ *    stream or by synchronisation between streams.
  *  - State layout (SoA): U[v*ncells + c] with v = 0..8 the conservative
  *    variables (rho, rho vx, rho vy, rho vz, Bx, By, Bz, E, psi), nondimensional
  *    (rho_ref, B_ref of Eq. 1, V_ref = B_ref/sqrt(mu0 rho_ref), lengths in R_sun).
