@@ -26,14 +26,14 @@ __device__ __forceinline__ const A& first_kernel_arg() {
 }
 
 // load/store a scalar of type T from a value array and (for Dual) a tangent array
-__host__ __device__ __forceinline__ void ldT(const double* a, const double*, int64_t i, double& x) { x = a[i]; }
+__host__ __device__ __forceinline__ void ldT(const double* a, const double*, int64_t i, double& x) { x = gld(a, i); }
 __host__ __device__ __forceinline__ void ldT(const double* a, const double* b, int64_t i, Dual& x) {
-  x = Dual(a[i], b ? b[i] : 0.0);
+  x = Dual(gld(a, i), b ? gld(b, i) : 0.0);
 }
-__host__ __device__ __forceinline__ void stT(double* a, double*, int64_t i, double x) { a[i] = x; }
+__host__ __device__ __forceinline__ void stT(double* a, double*, int64_t i, double x) { gst(a, i, x); }
 __host__ __device__ __forceinline__ void stT(double* a, double* b, int64_t i, Dual x) {
-  a[i] = x.v;
-  b[i] = x.d;
+  gst(a, i, x.v);
+  gst(b, i, x.d);
 }
 
 // Ghost primitives of boundary cell (p,k,j,i) across local face lf (0 inner,
@@ -46,7 +46,7 @@ __host__ __device__ __forceinline__ void ghost_prims(const DevGrid& d, int p, in
   xG = ghost_centre(xI, S, xf);
   if (lf == 0) {
     if (d.pr.inner_mode == 1)
-      inner_ghost_large_e(qI, xf, br, d.bth[column_of(d.g, p, j, i)], qG, d.pr);
+      inner_ghost_large_e(qI, xf, br, gld(d.bth, column_of(d.g, p, j, i)), qG, d.pr);
     else
       inner_ghost(qI, xf, br, qG, d.pr);
   } else {

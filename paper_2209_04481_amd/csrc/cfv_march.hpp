@@ -159,7 +159,7 @@ struct GradWG {
       dir_offset(q, dx, dy);
       if (in_tile_active(g, tm, ti + dx, tj + dy)) continue;
       st.remote |= 1u << q;
-      const V3 cn = cg3(G, CG_CSUM, G.cn[q * G.ncol + st.col]);
+      const V3 cn = cg3(G, CG_CSUM, gld(G.cn, q * G.ncol + st.col));
       const int pos = plane_pos(ti + dx, tj + dy);
       cs[pos] = cn.x; cs[kPlane + pos] = cn.y; cs[2 * kPlane + pos] = cn.z;
     }
@@ -179,14 +179,14 @@ struct GradWG {
     for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
     if (a.P) {
       const int64_t c = cell_index(g, st.p, k, st.j, st.i);
-      for (int v = 0; v < 9; ++v) a.P[v * g.ncells + c] = val(st.P0[v]);
+      for (int v = 0; v < 9; ++v) gst(a.P, v * g.ncells + c, val(st.P0[v]));
     }
     for (int q = 0; q < 4; ++q) {
       if (!(st.remote & (1u << q))) continue;
       int dx, dy;
       dir_offset(q, dx, dy);
       int np, nj, ni;
-      column_pji(g, G.cn[q * G.ncol + st.col], np, nj, ni);
+      column_pji(g, gld(G.cn, q * G.ncol + st.col), np, nj, ni);
       T qn[9];
       load_prims(a, cell_index(g, np, k, nj, ni), qn);
       const int pos = plane_pos(ti + dx, tj + dy);
@@ -206,7 +206,7 @@ struct GradWG {
     const T* L = lds_as<T>(lds);
     const double* cs = lds + 9 * kPlane * kTw;
     const int ti = t % kTI, tj = t / kTI;
-    const double rs = 0.125 * (G.r[k] + G.r[k + 1]);
+    const double rs = 0.125 * (gld(G.r, k) + gld(G.r, k + 1));
     const V3 xc = rs * cg3(G, CG_CSUM, st.col);
     // geometry: neighbour offsets and face-centroid offsets
     V3 dx[6], dxf[6];
@@ -257,7 +257,7 @@ struct GradWG {
       } else {  // instead of the gradient, the reconstructed state at each face centroid
 #pragma unroll
         for (int lf = 0; lf < 6; ++lf)
-          a.Q[(9 * lf + v) * g.ncells + c] = val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z));
+          gst(a.Q, (9 * lf + v) * g.ncells + c, val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z)));
       }
     }
     for (int v = 0; v < 9; ++v) {
@@ -283,13 +283,13 @@ template <class T>
 __host__ __device__ __forceinline__ void store_res(const MarchArgs& a, int64_t c, const T r[9]);
 template <>
 __host__ __device__ __forceinline__ void store_res<double>(const MarchArgs& a, int64_t c, const double r[9]) {
-  for (int v = 0; v < 9; ++v) a.R[v * a.d.g.ncells + c] = r[v];
+  for (int v = 0; v < 9; ++v) gst(a.R, v * a.d.g.ncells + c, r[v]);
 }
 template <>
 __host__ __device__ __forceinline__ void store_res<Dual>(const MarchArgs& a, int64_t c, const Dual r[9]) {
   for (int v = 0; v < 9; ++v) {
-    if (a.R) a.R[v * a.d.g.ncells + c] = r[v].v;
-    a.Rd[v * a.d.g.ncells + c] = r[v].d;
+    if (a.R) gst(a.R, v * a.d.g.ncells + c, r[v].v);
+    gst(a.Rd, v * a.d.g.ncells + c, r[v].d);
   }
 }
 
@@ -325,7 +325,7 @@ struct FluxWG {
     load_prims(a, c, P);
     load_grad(a, c, Gr);
     const V3 xc = cell_centre(a.d.G, g, st.p, km, st.j, st.i);
-    const V3 xf = a.d.G.r[tm.k0] * cg3(a.d.G, CG_XR, st.col);
+    const V3 xf = gld(a.d.G.r, tm.k0) * cg3(a.d.G, CG_XR, st.col);
     recon(P, Gr, xf - xc, st.qtop);
   }
 
@@ -419,7 +419,7 @@ struct FluxWG {
       V3 S, xf;
       bool own;
       canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
-      const int64_t nbcol = G.cn[q * G.ncol + st.col];
+      const int64_t nbcol = gld(G.cn, q * G.ncol + st.col);
       T qs[9], qo[9], F[9];
       if (q == 1) {
         for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
@@ -456,11 +456,11 @@ struct FluxWG {
     const T* Fb = lds_as<T>(lds) + 18 * kNT;
     const int ti = t % kTI, tj = t / kTI;
     if (ti > 0) {
-      const bool own = (G.cn[4 * G.ncol + st.col] >> 8) != 0;
+      const bool own = (gld(G.cn, 4 * G.ncol + st.col) >> 8) != 0;
       for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[v * kNT + t - 1] : -Fb[v * kNT + t - 1];
     }
     if (tj > 0) {
-      const bool own = (G.cn[6 * G.ncol + st.col] >> 8) != 0;
+      const bool own = (gld(G.cn, 6 * G.ncol + st.col) >> 8) != 0;
       for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[(9 + v) * kNT + t - kTI] : -Fb[(9 + v) * kNT + t - kTI];
     }
     for (int v = 0; v < 9; ++v) st.accp[v] = st.acc[v];

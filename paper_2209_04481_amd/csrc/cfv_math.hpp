@@ -66,6 +66,29 @@ __host__ __device__ __forceinline__ Dual powd(Dual a, double e) {
 }
 __host__ __device__ __forceinline__ double powd(double a, double e) { return ::pow(a, e); }
 
+// ------------------------------------------------------- global memory access
+// Loads and stores through pointers to device (global) memory that the
+// compiler cannot prove global, because they come from descriptor tables or
+// structures: without this it emits flat instructions, which also count
+// against the LDS wait counter, so LDS waits would also wait for them.  Only
+// for pointers into device memory allocations (never LDS or stack).
+template <class T>
+__host__ __device__ __forceinline__ T gld(const T* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+#else
+  return p[i];
+#endif
+}
+template <class T>
+__host__ __device__ __forceinline__ void gst(T* p, int64_t i, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+#else
+  p[i] = v;
+#endif
+}
+
 // ------------------------------------------------------------------- vectors
 struct V3 {
   double x, y, z;

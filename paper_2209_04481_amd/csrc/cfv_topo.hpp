@@ -144,16 +144,16 @@ __host__ __device__ __forceinline__ int64_t column_of(const Shape& g, int p, int
 }
 
 __host__ __device__ __forceinline__ V3 cg3(const GeomRef& G, int comp, int64_t col) {
-  return mk(G.cg[comp * G.ncol + col], G.cg[(comp + 1) * G.ncol + col], G.cg[(comp + 2) * G.ncol + col]);
+  return mk(gld(G.cg, comp * G.ncol + col), gld(G.cg, (comp + 1) * G.ncol + col), gld(G.cg, (comp + 2) * G.ncol + col));
 }
 
 __host__ __device__ __forceinline__ V3 cell_centre(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  return (0.125 * (G.r[k] + G.r[k + 1])) * cg3(G, CG_CSUM, column_of(g, p, j, i));
+  return (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * cg3(G, CG_CSUM, column_of(g, p, j, i));
 }
 
 __host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  const double r0 = G.r[k], r1 = G.r[k + 1];
-  return (r1 * r1 * r1 - r0 * r0 * r0) * G.cg[CG_OMEGA * G.ncol + column_of(g, p, j, i)] / 3.0;
+  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+  return (r1 * r1 * r1 - r0 * r0 * r0) * gld(G.cg, CG_OMEGA * G.ncol + column_of(g, p, j, i)) / 3.0;
 }
 
 // canonical geometry of the face across local face lf of cell (p,k,j,i): the
@@ -164,7 +164,7 @@ __host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shap
                                            const Nbr&, int64_t, V3& S, V3& xf, bool& owner) {
   const int64_t col = column_of(g, p, j, i);
   if (lf < 2) {
-    const double r = G.r[k + lf];
+    const double r = gld(G.r, k + lf);
     const V3 sr = cg3(G, CG_SR, col);
     S = (r * r) * sr;
     xf = r * cg3(G, CG_XR, col);
@@ -173,10 +173,10 @@ __host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shap
     return;
   }
   const int q = lf - 2;
-  const double r0 = G.r[k], r1 = G.r[k + 1];
+  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
   S = (0.5 * (r1 * r1 - r0 * r0)) * cg3(G, CG_ANG + 6 * q, col);
   xf = (0.25 * (r0 + r1)) * cg3(G, CG_ANG + 6 * q + 3, col);
-  owner = (G.cn[(4 + q) * G.ncol + col] >> 8) != 0;
+  owner = (gld(G.cn, (4 + q) * G.ncol + col) >> 8) != 0;
 }
 
 // vector area pointing out of cell (p,k,j,i) and centroid of its face lf

@@ -73,6 +73,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const bool bin = k == 0, bout = k == d.g.Nr - 1;
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
   // rows of cells in the workgroup's window [c0, c0 + kVBlock) come from LDS
+  // (one flat load serves either memory: the select stays a single load)
   auto Wr = [&](int row, int64_t id) -> double {
     const int64_t l = id - c0;
     return (l >= 0 && l < kVBlock) ? lW[row * kVBlock + l] : W[row * nc + id];
@@ -93,7 +94,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     wc[v] = wr(v, c);
   }
   const int64_t col = column_of(d.g, p, j, i);
-  const double brc = d.br[col];
+  const double brc = gld(d.br, col);
 
   // ---- ghost states, then per face: geometry once and the flux adjoint for
   // this cell's side (and the ghost side); the face loop is unrolled so that
@@ -249,20 +250,20 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       if (bin) PbGin[v2] += o[0];
       if (bout) PbGout[v2] += o[1];
     }
-    A[(9 + v) * nc + c] = bin ? 0.0 : o[0];
-    A[(18 + v) * nc + c] = bout ? 0.0 : o[1];
+    gst(A, (9 + v) * nc + c, bin ? 0.0 : o[0]);
+    gst(A, (18 + v) * nc + c, bout ? 0.0 : o[1]);
 #pragma unroll
-    for (int lf = 2; lf < 6; ++lf) A[(9 + 9 * lf + v) * nc + c] = o[lf];
+    for (int lf = 2; lf < 6; ++lf) gst(A, (9 + 9 * lf + v) * nc + c, o[lf]);
   }
 
   // ---- ghost laws back onto the cell and the B_r map
   if (bin) {
     const double brb = ghost_adjoint(d, p, k, j, i, 0, Pc, xc, brc, PbGin, Pb);
-    if (gbr) gbr[col] = brb;
+    if (gbr) gst(gbr, col, brb);
   }
   if (bout) (void)ghost_adjoint(d, p, k, j, i, 1, Pc, xc, 0.0, PbGout, Pb);
 #pragma unroll
-  for (int v = 0; v < 9; ++v) A[v * nc + c] = Pb[v];
+  for (int v = 0; v < 9; ++v) gst(A, v * nc + c, Pb[v]);
 }
 
 __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __restrict__ U,
