@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kSB) void step_negate_norm_kernel(const StepVec* __
   const int64_t n9 = 9 * v.nc;
   double s = 0.0;
   STEP_LOOP(n9) {
-    const double r = -v.Unew[e];
-    v.Unew[e] = r;
+    const double r = -gld(v.Unew, e);
+    gst(v.Unew, e, r);
     s += r * r;
   }
   const double t = block_sum_step(s, sh);
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kSB) void step_dot_kernel(const StepVec* __restrict
   const int64_t n9 = 9 * v.nc;
   const double* a = i >= 0 ? v.V + int64_t(i) * n9 : v.w;
   double s = 0.0;
-  STEP_LOOP(n9) s += a[e] * v.w[e];
+  STEP_LOOP(n9) s += gld(a, e) * gld(v.w, e);
   const double t = block_sum_step(s, sh);
   if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
 }
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kSB) void step_scale_kernel(const StepVec* __restri
   const double den = v.sm[slot];
   const double* src = j < 0 ? v.Unew : v.w;
   double* dst = v.V + int64_t(j < 0 ? 0 : j + 1) * n9;
-  STEP_LOOP(n9) dst[e] = den != 0.0 ? src[e] / den : 0.0;
+  STEP_LOOP(n9) gst(dst, e, den != 0.0 ? gld(src, e) / den : 0.0);
 }
 
 // w += diag o V_j (the V/dt part of the operator)
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __res
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const double* x = v.V + int64_t(j) * n9;
-  STEP_LOOP(n9) v.w[e] += v.diag[e % v.nc] * x[e];
+  STEP_LOOP(n9) gst(v.w, e, gld(v.w, e) + gld(v.diag, e % v.nc) * gld(x, e));
 }
 
 // w -= sm[slot] V_i fused with the next projection: partial sums of the
@@ -112,9 +112,9 @@ __global__ __launch_bounds__(kSB) void step_axpy_dot_kernel(const StepVec* __res
   const double* y = next >= 0 ? v.V + int64_t(next) * n9 : nullptr;
   double s = 0.0;
   STEP_LOOP(n9) {
-    const double wn = v.w[e] - h * x[e];
-    v.w[e] = wn;
-    s += (y ? y[e] : wn) * wn;
+    const double wn = gld(v.w, e) - h * gld(x, e);
+    gst(v.w, e, wn);
+    s += (y ? gld(y, e) : wn) * wn;
   }
   const double t = block_sum_step(s, sh);
   if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
@@ -177,8 +177,8 @@ __global__ __launch_bounds__(kSB) void step_update_kernel(const StepVec* __restr
   const int k = int(v.sm[L.kdone]);
   STEP_LOOP(n9) {
     double s = 0.0;
-    for (int i = 0; i < k; ++i) s += v.sm[L.y + i] * v.V[int64_t(i) * n9 + e];
-    v.Unew[e] = v.U[e] + s;
+    for (int i = 0; i < k; ++i) s += gld(v.sm, L.y + i) * gld(v.V, int64_t(i) * n9 + e);
+    gst(v.Unew, e, gld(v.U, e) + s);
   }
 }
 
