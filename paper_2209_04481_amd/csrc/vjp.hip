@@ -87,11 +87,16 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     const int64_t l = id - c0;
     return (l >= 0 && l < kVBlock) ? lW[(9 + 9 * lf + v) * kVBlock + l] : Q[(9 * lf + v) * nc + id];
   };
+  // the LDS window holds copies of global rows, so any row may also be read
+  // from global memory: the cell itself always from LDS, radial neighbours
+  // (never in the window once a layer has 256 cells) always from global
+  // memory, angular ones from wherever they are
+  const int lc = int(c - c0);
   double Pc[9], wc[9];
 #pragma unroll
   for (int v = 0; v < 9; ++v) {
-    Pc[v] = Wr(v, c);
-    wc[v] = wr(v, c);
+    Pc[v] = lW[v * kVBlock + lc];
+    wc[v] = lw[v * kVBlock + lc];
   }
   const int64_t col = column_of(d.g, p, j, i);
   const double brc = gld(d.br, col);
@@ -133,7 +138,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     dx[lf] = xn - xc;
     double qs[9], qo[9], wb[9];
 #pragma unroll
-    for (int v = 0; v < 9; ++v) qs[v] = Qr(lf, v, c);
+    for (int v = 0; v < 9; ++v) qs[v] = lW[(9 + 9 * lf + v) * kVBlock + lc];
     if (ghost) {
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
@@ -145,8 +150,8 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       // the neighbour's state on this face, as the forward pass reconstructed it
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
-        qo[v] = Qr(nb.back, v, o);
-        const double wn = wr(v, o);
+        qo[v] = lf < 2 ? gld(Q, (9 * nb.back + v) * nc + o) : Qr(nb.back, v, o);
+        const double wn = lf < 2 ? gld(w, v * nc + o) : wr(v, o);
         wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
       }
     }
@@ -182,7 +187,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     for (int lf = 0; lf < 6; ++lf) {
       if (lf == 0 && bin) qn[lf] = qGin[v];
       else if (lf == 1 && bout) qn[lf] = qGout[v];
-      else qn[lf] = Wr(v, nid[lf]);
+      else qn[lf] = lf < 2 ? gld(W, v * nc + nid[lf]) : Wr(v, nid[lf]);
     }
     const double qc = Pc[v];
     double gx = 0.0, gy = 0.0, gz = 0.0, qmax = qc, qmin = qc;
