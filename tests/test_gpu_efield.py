@@ -77,6 +77,20 @@ def test_efree_parity(N, Nr):
     assert torch.equal(Ud.cpu(), U0)
 
 
+def test_efree_parity_other_gamma():
+    """The energy is rebuilt with the context's gamma (5/3 here)."""
+    from paper_2209_04481_amd import Context, Grid, Params
+    inst = ci.make_instance(6, 3, "log", lmax=2, seed=44)
+    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes), Params(gamma=5.0 / 3.0))
+    U = torch.tensor(inst.U)
+    U0 = ctx.efree_state(U.cuda()).cpu()
+    U0o = mhd.efree_state(U, mhd.Params(gamma=5.0 / 3.0))
+    assert float(rel_err_per_var(U0, U0o).max()) <= 1e-13
+    # with the default gamma the energy row differs
+    U0d = mhd.efree_state(U, mhd.Params())
+    assert float(rel_err_per_var(U0[7:8], U0d[7:8]).max()) > 1e-6
+
+
 def test_efield_efree_bad_arguments():
     from paper_2209_04481_amd.binding import CfvError
     inst, ctx = make(4, 2, 3)
