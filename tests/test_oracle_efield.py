@@ -151,3 +151,16 @@ def test_efree_state_of_the_paper_dipole_keeps_parallel_outflow():
     assert torch.allclose((P0[:, 1:4] * rh).sum(-1), Vr * Br * Br / B2, rtol=1e-12, atol=1e-16)
     assert torch.allclose((P0[:, 1:4] * thh).sum(-1), Vr * Br * Bt / B2, rtol=1e-12, atol=1e-16)
     assert torch.allclose((P0[:, 1:4] * phh).sum(-1), torch.zeros(n, dtype=DT), atol=1e-16)
+
+
+def test_efree_energy_is_independent_of_gamma():
+    # p is kept while V changes: the new energy is E - rho (|V|^2 - |V0|^2) / 2
+    inst = ci.make_instance(4, 3, seed=9)
+    U = torch.from_numpy(inst.U)
+    a = mhd.efree_state(U, mhd.Params(gamma=5.0 / 3.0))
+    b = mhd.efree_state(U, mhd.Params(gamma=1.05))
+    assert torch.allclose(a, b, rtol=1e-13, atol=1e-15)
+    P = mhd.cons_to_prim(U.T, 1.05)
+    P0 = mhd.cons_to_prim(a.T, 1.05)
+    want = U[7] - 0.5 * P[:, 0] * ((P[:, 1:4] ** 2).sum(-1) - (P0[:, 1:4] ** 2).sum(-1))
+    assert torch.allclose(a[7], want, rtol=1e-12, atol=1e-15)
