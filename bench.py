@@ -36,7 +36,7 @@ ALG_BYTES = {"residual": 144, "jvp": 216, "vjp": 216}
 OP_KERNELS = {
     "residual": ("grad_march", "flux_march"),
     "jvp": ("grad_march_jvp", "flux_march_jvp"),
-    "vjp": ("grad_march_fwd", "adjoint", "adjoint_gather"),
+    "vjp": ("grad_march_fwd", "adjoint", "adjoint_ghosts", "adjoint_gather"),
 }
 
 

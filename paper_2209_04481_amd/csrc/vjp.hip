@@ -11,9 +11,12 @@
 //           w_L - w_R; then the adjoint of c's reconstruction, limiter and
 //           least-squares gradient.  Contributions that land on c itself go
 //           to own[c]; those that land on face neighbour n go to out[c][f];
-//           ghost contributions are folded back through the boundary law into
-//           c and the B_r map (each ghost belongs to exactly one cell).
-//   pass 3  per cell n: Pb = own[n] + sum over the six neighbours c of
+//           those that land on a ghost state are stored for pass 3 (each
+//           ghost belongs to exactly one cell).
+//   pass 3  per boundary column: the ghost-state adjoints of pass 2 back
+//           through the boundary laws onto own[] of the boundary cells and
+//           onto the B_r map.
+//   pass 4  per cell n: Pb = own[n] + sum over the six neighbours c of
 //           out[c][face of c that faces n]; gU = (dP/dU)^T Pb minus the
 //           gravity source adjoint.
 #include "cfv_adjoint.hpp"
@@ -24,8 +27,9 @@ namespace cfv {
 
 static constexpr int kVBlock = 256;
 
-// 63 adjoint rows, then the 54 face-state rows of the forward pass
-int64_t vjp_workspace_doubles(const Shape& g) { return int64_t(63 + 54) * g.ncells; }
+// 63 adjoint rows, the 54 face-state rows of the forward pass, then the
+// adjoints of the inner and outer ghost states (2 x 9 rows of 6N^2)
+int64_t vjp_workspace_doubles(const Shape& g) { return int64_t(63 + 54) * g.ncells + 18 * g.nb; }
 
 // Adjoint of the ghost law for the ghost of boundary cell (p,k,j,i) across
 // face lf: accumulates (dqG/dqI)^T qGb into qIb and returns (dqG/dbr)^T qGb,
@@ -65,7 +69,7 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 // this pass's time is neighbour loads at one wavefront per SIMD.
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, const double* __restrict__ Q,
-                                             double* __restrict__ A, double* __restrict__ gbr, int64_t c,
+                                             double* __restrict__ A, double* __restrict__ Gg, int64_t c,
                                              const double* lW, const double* lw, int64_t c0) {
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
@@ -262,11 +266,14 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   }
 
   // ---- ghost laws back onto the cell and the B_r map
-  if (bin) {
-    const double brb = ghost_adjoint(d, p, k, j, i, 0, Pc, xc, brc, PbGin, Pb);
-    if (gbr) gst(gbr, col, brb);
-  }
-  if (bout) (void)ghost_adjoint(d, p, k, j, i, 1, Pc, xc, 0.0, PbGout, Pb);
+  // the ghost states' adjoints go back through the boundary laws in a pass
+  // of their own (ghost_fold_kernel), which keeps that code out of this one
+  if (bin)
+#pragma unroll
+    for (int v = 0; v < 9; ++v) gst(Gg, v * d.g.nb + col, PbGin[v]);
+  if (bout)
+#pragma unroll
+    for (int v = 0; v < 9; ++v) gst(Gg, (9 + v) * d.g.nb + col, PbGout[v]);
 #pragma unroll
   for (int v = 0; v < 9; ++v) gst(A, v * nc + c, Pb[v]);
 }
@@ -303,7 +310,7 @@ __host__ __device__ inline void gather_cell(const DevGrid& d, const double* __re
 
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, const double* __restrict__ Q,
-                                                          double* __restrict__ A, double* __restrict__ gbr) {
+                                                          double* __restrict__ A, double* __restrict__ Gg) {
   __shared__ double lW[63 * kVBlock];  // primitives (9 rows), then the face states (54)
   __shared__ double lw[9 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
@@ -316,7 +323,38 @@ __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double*
     for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = w[r * nc + c];
   }
   __syncthreads();
-  if (c < nc) adjoint_cell(d, w, W, Q, A, gbr, c, lW, lw, c0);
+  if (c < nc) adjoint_cell(d, w, W, Q, A, Gg, c, lW, lw, c0);
+}
+
+// Per boundary column: the adjoints of the inner and outer ghost states
+// through the boundary laws, onto the boundary cell (its own adjoint row) and
+// the B_r map.  One thread per column handles both sides in order (a one-layer
+// shell has one cell for both).
+__global__ __launch_bounds__(kVBlock) void ghost_fold_kernel(DevGrid, const double* __restrict__ W,
+                                                             const double* __restrict__ Gg, double* __restrict__ A,
+                                                             double* __restrict__ gbr) {
+  const DevGrid& d = first_kernel_arg<DevGrid>();
+  const int64_t col = int64_t(blockIdx.x) * kVBlock + threadIdx.x;
+  if (col >= d.g.nb) return;
+  const int64_t nc = d.g.ncells;
+  const int p = int(col / (int64_t(d.g.N) * d.g.N));
+  const int rest = int(col - int64_t(p) * d.g.N * d.g.N);
+  const int j = rest / d.g.N, i = rest - j * d.g.N;
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    const int k = side == 0 ? 0 : d.g.Nr - 1;
+    const int64_t c = cell_index(d.g, p, k, j, i);
+    double Pc[9], qGb[9], dPb[9];
+    for (int v = 0; v < 9; ++v) {
+      Pc[v] = W[v * nc + c];
+      qGb[v] = Gg[(9 * side + v) * d.g.nb + col];
+      dPb[v] = 0.0;
+    }
+    const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
+    const double brb = ghost_adjoint(d, p, k, j, i, side, Pc, xc, side == 0 ? gld(d.br, col) : 0.0, qGb, dPb);
+    for (int v = 0; v < 9; ++v) A[v * nc + c] += dPb[v];
+    if (side == 0 && gbr) gbr[col] = brb;
+  }
 }
 
 __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double* __restrict__ U,
@@ -334,12 +372,18 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
   // W) and, instead of the limited gradients, the face states they give
   // (the workspace's last 54 rows)
   double* Q = A + int64_t(63) * nc;
+  double* Gg = A + int64_t(63 + 54) * nc;
   MarchArgs fa{d, U, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, Q};
   hipError_t e = launch_march_grad(fa, slot, s, t);
   if (e != hipSuccess) return e;
   {
     TimedScope ts(t, "adjoint", s);
-    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, Q, A, gbr);
+    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, Q, A, Gg);
+  }
+  {
+    TimedScope ts(t, "adjoint_ghosts", s);
+    hipLaunchKernelGGL(ghost_fold_kernel, dim3(unsigned((d.g.nb + kVBlock - 1) / kVBlock)), dim3(kVBlock), 0, s, d, W,
+                       Gg, A, gbr);
   }
   {
     TimedScope ts(t, "adjoint_gather", s);
