@@ -84,7 +84,8 @@ const char* cfv_last_error(void);
 
 /* ----------------------------------------------------------------- grid --
  * Cubed-sphere shell with 6 N x N panels (2 <= N <= 16384) and Nr >= 1 radial layers between the
- * Nr+1 strictly increasing radii r_nodes (host array, copied).  Host only:
+ * Nr+1 strictly increasing radii r_nodes (host array, copied), at most 2^31 - 1 cells in all
+ * (CFV_ERR_ARG otherwise, checked before anything is allocated).  Host only:
  * builds topology (closed-form panel-edge table) and the corner directions. */
 cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_grid** out);
 void cfv_grid_destroy(cfv_grid* g);

@@ -247,6 +247,8 @@ cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_gri
   if (!out || !r_nodes) return fail(CFV_ERR_ARG, "null argument");
   if (N < 2 || Nr < 1) return fail(CFV_ERR_ARG, "need N >= 2 and Nr >= 1");
   if (N > 16384) return fail(CFV_ERR_ARG, "need N <= 16384 (per-panel column indices are 32-bit)");
+  if (6LL * N * N * Nr > 2147483647LL)
+    return fail(CFV_ERR_ARG, "need 6 N^2 Nr < 2^31 cells (one-thread-per-cell launches use 32-bit grids)");
   for (int k = 0; k < Nr; ++k)
     if (!(r_nodes[k + 1] > r_nodes[k]) || !(r_nodes[k] > 0.0))
       return fail(CFV_ERR_ARG, "r_nodes must be positive and strictly increasing");

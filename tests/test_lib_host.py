@@ -64,6 +64,8 @@ def test_grid_sizes_and_argument_errors(built):
         Grid(1, 4, ci.radial_nodes(4, "log"))
     with pytest.raises(CfvError, match="16384"):
         Grid(16385, 1, ci.radial_nodes(1, "log"))
+    with pytest.raises(CfvError, match="2\\^31"):
+        Grid(16384, 8, ci.radial_nodes(8, "log"))   # 1.3e10 cells
 
 
 def test_bench_refuses_more_than_one_gpu():
