@@ -101,7 +101,10 @@ __global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __res
 }
 
 // w -= sm[slot] V_i fused with the next projection: partial sums of the
-// updated w times V_next (next >= 0) or times itself (next < 0, the norm)
+// updated w times V_next (HasY) or times itself (the norm).  Four entries of
+// the block's strided range per pass, loads before stores, summed in entry
+// order (the same sums as one entry per pass).
+template <bool HasY>
 __global__ __launch_bounds__(kSB) void step_axpy_dot_kernel(const StepVec* __restrict__ sv, int i, int slot, int next,
                                                             double* __restrict__ part) {
   __shared__ double sh[kSB / 64];
@@ -109,12 +112,30 @@ __global__ __launch_bounds__(kSB) void step_axpy_dot_kernel(const StepVec* __res
   const int64_t n9 = 9 * v.nc;
   const double h = v.sm[slot];
   const double* x = v.V + int64_t(i) * n9;
-  const double* y = next >= 0 ? v.V + int64_t(next) * n9 : nullptr;
+  const double* y = HasY ? v.V + int64_t(next) * n9 : nullptr;
+  double* w = v.w;
+  const int64_t S = int64_t(gridDim.x) * kSB;
+  int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x;
   double s = 0.0;
-  STEP_LOOP(n9) {
-    const double wn = gld(v.w, e) - h * gld(x, e);
-    gst(v.w, e, wn);
-    s += (y ? gld(y, e) : wn) * wn;
+  for (; e + 3 * S < n9; e += 4 * S) {
+    double wv[4], xv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wv[u] = gld(w, e + u * S);
+      xv[u] = gld(x, e + u * S);
+      if (HasY) yv[u] = gld(y, e + u * S);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double wn = wv[u] - h * xv[u];
+      gst(w, e + u * S, wn);
+      s += (HasY ? yv[u] : wn) * wn;
+    }
+  }
+  for (; e < n9; e += S) {
+    const double wn = gld(w, e) - h * gld(x, e);
+    gst(w, e, wn);
+    s += (HasY ? gld(y, e) : wn) * wn;
   }
   const double t = block_sum_step(s, sh);
   if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
@@ -211,8 +232,10 @@ hipError_t launch_ensemble_step(const StepLaunch& L, hipStream_t s, KernelTimer*
     hipLaunchKernelGGL(step_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, 0, L.part);
     hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol, 0);
     for (int i = 0; i <= j; ++i) {
-      hipLaunchKernelGGL(step_axpy_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, i, Y.hcol + i, i < j ? i + 1 : -1,
-                         L.part);
+      if (i < j)
+        hipLaunchKernelGGL(step_axpy_dot_kernel<true>, vgrid, dim3(kSB), 0, s, L.sv, i, Y.hcol + i, i + 1, L.part);
+      else
+        hipLaunchKernelGGL(step_axpy_dot_kernel<false>, vgrid, dim3(kSB), 0, s, L.sv, i, Y.hcol + i, -1, L.part);
       hipLaunchKernelGGL(step_fold_kernel, dim3(L.n), dim3(kSB), 0, s, L.sv, L.part, L.blocks, Y.hcol + i + 1,
                          i < j ? 0 : 1);
     }

@@ -131,18 +131,38 @@ __global__ __launch_bounds__(kRBlock) void axpby_kernel(int64_t n, double a, con
 
 // One modified Gram-Schmidt update fused with the next projection:
 // w -= (*coef) x, and part[block] = sum over the block's entries of the
-// updated w times y (y null: times w itself, for the norm).  The entries of a
-// block are those of dot_partials, so the sums fold in the same order.
+// updated w times y (HasY) or times itself (the norm).  The entries of a
+// block are those of dot_partials and are summed in the same order; each pass
+// of the main loop takes four of them with all loads issued before the first
+// store, so a wavefront keeps four times the bytes in flight.
+template <bool HasY>
 __global__ __launch_bounds__(kRBlock) void axpy_dot_partials(int64_t n, const double* __restrict__ coef,
                                                              const double* __restrict__ x, double* __restrict__ w,
                                                              const double* __restrict__ y, double* __restrict__ part) {
   __shared__ double sh[kRBlock / 64];
   const double a = -coef[0];
+  const int64_t S = int64_t(kRGrid) * kRBlock;
+  int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x;
   double s = 0.0;
-  for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock) {
+  for (; c + 3 * S < n; c += 4 * S) {
+    double wv[4], xv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wv[u] = w[c + u * S];
+      xv[u] = x[c + u * S];
+      if (HasY) yv[u] = y[c + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double wn = wv[u] + a * xv[u];
+      w[c + u * S] = wn;
+      s += (HasY ? yv[u] : wn) * wn;
+    }
+  }
+  for (; c < n; c += S) {
     const double wn = w[c] + a * x[c];
     w[c] = wn;
-    s += (y ? y[c] : wn) * wn;
+    s += (HasY ? y[c] : wn) * wn;
   }
   const double t = block_sum<kRBlock>(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -225,7 +245,10 @@ hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, doubl
 
 hipError_t launch_axpy_dot(int64_t n, const double* coef, const double* x, double* w, const double* y, double* out,
                            double* part, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, coef, x, w, y, part);
+  if (y)
+    hipLaunchKernelGGL(axpy_dot_partials<true>, dim3(kRGrid), dim3(kRBlock), 0, s, n, coef, x, w, y, part);
+  else
+    hipLaunchKernelGGL(axpy_dot_partials<false>, dim3(kRGrid), dim3(kRBlock), 0, s, n, coef, x, w, y, part);
   hipLaunchKernelGGL(fold_partials, dim3(1), dim3(kRBlock), 0, s, part, 1, out, y ? 0 : 1);
   return hipGetLastError();
 }
