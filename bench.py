@@ -366,6 +366,25 @@ def main():
             per_step[op].append(sum(t_step[k][0] for k in ks if k in t_step))
     ctx.timing_enable(False)
 
+    # the same step with R taken from the JVP's dual pass (cfv_jvp with R):
+    # the outputs of the step above from one march fewer
+    R_sep = R.clone()
+    R.zero_()
+
+    def step_fused():
+        ctx.jvp(U, v, dbr, out=Jv, R=R)
+        ctx.vjp(U, w, out=gU, gbr=gbr)
+        ctx.norms(R, out=nrm)
+
+    step_fused()
+    torch.cuda.synchronize()
+    tf0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_fused()
+    torch.cuda.synchronize()
+    tf1 = time.perf_counter()
+    r_diff = float(((R - R_sep).abs().max() / R_sep.abs().max()).item())
+
     nc = inst.ncells
     per_kernel = {k: {"avg_ms": ms / n, "launches": n} for k, (ms, n) in times.items()}
     op_ms = {}
@@ -402,6 +421,11 @@ def main():
                               for op, v in per_step.items()},
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
+        "step_r_from_jvp": {"mcells_per_s": round(nc * args.steps / (tf1 - tf0) / 1e6, 2),
+                            "ms_per_step": round((tf1 - tf0) * 1e3 / args.steps, 4),
+                            "max_rel_r_difference": r_diff,
+                            "note": "the step with R written by the JVP launch (cfv_jvp with R) instead of a "
+                                    "residual launch of its own; not the headline value"},
     }
     vrec, vsrc = profile_record("valu-record", {"workload": args.workload})
     if vrec:
@@ -417,9 +441,15 @@ def main():
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for q in range(2):
             b.copy_(a)
+            ev[q + 1].record()
         torch.cuda.synchronize()
+        cms = [ev[q].elapsed_time(ev[q + 1]) for q in range(2)]
+        out["copy_calibration"] = {"bytes_moved": 2 * a.numel() * 8, "ms": [round(x, 4) for x in cms],
+                                   "gbs": round(2 * a.numel() * 8 / (min(cms) * 1e-3) / 1e9, 1)}
         del a, b
     if not args.no_ensemble:
         del ctx, U, v, w, R, Jv, gU

@@ -53,8 +53,20 @@ __global__ __launch_bounds__(kSB) void step_dot_kernel(const StepVec* __restrict
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const double* a = i >= 0 ? v.V + int64_t(i) * n9 : v.w;
+  const int64_t S = int64_t(gridDim.x) * kSB;
+  int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x;
   double s = 0.0;
-  STEP_LOOP(n9) s += gld(a, e) * gld(v.w, e);
+  for (; e + 3 * S < n9; e += 4 * S) {  // four entries' loads in flight, summed in entry order
+    double av[4], wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = gld(a, e + u * S);
+      wv[u] = gld(v.w, e + u * S);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += av[u] * wv[u];
+  }
+  for (; e < n9; e += S) s += gld(a, e) * gld(v.w, e);
   const double t = block_sum_step(s, sh);
   if (threadIdx.x == 0) part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
 }
@@ -89,7 +101,16 @@ __global__ __launch_bounds__(kSB) void step_scale_kernel(const StepVec* __restri
   const double den = v.sm[slot];
   const double* src = j < 0 ? v.Unew : v.w;
   double* dst = v.V + int64_t(j < 0 ? 0 : j + 1) * n9;
-  STEP_LOOP(n9) gst(dst, e, den != 0.0 ? gld(src, e) / den : 0.0);
+  const int64_t S = int64_t(gridDim.x) * kSB;
+  int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x;
+  for (; e + 3 * S < n9; e += 4 * S) {  // four entries per pass, loads before stores
+    double xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = gld(src, e + u * S);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) gst(dst, e + u * S, den != 0.0 ? xv[u] / den : 0.0);
+  }
+  for (; e < n9; e += S) gst(dst, e, den != 0.0 ? gld(src, e) / den : 0.0);
 }
 
 // w += diag o V_j (the V/dt part of the operator)
@@ -97,7 +118,20 @@ __global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __res
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const double* x = v.V + int64_t(j) * n9;
-  STEP_LOOP(n9) gst(v.w, e, gld(v.w, e) + gld(v.diag, e % v.nc) * gld(x, e));
+  const int64_t S = int64_t(gridDim.x) * kSB;
+  int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x;
+  for (; e + 3 * S < n9; e += 4 * S) {  // four entries per pass, loads before stores
+    double wv[4], dv[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wv[u] = gld(v.w, e + u * S);
+      dv[u] = gld(v.diag, (e + u * S) % v.nc);
+      xv[u] = gld(x, e + u * S);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) gst(v.w, e + u * S, wv[u] + dv[u] * xv[u]);
+  }
+  for (; e < n9; e += S) gst(v.w, e, gld(v.w, e) + gld(v.diag, e % v.nc) * gld(x, e));
 }
 
 // w -= sm[slot] V_i fused with the next projection: partial sums of the

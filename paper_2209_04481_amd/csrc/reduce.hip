@@ -113,11 +113,22 @@ __global__ __launch_bounds__(kRBlock) void fold_partials(const double* __restric
 __global__ __launch_bounds__(kRBlock) void dot_partials(int64_t n, const double* __restrict__ V, int k,
                                                        const double* __restrict__ w, double* __restrict__ part) {
   __shared__ double sh[kRBlock / 64];
+  const int64_t S = int64_t(kRGrid) * kRBlock;
   for (int q = 0; q < k; ++q) {
     const double* x = V + int64_t(q) * n;
     double s = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < n; c += int64_t(kRGrid) * kRBlock)
-      s += x[c] * w[c];
+    int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x;
+    for (; c + 3 * S < n; c += 4 * S) {  // four entries' loads in flight, summed in entry order
+      double xv[4], wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xv[u] = x[c + u * S];
+        wv[u] = w[c + u * S];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += xv[u] * wv[u];
+    }
+    for (; c < n; c += S) s += x[c] * w[c];
     double t = block_sum<kRBlock>(s, sh);
     if (threadIdx.x == 0) part[q * kRGrid + blockIdx.x] = t;
   }
