@@ -300,12 +300,18 @@ def test_full_size_sampled_parity(name, n):
     S = sample_cells(inst, n, 7)
     v = torch.tensor(ci.scaled_direction(inst.U, inst.seed))
     dbr = torch.tensor(ci.br_direction(c.grid.nb, inst.seed))
-    R = c.ctx.residual(c.Ud)[:, S.cuda()].cpu()
-    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda())[:, S.cuda()].cpu()
+    Rfull = c.ctx.residual(c.Ud)
+    Rj = torch.full_like(c.Ud, float("nan"))
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda(), R=Rj)[:, S.cuda()].cpu()
+    R = Rfull[:, S.cuda()].cpu()
     Ro = mhd.residual(c.og, c.U, c.br, c.op, cells=S)
     Jo, _ = solve.jvp(c.og, c.U, c.br, c.op, v, dbr, cells=S)
     assert float(rel_err_per_var(R, Ro).max()) <= TOL
     assert float(rel_err_per_var(Jv, Jo).max()) <= TOL
+    # the residual the JVP launch writes (its dual pass's value part) is the
+    # residual launch's on every cell, to rounding
+    assert float(rel_err_per_var(Rj, Rfull).max()) <= 1e-14
+    del Rfull, Rj
     # VJP at the sampled cells is exact from w on their distance-2 stencils
     st = mhd._Stencil(c.og, S)
     T = st.D2
