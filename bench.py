@@ -97,19 +97,42 @@ def cpu_baseline(inst, ncells_sample: int):
 
 
 def bench_solver(with_sensitivity: bool):
-    """The implicit step on the 1.66M-cell workload: one backward-Euler step
-    (CFL 1e3, GMRES(30), no restart) and, optionally, the 20-step B_r
-    sensitivity (CFL 0.05, tight solves, checkpoints every 5 steps)."""
+    """The 1.66M-cell workload: residual and JVP (20 calls each, percentiles
+    of the library's event times), one backward-Euler step (CFL 1e3,
+    GMRES(30), no restart), the first steps of the steady march and,
+    optionally, the 20-step B_r sensitivity (CFL 0.05, tight solves,
+    checkpoints every 5 steps)."""
+    import numpy as np
     import torch
 
     import coronal_inputs as ci
     from paper_2209_04481_amd import Context, Grid, Params
 
     inst = ci.workload("medium")
-    ctx = Context(Grid(inst.N, inst.Nr, inst.r_nodes), Params())
+    grid = Grid(inst.N, inst.Nr, inst.r_nodes)
+    ctx = Context(grid, Params())
     ctx.set_inner_br(torch.from_numpy(inst.br).cuda())
     U = torch.from_numpy(inst.U).cuda()
     out = torch.empty_like(U)
+    # residual and JVP on this workload: 20 calls each after a warm-up, library event times per call
+    v = torch.from_numpy(ci.scaled_direction(inst.U, inst.seed)).cuda()
+    dbr = torch.from_numpy(ci.br_direction(grid.nb, inst.seed)).cuda()
+    Jv = torch.empty_like(U)
+    ctx.residual(U, out=out)
+    ctx.jvp(U, v, dbr, out=Jv)
+    ctx.timing_enable(True)
+    ctx.timing_read()
+    per = {"residual": [], "jvp": []}
+    for _ in range(20):
+        ctx.residual(U, out=out)
+        t = ctx.timing_read()
+        per["residual"].append(sum(t[k][0] for k in OP_KERNELS["residual"] if k in t))
+        ctx.jvp(U, v, dbr, out=Jv)
+        t = ctx.timing_read()
+        per["jvp"].append(sum(t[k][0] for k in OP_KERNELS["jvp"] if k in t))
+    ctx.timing_enable(False)
+    op_pct = {op: [round(float(np.percentile(x, q)), 4) for q in (10, 50, 90)] for op, x in per.items()}
+    del Jv
     ctx.be_step(U, cfl=1e3, m=30, out=out)
     torch.cuda.synchronize()
     reps = 5
@@ -119,6 +142,7 @@ def bench_solver(with_sensitivity: bool):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
     res = {"workload": f"medium: 6x{inst.N}x{inst.N}x{inst.Nr} ({inst.ncells} cells)",
+           "op_ms_p10_p50_p90": op_pct,
            "be_step_ms": round(ms, 2), "gmres_iterations": int(len(hist)),
            "ms_per_gmres_iteration": round(ms / max(len(hist), 1), 3), "final_relative_residual": float(hist[-1])}
     print(f"[bench] backward-Euler step: {ms:.1f} ms", file=sys.stderr, flush=True)
@@ -299,6 +323,8 @@ def main():
     ap.add_argument("--solve-reps", type=int, default=2)
     ap.add_argument("--no-solver", action="store_true")
     ap.add_argument("--efield-reps", type=int, default=20)
+    ap.add_argument("--sweep-reps", type=int, default=100,
+                    help="steps of the per-operation percentile pass (library event times per call)")
     ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 70 s)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -359,7 +385,7 @@ def main():
     ctx.timing_enable(True)
     ctx.timing_read()
     per_step = {op: [] for op in OP_KERNELS}
-    for _ in range(args.steps):
+    for _ in range(args.sweep_reps):
         step()
         t_step = ctx.timing_read()
         for op, ks in OP_KERNELS.items():
