@@ -82,14 +82,34 @@ __global__ __launch_bounds__(kRBlock) void fold_max(const double* __restrict__ p
   if (threadIdx.x == 0) out[v] = t;
 }
 
-// partial[v*kRGrid + block] = sum over the block's cells of (a - b)^2 for variable v
+// partial[v*kRGrid + block] = sum over the block's cells of (a - b)^2 for
+// variable v (HasB) or of a^2; four cells' loads in flight per pass, summed in
+// cell order
+template <bool HasB>
 __global__ __launch_bounds__(kRBlock) void sq_partials(int64_t nc, const double* __restrict__ a,
                                                       const double* __restrict__ b, double* __restrict__ part) {
   __shared__ double sh[kRBlock / 64];
+  const int64_t S = int64_t(kRGrid) * kRBlock;
   for (int v = 0; v < 9; ++v) {
+    const double* av = a + v * nc;
+    const double* bv = HasB ? b + v * nc : nullptr;
     double s = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x; c < nc; c += int64_t(kRGrid) * kRBlock) {
-      double d = a[v * nc + c] - (b ? b[v * nc + c] : 0.0);
+    int64_t c = int64_t(blockIdx.x) * kRBlock + threadIdx.x;
+    for (; c + 3 * S < nc; c += 4 * S) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = av[c + u * S];
+        y[u] = HasB ? bv[c + u * S] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double d = x[u] - y[u];
+        s += d * d;
+      }
+    }
+    for (; c < nc; c += S) {
+      const double d = av[c] - (HasB ? bv[c] : 0.0);
       s += d * d;
     }
     double t = block_sum<kRBlock>(s, sh);
@@ -243,7 +263,10 @@ hipError_t launch_ratio_max(int64_t n, int nvar, const double* x, const double* 
 }
 
 hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(sq_partials, dim3(kRGrid), dim3(kRBlock), 0, s, nc, a, b, part);
+  if (b)
+    hipLaunchKernelGGL(sq_partials<true>, dim3(kRGrid), dim3(kRBlock), 0, s, nc, a, b, part);
+  else
+    hipLaunchKernelGGL(sq_partials<false>, dim3(kRGrid), dim3(kRBlock), 0, s, nc, a, b, part);
   hipLaunchKernelGGL(fold_partials, dim3(9), dim3(kRBlock), 0, s, part, 9, out9, 1);
   return hipGetLastError();
 }
