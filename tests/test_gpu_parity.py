@@ -330,6 +330,42 @@ def test_full_size_sampled_parity(name, n):
     assert abs(lhs - rhs) <= 1e-12 * float((ww * Jvv).abs().sum())
 
 
+@pytest.mark.parametrize("case", [1, 9])
+def test_large_e_and_outer_laws_medium_sampled(case):
+    """The large-E inner law (dipole B_theta) with Table 2 outer law 1 or 9
+    at 1.66M cells, in the bench's launch configuration: R, the JVP with a
+    B_r direction, the VJP and the B_r gradient, at sampled cells of the
+    three innermost and outermost layers (where the laws act) and random
+    ones, against the oracle on their distance-2 stencils."""
+    print(f"case: large-E + outer law {case}, medium sampled", flush=True)
+    inst = ci.workload("medium")
+    N, Nr = inst.N, inst.Nr
+    c = Case(inst, mhd.Params.table2(case, inner_mode=1, inner_btheta=torch.tensor(ci.btheta_map(N))))
+    rng = np.random.default_rng(40 + case)
+    m = 40
+    p, j, i = rng.integers(0, 6, 2 * m), rng.integers(0, N, 2 * m), rng.integers(0, N, 2 * m)
+    k = np.concatenate([rng.integers(0, 3, m), rng.integers(Nr - 3, Nr, m)])
+    picks = set(int(x) for x in ((p * Nr + k) * N + j) * N + i) | set(int(x) for x in sample_cells(inst, 24, case))
+    S = torch.tensor(sorted(picks))
+    v = torch.tensor(ci.scaled_direction(inst.U, inst.seed + case))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, inst.seed + case))
+    R = c.ctx.residual(c.Ud)[:, S.cuda()].cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda())[:, S.cuda()].cpu()
+    Ro = mhd.residual(c.og, c.U, c.br, c.op, cells=S)
+    Jo, _ = solve.jvp(c.og, c.U, c.br, c.op, v, dbr, cells=S)
+    assert float(rel_err_per_var(R, Ro).max()) <= TOL
+    assert float(rel_err_per_var(Jv, Jo).max()) <= TOL
+    # w supported on the samples' stencils: the VJP at the samples and the
+    # whole B_r gradient are exact from those cells' residuals
+    T = mhd._Stencil(c.og, S).D2
+    w = torch.zeros(9, inst.ncells, dtype=torch.float64)
+    w[:, T] = torch.randn(9, T.numel(), dtype=torch.float64, generator=torch.Generator().manual_seed(case))
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w[:, T], cells=T)
+    assert float(rel_err_per_var(gU[:, S.cuda()].cpu(), gUo[:, S]).max()) <= TOL
+    assert float(rel_err_per_var(gbr.cpu()[None], gbro[None]).max()) <= TOL
+
+
 @pytest.mark.parametrize("limiter", [1, 0])
 def test_jvp_matches_central_differences_medium(limiter):
     """The 1.66M-cell workload: J_U v + J_b dbr against the central difference
