@@ -330,15 +330,17 @@ def test_full_size_sampled_parity(name, n):
     assert abs(lhs - rhs) <= 1e-12 * float((ww * Jvv).abs().sum())
 
 
-@pytest.mark.parametrize("case", [1, 9])
-def test_large_e_and_outer_laws_medium_sampled(case):
+@pytest.mark.parametrize("radial,case", [("log", 1), ("log", 9), ("bcind", 1), ("bcind", 9)])
+def test_large_e_and_outer_laws_medium_sampled(radial, case):
     """The large-E inner law (dipole B_theta) with Table 2 outer law 1 or 9
-    at 1.66M cells, in the bench's launch configuration: R, the JVP with a
-    B_r direction, the VJP and the B_r gradient, at sampled cells of the
-    three innermost and outermost layers (where the laws act) and random
-    ones, against the oracle on their distance-2 stencils."""
-    print(f"case: large-E + outer law {case}, medium sampled", flush=True)
-    inst = ci.workload("medium")
+    at 1.66M cells (48 x 48 x 120 per panel), on the log-spaced shell and on
+    the BC-independent extended grid, in the bench's launch configuration:
+    R, the JVP with a B_r direction, the VJP and the B_r gradient, at sampled
+    cells of the three innermost and outermost layers (where the laws act)
+    and random ones, against the oracle on their distance-2 stencils."""
+    print(f"case: large-E + outer law {case}, {radial} grid, medium sampled", flush=True)
+    w0 = ci.workload("medium")
+    inst = w0 if radial == "log" else ci.make_instance(w0.N, w0.Nr, radial, lmax=15, seed=w0.seed + 1)
     N, Nr = inst.N, inst.Nr
     c = Case(inst, mhd.Params.table2(case, inner_mode=1, inner_btheta=torch.tensor(ci.btheta_map(N))))
     rng = np.random.default_rng(40 + case)
