@@ -76,3 +76,16 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(here, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_cpu_baseline_record_on_a_small_shell():
+    """The bench's CPU-baseline leg (the oracle timed on a block of cells)
+    clamps its sample to the shell and reports the fields of its record."""
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, here)
+    import bench
+    inst = ci.make_instance(4, 3, "log", lmax=2, seed=5)
+    rec = bench.cpu_baseline(inst, 10 ** 6, "small")
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] >= 1
+    assert rec["sample"].startswith(f"{inst.ncells} contiguous cells of the small workload")
