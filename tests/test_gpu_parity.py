@@ -289,14 +289,15 @@ def sample_cells(inst, n, seed):
     return torch.tensor(sorted(set(int(x) for x in picks)))
 
 
-@pytest.mark.parametrize("name,n", [("medium", 160), ("large", 96)])
-def test_full_size_sampled_parity(name, n):
+@pytest.mark.parametrize("name,n,limiter", [("medium", 160, 1), ("large", 96, 1), ("medium", 120, 0)])
+def test_full_size_sampled_parity(name, n, limiter):
     """At the medium (1.66M cells) and large (13.3M cells) sizes, in the
     launch configuration the bench uses: sampled cells computed one by one by
-    the oracle from their distance-2 stencils."""
-    print(f"case: full size {name}", flush=True)
+    the oracle from their distance-2 stencils (with the limiter, and without
+    it at 1.66M cells)."""
+    print(f"case: full size {name}, limiter {limiter}", flush=True)
     inst = ci.workload(name)
-    c = Case(inst)
+    c = Case(inst, mhd.Params(limiter=limiter))
     S = sample_cells(inst, n, 7)
     v = torch.tensor(ci.scaled_direction(inst.U, inst.seed))
     dbr = torch.tensor(ci.br_direction(c.grid.nb, inst.seed))
