@@ -331,6 +331,31 @@ def test_full_size_sampled_parity(name, n, limiter):
     assert abs(lhs - rhs) <= 1e-12 * float((ww * Jvv).abs().sum())
 
 
+def test_sampled_parity_past_2_31_workspace_entries():
+    """A 19.3M-cell shell (6 x 112 x 112 x 256): the VJP workspace then holds
+    more than 2^31 doubles (117 rows of cells), so its row offsets need
+    64-bit arithmetic.  R, the JVP and the VJP at sampled cells, including
+    the last cell of every panel, against the oracle on their stencils."""
+    print("case: 19.3M cells (workspace past 2^31 entries)", flush=True)
+    inst = ci.make_instance(112, 256, "log", lmax=15, seed=77)
+    assert 117 * inst.ncells > 2 ** 31
+    c = Case(inst)
+    S = sample_cells(inst, 48, 11)
+    v = torch.tensor(ci.scaled_direction(inst.U, 78))
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, 78))
+    R = c.ctx.residual(c.Ud)[:, S.cuda()].cpu()
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), dbr.cuda())[:, S.cuda()].cpu()
+    assert float(rel_err_per_var(R, mhd.residual(c.og, c.U, c.br, c.op, cells=S)).max()) <= TOL
+    assert float(rel_err_per_var(Jv, solve.jvp(c.og, c.U, c.br, c.op, v, dbr, cells=S)[0]).max()) <= TOL
+    T = mhd._Stencil(c.og, S).D2
+    w = torch.zeros(9, inst.ncells, dtype=torch.float64)
+    w[:, T] = torch.randn(9, T.numel(), dtype=torch.float64, generator=torch.Generator().manual_seed(79))
+    gU, gbr = c.ctx.vjp(c.Ud, w.cuda())
+    gUo, gbro = solve.vjp(c.og, c.U, c.br, c.op, w[:, T], cells=T)
+    assert float(rel_err_per_var(gU[:, S.cuda()].cpu(), gUo[:, S]).max()) <= TOL
+    assert float(rel_err_per_var(gbr.cpu()[None], gbro[None]).max()) <= TOL
+
+
 @pytest.mark.parametrize("radial,case", [("log", 1), ("log", 9), ("bcind", 1), ("bcind", 9)])
 def test_large_e_and_outer_laws_medium_sampled(radial, case):
     """The large-E inner law (dipole B_theta) with Table 2 outer law 1 or 9
