@@ -295,8 +295,24 @@ __host__ __device__ __forceinline__ void store_res<Dual>(const MarchArgs& a, int
 
 template <class T>
 struct FluxWG {
-  // two buffers: west/south face states, then east/north face fluxes
-  static constexpr int kLds = 2 * 18 * kNT * int(sizeof(T) / sizeof(double));
+  // LDS, in units of T: the west and south face states of the tile's cells
+  // (18 rows of kNT), their east and north face fluxes (18 rows), the states
+  // of the out-of-tile neighbours across the tile's four edges on the shared
+  // faces (9 rows of kRing: east edge by row, north by column, west by row,
+  // south by column) and the signed fluxes of the tile's west and south edge
+  // faces (9 rows of kEdge: south by column, then west by row)
+  static constexpr int kRing = 4 * 16, kEdge = 2 * 16;
+  static_assert(kTI == 16 && kTJ == 16, "ring and edge slots are laid out for 16 x 16 tiles");
+  static constexpr int kRingOff = 36 * kNT, kEdgeOff = kRingOff + 9 * kRing;
+  static constexpr int kLds = (kEdgeOff + 9 * kEdge) * int(sizeof(T) / sizeof(double));
+
+  // last active column and row of the tile (partial tiles at the panel edge)
+  __host__ __device__ static int last_ti(const Shape& g, const TileMap& tm) {
+    return (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
+  }
+  __host__ __device__ static int last_tj(const Shape& g, const TileMap& tm) {
+    return (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
+  }
 
   // state of cell (column ncol, layer k) reconstructed at the face centroid xf
   __host__ __device__ static void remote_state(const MarchArgs& a, int64_t ncol, int k, V3 xf, T q[9]) {
@@ -308,6 +324,30 @@ struct FluxWG {
     load_prims(a, c, P);
     load_grad(a, c, Gr);
     recon(P, Gr, xf - cell_centre(a.d.G, g, np, k, nj, ni), q);
+  }
+
+  // ring slot r of layer k: the state of the out-of-tile neighbour across
+  // one edge face of the tile, on that face (one wavefront loads all 64)
+  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, int r, int k, double* lds) {
+    const Shape& g = a.d.g;
+    const int kind = r >> 4, idx = r & 15;
+    const int tiL = last_ti(g, tm), tjL = last_tj(g, tm);
+    // kind 0: east face of row idx's last cell; 1: north face of column idx's
+    // last cell; 2: west face of row idx's first cell; 3: south face of
+    // column idx's first cell
+    const int ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
+    const int tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
+    const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
+    if (ti > tiL || tj > tjL) return;
+    const int j = tm.j0 + tj, i = tm.i0 + ti;
+    V3 S, xf;
+    bool own;
+    canon_face(a.d.G, g, tm.p, k, j, i, 2 + q, Nbr{}, 0, S, xf, own);
+    const int64_t nbcol = gld(a.d.G.cn, q * a.d.G.ncol + column_of(g, tm.p, j, i));
+    T qo[9];
+    remote_state(a, nbcol, k, xf, qo);
+    T* Rg = lds_as<T>(lds) + kRingOff;
+    for (int v = 0; v < 9; ++v) Rg[v * kRing + r] = qo[v];
   }
 
   __host__ __device__ static void init(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t) {
@@ -403,49 +443,62 @@ struct FluxWG {
     }
   }
 
+  // east and north faces of every cell (neighbour states from LDS: in-tile
+  // or ring); the west and south faces on the tile's edges by the first kEdge
+  // threads, for the edge cells, with their signed fluxes left in LDS
   __host__ __device__ static void faces(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
                                         double* lds) {
-    if (!st.act) return;
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     const T* Sb = lds_as<T>(lds);
     T* Fb = lds_as<T>(lds) + 18 * kNT;
+    const T* Rg = lds_as<T>(lds) + kRingOff;
+    T* Eb = lds_as<T>(lds) + kEdgeOff;
     const int ti = t % kTI, tj = t / kTI;
-    for (int q = 0; q < 4; ++q) {
-      const bool east = q == 1 || q == 3;
-      const bool edge_west = q == 0 && ti == 0;
-      const bool edge_south = q == 2 && tj == 0;
-      if (!east && !edge_west && !edge_south) continue;
-      V3 S, xf;
-      bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
-      const int64_t nbcol = gld(G.cn, q * G.ncol + st.col);
-      T qs[9], qo[9], F[9];
-      if (q == 1) {
-        for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
-        if (st.i + 1 < g.N && ti + 1 < kTI)
-          for (int v = 0; v < 9; ++v) qo[v] = Sb[v * kNT + t + 1];
-        else
-          remote_state(a, nbcol, k, xf, qo);
-      } else if (q == 3) {
-        for (int v = 0; v < 9; ++v) qs[v] = st.q5[v];
-        if (st.j + 1 < g.N && tj + 1 < kTJ)
-          for (int v = 0; v < 9; ++v) qo[v] = Sb[(9 + v) * kNT + t + kTI];
-        else
-          remote_state(a, nbcol, k, xf, qo);
-      } else {
-        const int off = q == 0 ? 0 : 9;
-        for (int v = 0; v < 9; ++v) qs[v] = Sb[(off + v) * kNT + t];
-        remote_state(a, nbcol, k, xf, qo);
+    const int tiL = last_ti(g, tm), tjL = last_tj(g, tm);
+    if (st.act) {
+      for (int h = 0; h < 2; ++h) {
+        const int q = h == 0 ? 1 : 3;
+        V3 S, xf;
+        bool own;
+        canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
+        T qs[9], qo[9], F[9];
+        if (h == 0) {
+          for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
+          if (ti < tiL)
+            for (int v = 0; v < 9; ++v) qo[v] = Sb[v * kNT + t + 1];
+          else
+            for (int v = 0; v < 9; ++v) qo[v] = Rg[v * kRing + tj];
+        } else {
+          for (int v = 0; v < 9; ++v) qs[v] = st.q5[v];
+          if (tj < tjL)
+            for (int v = 0; v < 9; ++v) qo[v] = Sb[(9 + v) * kNT + t + kTI];
+          else
+            for (int v = 0; v < 9; ++v) qo[v] = Rg[v * kRing + 16 + ti];
+        }
+        face_flux(own, qs, qo, S, F, a.d.pr);
+        for (int v = 0; v < 9; ++v) st.acc[v] += own ? F[v] : -F[v];
+        for (int v = 0; v < 9; ++v) Fb[(9 * h + v) * kNT + t] = F[v];
       }
-      face_flux(own, qs, qo, S, F, a.d.pr);
-      for (int v = 0; v < 9; ++v) st.acc[v] += own ? F[v] : -F[v];
-      if (q == 1)
-        for (int v = 0; v < 9; ++v) Fb[v * kNT + t] = F[v];
-      else if (q == 3)
-        for (int v = 0; v < 9; ++v) Fb[(9 + v) * kNT + t] = F[v];
     }
-    (void)tm;
+    if (t < kEdge) {
+      const bool south = t < 16;
+      const int eti = south ? t : 0, etj = south ? 0 : t - 16;
+      if (eti <= tiL && etj <= tjL) {
+        const int q = south ? 2 : 0;
+        const int tc = etj * kTI + eti;
+        V3 S, xf;
+        bool own;
+        canon_face(G, g, tm.p, k, tm.j0 + etj, tm.i0 + eti, 2 + q, Nbr{}, 0, S, xf, own);
+        T qs[9], qo[9], F[9];
+        for (int v = 0; v < 9; ++v) {
+          qs[v] = Sb[((south ? 9 : 0) + v) * kNT + tc];
+          qo[v] = Rg[v * kRing + (south ? 48 + eti : 32 + etj)];
+        }
+        face_flux(own, qs, qo, S, F, a.d.pr);
+        for (int v = 0; v < 9; ++v) Eb[v * kEdge + t] = own ? F[v] : -F[v];
+      }
+    }
   }
 
   __host__ __device__ static void accumulate(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
@@ -454,14 +507,19 @@ struct FluxWG {
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     const T* Fb = lds_as<T>(lds) + 18 * kNT;
+    const T* Eb = lds_as<T>(lds) + kEdgeOff;
     const int ti = t % kTI, tj = t / kTI;
     if (ti > 0) {
       const bool own = (gld(G.cn, 4 * G.ncol + st.col) >> 8) != 0;
       for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[v * kNT + t - 1] : -Fb[v * kNT + t - 1];
+    } else {
+      for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + 16 + tj];
     }
     if (tj > 0) {
       const bool own = (gld(G.cn, 6 * G.ncol + st.col) >> 8) != 0;
       for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[(9 + v) * kNT + t - kTI] : -Fb[(9 + v) * kNT + t - kTI];
+    } else {
+      for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + ti];
     }
     for (int v = 0; v < 9; ++v) st.accp[v] = st.acc[v];
     if (k == g.Nr - 1) store_res(a, cell_index(g, st.p, k, st.j, st.i), st.acc);

@@ -46,6 +46,8 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
   FluxWG<T>::init(a, tm, st, t);
   for (int k = tm.k0; k < tm.k1; ++k) {
     FluxWG<T>::states(a, tm, st, t, k, lds);
+    // the second wavefront also loads the ring of out-of-tile neighbour states
+    if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, t - kNT / 4, k, lds);
     __syncthreads();
     FluxWG<T>::faces(a, tm, st, t, k, lds);
     __syncthreads();
