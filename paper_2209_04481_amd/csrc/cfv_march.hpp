@@ -110,9 +110,10 @@ __host__ __device__ __forceinline__ void face_flux(bool own, const T qs[9], cons
 // ======================================================== gradient pass
 // LDS plane of (kTI + 2) x (kTJ + 2) positions: the tile at offset (1, 1)
 // and a ring.  Every in-plane neighbour of an active cell has a position:
-// an active in-tile cell publishes itself; a neighbour that is not (tile edge,
-// panel edge, or beyond a partial tile) is loaded by the one active cell next
-// to it, which is the only cell that can see that position.
+// an active in-tile cell publishes itself; for a neighbour that is not (tile
+// edge, panel edge, or beyond a partial tile) the one active cell next to it
+// stores its centroid sums once per item, and the second wavefront loads its
+// primitives for every layer (ring()).
 constexpr int kPW = kTI + 2, kPH = kTJ + 2, kPlane = kPW * kPH;
 __host__ __device__ __forceinline__ int plane_pos(int ti, int tj) { return (tj + 1) * kPW + (ti + 1); }
 __host__ __device__ __forceinline__ void dir_offset(int q, int& dx, int& dy) {
@@ -125,7 +126,6 @@ struct GState {
   int p, j, i;
   int64_t col;
   bool act;
-  unsigned remote;  // bit q: the neighbour across angular face q is loaded by this cell
   T Pm[9], P0[9], Pp[9];
 };
 
@@ -147,7 +147,6 @@ struct GradWG {
     st.j = tm.j0 + tj;
     st.i = tm.i0 + ti;
     st.act = st.j < g.N && st.i < g.N;
-    st.remote = 0;
     if (!st.act) return;
     st.col = column_of(g, st.p, st.j, st.i);
     double* cs = lds + 9 * kPlane * kTw;
@@ -158,7 +157,6 @@ struct GradWG {
       int dx, dy;
       dir_offset(q, dx, dy);
       if (in_tile_active(g, tm, ti + dx, tj + dy)) continue;
-      st.remote |= 1u << q;
       const V3 cn = cg3(G, CG_CSUM, gld(G.cn, q * G.ncol + st.col));
       const int pos = plane_pos(ti + dx, tj + dy);
       cs[pos] = cn.x; cs[kPlane + pos] = cn.y; cs[2 * kPlane + pos] = cn.z;
@@ -181,17 +179,31 @@ struct GradWG {
       const int64_t c = cell_index(g, st.p, k, st.j, st.i);
       for (int v = 0; v < 9; ++v) gst(a.P, v * g.ncells + c, val(st.P0[v]));
     }
-    for (int q = 0; q < 4; ++q) {
-      if (!(st.remote & (1u << q))) continue;
-      int dx, dy;
-      dir_offset(q, dx, dy);
-      int np, nj, ni;
-      column_pji(g, gld(G.cn, q * G.ncol + st.col), np, nj, ni);
-      T qn[9];
-      load_prims(a, cell_index(g, np, k, nj, ni), qn);
-      const int pos = plane_pos(ti + dx, tj + dy);
-      for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
-    }
+  }
+
+  // Ring position r of layer k (the plane's out-of-tile neighbours, loaded
+  // by one wavefront in one pass instead of a divergent pass per direction
+  // in every wavefront): kind 0 east of row idx's last cell, 1 north of
+  // column idx's last cell, 2 west of row idx's first cell, 3 south of
+  // column idx's first cell.
+  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, int r, int k, double* lds) {
+    const Shape& g = a.d.g;
+    const int kind = r >> 4, idx = r & 15;
+    const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
+    const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
+    const int ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
+    const int tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
+    const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
+    if (ti > tiL || tj > tjL) return;
+    int dx, dy;
+    dir_offset(q, dx, dy);
+    int np, nj, ni;
+    column_pji(g, gld(a.d.G.cn, q * a.d.G.ncol + column_of(g, tm.p, tm.j0 + tj, tm.i0 + ti)), np, nj, ni);
+    T qn[9];
+    load_prims(a, cell_index(g, np, k, nj, ni), qn);
+    T* L = lds_as<T>(lds);
+    const int pos = plane_pos(ti + dx, tj + dy);
+    for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
   }
 
   // Faces: write the reconstructed face states to a.Q instead of the

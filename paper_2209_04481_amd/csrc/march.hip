@@ -33,6 +33,7 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   GradWG<T>::init(a, tm, st, t, lds);
   for (int k = tm.k0; k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
+    if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
     __syncthreads();
