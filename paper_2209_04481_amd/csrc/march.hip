@@ -109,10 +109,10 @@ __device__ __forceinline__ int find_instance(const int64_t* __restrict__ off, in
 
 // Wavefronts per SIMD each pass is compiled for (register budget 512 / n per
 // lane; the LDS of n workgroups must fit in 160 KB).  Measured on the 13.3M-
-// cell shell: the residual passes run 25-30% faster at 2 than at 1 despite a
-// few hundred bytes of spills, and slower at 3 or 4; the JVP gradient pass
-// is 3% slower at 2 (456 bytes of spills) and the JVP flux pass needs 148 KB
-// of LDS, so both JVP passes stay at 1.
+// cell shell: the residual passes run faster at 2 than at 1 despite a few
+// hundred bytes of spills (the flux pass 3.56 against 3.92 ms), and slower
+// at 3 or 4; the JVP gradient pass is slower at 2 (4.33 against 3.58 ms) and
+// the JVP flux pass needs 158 KB of LDS, so both JVP passes stay at 1.
 template <class T, bool Flux>
 struct MarchOccupancy {
   static constexpr int value = sizeof(T) == sizeof(double) ? 2 : 1;
