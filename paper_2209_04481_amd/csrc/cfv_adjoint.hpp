@@ -128,6 +128,39 @@ __host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], con
   if (want_R) flux_side_adjoint(qR, n, Fb, URb, lamRb, qRb, pr.gamma, pr.c_h);
 }
 
+// Adjoint of rusanov() with respect to one side only: qa is that side's
+// state, qb the other's, a_is_L whether qa is the left (owner) state of the
+// canonical face; accumulates into qab.  The arithmetic is that of
+// rusanov_adjoint() for the side asked for, with the roles chosen by value,
+// so that lanes of both orientations follow one code path.
+__host__ __device__ __forceinline__ void rusanov_adjoint_side(const double qa[9], const double qb[9], V3 S,
+                                                     const double wb[9], double qab[9], const Params& pr,
+                                                     bool a_is_L) {
+  const double area = norm3(S);
+  const double ia = 1.0 / area;
+  const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
+  const double lamA = side_speed(qa, n, pr.gamma);
+  const double lamB = side_speed(qb, n, pr.gamma);
+  const double lamL = a_is_L ? lamA : lamB, lamR = a_is_L ? lamB : lamA;
+  const bool left_wins = lamL >= lamR;  // the left speed wins ties
+  const double s1 = left_wins ? lamL : lamR;
+  const double s = s1 >= pr.c_h ? s1 : pr.c_h;
+  double UA[9], UB[9];
+  prim_to_cons(qa, UA, pr.gamma);
+  prim_to_cons(qb, UB, pr.gamma);
+  const double sg = a_is_L ? 1.0 : -1.0;  // U_R - U_L = sg (U_B - U_A); U_A's weight is sg s/2
+  double Fb[9], UAb[9];
+  double sb = 0.0;
+  for (int v = 0; v < 9; ++v) {
+    Fb[v] = 0.5 * area * wb[v];
+    UAb[v] = sg * (0.5 * s * area * wb[v]);
+    sb -= 0.5 * area * wb[v] * (sg * (UB[v] - UA[v]));
+  }
+  const bool a_wins = a_is_L == left_wins;
+  const double lamAb = s1 >= pr.c_h && a_wins ? sb : 0.0;
+  flux_side_adjoint(qa, n, Fb, UAb, lamAb, qab, pr.gamma, pr.c_h);
+}
+
 // (dP/dU)^T Pb for P = prim(U): returns Ub.
 __host__ __device__ __forceinline__ void prim_adjoint(const double u[9], const double Pb[9], double Ub[9], double gamma) {
   const double rho = u[0];

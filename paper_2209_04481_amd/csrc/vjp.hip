@@ -162,14 +162,17 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     double qLb[9], qRb[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) qLb[v] = qRb[v] = 0.0;
-    // this cell's side, and the ghost side on a boundary face
-    if (own)
-      rusanov_adjoint(qs, qo, S, wb, qLb, qRb, d.pr, true, ghost);
+    // this cell's side (into qLb whatever its orientation: the owner is not
+    // the same on every lane's face at panel edges, and one code path keeps
+    // such wavefronts from running both), and the ghost side on a boundary
+    // face, which this cell always owns
+    if (ghost)
+      rusanov_adjoint(qs, qo, S, wb, qLb, qRb, d.pr, true, true);
     else
-      rusanov_adjoint(qo, qs, S, wb, qLb, qRb, d.pr, false, true);
+      rusanov_adjoint_side(qs, qo, S, wb, qLb, d.pr, own);
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-      const double qsb = own ? qLb[v] : qRb[v];
+      const double qsb = qLb[v];
       Pb[v] += qsb;
       Gb[3 * v] += qsb * ds.x;
       Gb[3 * v + 1] += qsb * ds.y;
