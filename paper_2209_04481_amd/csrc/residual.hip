@@ -122,15 +122,14 @@ __host__ __device__ inline void flux_cell(const DevGrid& d, const double* __rest
         qo[v] = P + (gx * dn.x + gy * dn.y + gz * dn.z);
       }
     }
+    // orientation by value, so that lanes owning and not owning their face
+    // (at panel edges) share one code path
     T F[9];
-    T s = own ? rusanov(qs, qo, S, F, d.pr) : rusanov(qo, qs, S, F, d.pr);
-    if (own) {
+    const T* L = own ? qs : qo;
+    const T* R = own ? qo : qs;
+    T s = rusanov(L, R, S, F, d.pr);
 #pragma unroll
-      for (int v = 0; v < 9; ++v) acc[v] += F[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 9; ++v) acc[v] -= F[v];
-    }
+    for (int v = 0; v < 9; ++v) acc[v] += own ? F[v] : -F[v];
     if (kDiag) speed_area += val(s) * norm3(S);
   }
   T u[9], src[9];
