@@ -477,16 +477,18 @@ struct FluxWG {
         T qs[9], qo[9], F[9];
         if (h == 0) {
           for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
-          if (ti < tiL)
-            for (int v = 0; v < 9; ++v) qo[v] = Sb[v * kNT + t + 1];
-          else
-            for (int v = 0; v < 9; ++v) qo[v] = Rg[v * kRing + tj];
+          // the neighbour's state from the tile or the ring, one code path
+          // for both (lanes of one wavefront take either)
+          const bool in = ti < tiL;
+          const T* src = in ? Sb + t + 1 : Rg + tj;
+          const int stride = in ? kNT : kRing;
+          for (int v = 0; v < 9; ++v) qo[v] = src[v * stride];
         } else {
           for (int v = 0; v < 9; ++v) qs[v] = st.q5[v];
-          if (tj < tjL)
-            for (int v = 0; v < 9; ++v) qo[v] = Sb[(9 + v) * kNT + t + kTI];
-          else
-            for (int v = 0; v < 9; ++v) qo[v] = Rg[v * kRing + 16 + ti];
+          const bool in = tj < tjL;
+          const T* src = in ? Sb + 9 * kNT + t + kTI : Rg + 16 + ti;
+          const int stride = in ? kNT : kRing;
+          for (int v = 0; v < 9; ++v) qo[v] = src[v * stride];
         }
         face_flux(own, qs, qo, S, F, a.d.pr);
         for (int v = 0; v < 9; ++v) st.acc[v] += own ? F[v] : -F[v];
