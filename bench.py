@@ -325,7 +325,7 @@ def main():
     ap.add_argument("--efield-reps", type=int, default=20)
     ap.add_argument("--sweep-reps", type=int, default=100,
                     help="steps of the per-operation percentile pass (library event times per call)")
-    ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 60 s)")
+    ap.add_argument("--sensitivity", action="store_true", help="also time the 20-step B_r sensitivity (about 57 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
