@@ -336,6 +336,42 @@ def test_barth_jespersen_bounds_face_values():
     # the limiter is active: some face reaches an extreme exactly
     act = phi < 1
     assert bool(act.any())
+    _assert_limited_faces_reach_an_extreme(qc, qn, grad, dxf, phi)
+
+
+def _assert_limited_faces_reach_an_extreme(qc, qn, grad, dxf, phi):
+    """Barth-Jespersen takes the largest factor that keeps every face value
+    inside the neighbourhood's range: wherever phi < 1, some face value sits
+    on the bound on its side of q_c (q_max where the extrapolation rises,
+    q_min where it falls).  With the bounds themselves checked separately,
+    this fixes phi; an over-limited factor leaves every face short of both."""
+    d2 = torch.einsum("nva,nfa->nfv", grad, dxf)                # (n, 6, 9)
+    qf = qc[:, None, :] + phi[:, None, :] * d2
+    qmax = torch.maximum(qc, qn.amax(1))[:, None, :]
+    qmin = torch.minimum(qc, qn.amin(1))[:, None, :]
+    ext = torch.where(d2 > 0, qmax, qmin)
+    scale = (qmax - qmin).clamp_min(1e-300)
+    hit = ((qf - ext).abs() <= 1e-13 * scale) & (d2 != 0)
+    act = phi < 1
+    assert bool(hit.any(1)[act].all())
+    # and where phi == 1 no face needed limiting: all within the bounds
+    assert bool(((qf <= qmax + 1e-13 * scale) & (qf >= qmin - 1e-13 * scale)).all())
+
+
+def test_barth_jespersen_is_maximal_on_a_shell_stencil():
+    """The same property on the gradients and neighbour values of a real
+    stencil (the tiny workload's state, every cell and variable)."""
+    from oracle.grid import Grid
+    inst = ci.make_instance(4, 6, "geometric", lmax=0, seed=11)
+    g = Grid(inst.N, inst.Nr, inst.r_nodes)
+    U = torch.from_numpy(inst.U)
+    br = torch.from_numpy(inst.br)
+    cells = torch.arange(g.ncells)
+    st = mhd._Stencil(g, cells)
+    fs = mhd.face_states(g, U, br, mhd.Params(), cells, st)
+    phi = fs["phi"]
+    assert bool((phi < 1).any())
+    _assert_limited_faces_reach_an_extreme(fs["qc"], fs["qn"], fs["g"], fs["dxf"], phi)
 
 
 def test_gravity_and_source():
