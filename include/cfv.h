@@ -97,13 +97,29 @@ cfv_status cfv_grid_sizes(const cfv_grid* g, int64_t* ncells, int64_t* nfaces, i
  * face is a ghost id: ncells + col (inner) or ncells + 6N^2 + col (outer).
  * kind: 0 interior, 1 inner boundary, 2 outer boundary. */
 cfv_status cfv_grid_faces_to_host(const cfv_grid* g, int64_t* L, int64_t* R, int8_t* kind);
+/* Geometry of the finite-volume discretisation (Section 2.1) as the kernels
+ * rebuild it from the per-column tables, on the host (no device needed):
+ * S_f and x_f (host, 3 nfaces, face order of cfv_grid_faces_to_host) the
+ * vector area pointing from L to R (out of the domain on boundary faces) and
+ * the centroid of each face; V_c (ncells) and x_c (3 ncells) the volume and
+ * centroid of each cell.  Vector areas come from the face's four vertices,
+ * S = (v2 - v0) x (v3 - v1) / 2, so the six areas of a cell sum to zero;
+ * V_c = sum_f x_f . S_f / 3.  Caller-owned outputs; CFV_ERR_ARG on a null
+ * pointer. */
+cfv_status cfv_grid_geometry_to_host(const cfv_grid* g, double* S_f, double* x_f, double* V_c, double* x_c);
 
 /* ------------------------------------------------------------- context --
  * Binds a grid and parameters to the current HIP device: uploads the grid
  * tables and allocates the workspaces.  The grid must outlive the context. */
 cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** out);
 void cfv_ctx_destroy(cfv_ctx* ctx);
-/* Copy the inner-boundary B_r map (device array of n = 6N^2 values). */
+/* Copy the inner-boundary B_r map (device array of n = 6N^2 values, order
+ * (p*N + j)*N + i, one per inner face, nondimensional): the magnetogram-
+ * imposed radial field of the inner ghost cells (Section 3.2: B_r Dirichlet
+ * from the map; with the low-E law the boundary velocity is parallel to the
+ * boundary field, Eq. 25, with the outflow constant of Eq. 22).  The residual,
+ * JVP and VJP read the copy, so the caller's array may be freed after the
+ * stream reaches this call.  CFV_ERR_SIZE if n != 6N^2. */
 cfv_status cfv_set_inner_br(cfv_ctx* ctx, const double* br_dev, int64_t n, hipStream_t s);
 
 /* Copy the inner-boundary B_theta map (device array of n = 6N^2 values, the
@@ -119,18 +135,50 @@ cfv_status cfv_set_inner_btheta(cfv_ctx* ctx, const double* bth_dev, int64_t n, 
 cfv_status cfv_geometry(cfv_ctx* ctx, double* xc, double* vol, double* xf, double* S, hipStream_t s);
 
 /* ----------------------------------------------------------- hot path --
- * R = R(U, B_r): ghost fill, reconstruction, Rusanov flux, gravity. */
+ * R = R(U, B_r), the finite-volume residual of ideal MHD with hyperbolic
+ * divergence cleaning (Section 2.1, Eqs. 14-17 in the mu = 1 form, plus the
+ * psi equation with speed c_h): ghost states on the inner boundary from the
+ * B_r map (Section 3.2, Eq. 25 or Eqs. 20-24 by inner_mode) and on the outer
+ * boundary (Table 2 laws, Section 4.1), primitives, a least-squares gradient
+ * over the six face neighbours with the Barth-Jespersen limiter (limiter =
+ * 1), the reconstructed face states, the Rusanov flux of every face evaluated
+ * once in its canonical orientation, and the gravity source at the centroid.
+ * U, R: device [9][ncells] (caller-owned, must not overlap).  Asynchronous on
+ * s; a face state with non-positive (or NaN) density or pressure sets the
+ * context's non-physical flag (cfv_status_flags). */
 cfv_status cfv_residual(cfv_ctx* ctx, const double* U, double* R, hipStream_t s);
-/* Jv = J_U v + J_b dbr (dbr may be NULL: no map direction); when R is not
- * NULL the residual is written too.  Exact forward linearisation; branches
- * follow the primal values. */
+/* Jv = J_U v + J_b dbr, the Jacobian-vector product of the residual: the
+ * linearisation the implicit (Newton-Krylov) pseudo-time step of Section 2.1
+ * solves with.  v, Jv: device [9][ncells]; dbr: device 6N^2 (may be NULL: no
+ * map direction); when R is not NULL the residual is written too.  Exact
+ * forward linearisation (the residual's arithmetic on value-tangent pairs);
+ * branches (limiter choice, |v_n|, speed picks) follow the primal values.
+ * Asynchronous; sets the non-physical flag as cfv_residual. */
 cfv_status cfv_jvp(cfv_ctx* ctx, const double* U, const double* v, const double* dbr, double* Jv, double* R,
                    hipStream_t s);
-/* gU = J_U^T w and (when gbr is not NULL) gbr = J_b^T w (6N^2 values).
- * Deterministic: no floating-point atomics. */
+/* gU = J_U^T w and (when gbr is not NULL) gbr = J_b^T w (6N^2 values): the
+ * adjoint of the Section 2.1 residual linearisation, for transposed solves
+ * of the implicit step and the sensitivity of an outer-boundary objective to
+ * the magnetogram B_r map (Section 3.2).  w, gU: device [9][ncells].  A
+ * hand-written reverse pass, the exact transpose of cfv_jvp's operator
+ * (same branches).  Deterministic: no floating-point atomics.  Asynchronous;
+ * uses the context's workspace. */
 cfv_status cfv_vjp(cfv_ctx* ctx, const double* U, const double* w, double* gU, double* gbr, hipStream_t s);
-/* Backward-Euler diagonal V_c/dt_c = sum_f s_f |S_f| / cfl (s_f Rusanov speed). */
+/* Backward-Euler diagonal of the implicit pseudo-time step with a local
+ * time step set by the CFL number (Sections 2.1 and 4.1): diag[c] = V_c/dt_c
+ * = sum over the six faces of s_f |S_f| / cfl, s_f the Rusanov speed of the
+ * face (max of |v_n| + c_f on both reconstructed sides and c_h).  diag:
+ * device [ncells].  CFV_ERR_ARG unless cfl > 0.  Asynchronous. */
 cfv_status cfv_local_dt(cfv_ctx* ctx, const double* U, double cfl, double* diag, hipStream_t s);
+
+/* Non-physical state check (the face-state positivity condition of the
+ * reconstruction: no fix-up is applied).  The residual, JVP and VJP kernels
+ * OR bit 0 into a per-context device word whenever a reconstructed face state
+ * or a ghost state has density or pressure that is not positive (NaN
+ * included).  This call synchronises s, returns the word in *flags (host,
+ * nullable) and clears it; it returns CFV_ERR_NONPHYSICAL when bit 0 was
+ * set, CFV_OK otherwise.  The flag does not change any output. */
+cfv_status cfv_status_flags(cfv_ctx* ctx, int32_t* flags, hipStream_t s);
 
 /* -------------------------------------------------------- E-field --
  * The ideal-MHD electric field E = -V x B (Section 2.2), the diagnostic the
@@ -152,11 +200,18 @@ cfv_status cfv_efree_state(cfv_ctx* ctx, const double* U, double* U_out, hipStre
 
 /* --------------------------------------------------------- reductions --
  * out9[v] = sqrt(sum_c (a - b)^2) per variable (b may be NULL): the Eq. 2
- * monitor before the log10.  Fixed reduction order (deterministic). */
+ * residual monitor before the log10 (Section 2.1).  a, b: device
+ * [9][ncells]; out9: device, 9 doubles.  Fixed reduction order
+ * (deterministic).  Asynchronous. */
 cfv_status cfv_norms(cfv_ctx* ctx, const double* a, const double* b, double* out9_dev, hipStream_t s);
-/* out[i] = <V_i, w> for k vectors V_i stored back to back (9*ncells each). */
+/* out[i] = <V_i, w> for k vectors V_i stored back to back (9*ncells each,
+ * device; 1 <= k <= 32): the Gram-Schmidt projections of the GMRES solve of
+ * the implicit step (Section 2.1).  out: device, k doubles.  Fixed
+ * reduction order.  Asynchronous. */
 cfv_status cfv_dots(cfv_ctx* ctx, const double* V, int32_t k, const double* w, double* out_dev, hipStream_t s);
-/* y = a*x + b*y over n values (a, b scalars from the host). */
+/* y = a*x + b*y over n device values (a, b scalars from the host): the
+ * vector update of the Krylov solve and of the pseudo-time step (Section
+ * 2.1).  Asynchronous. */
 cfv_status cfv_axpby(cfv_ctx* ctx, int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 
 /* ---------------------------------------------------- implicit solver --
@@ -177,9 +232,12 @@ cfv_status cfv_axpby(cfv_ctx* ctx, int64_t n, double a, const double* x, double 
 cfv_status cfv_solve(cfv_ctx* ctx, const double* U, const double* diag, const double* rhs, int32_t transpose,
                      int32_t m, int32_t max_restarts, double rtol, double* x, double* hist, int32_t hist_len,
                      int32_t* iters, double* final_rel, hipStream_t s);
-/* One backward-Euler pseudo-time step: U_new = U + x with (V/dt + J) x = -R(U),
- * V/dt from cfv_local_dt at the given cfl, solved by cfv_solve.  U_new must
- * not alias U. */
+/* One backward-Euler pseudo-time step (Section 2.1, with the local CFL time
+ * step of Section 4.1): U_new = U + x with (V/dt + J) x = -R(U), V/dt from
+ * cfv_local_dt at the given cfl, solved by cfv_solve.  U, U_new: device
+ * [9][ncells]; U_new must not alias U.  Synchronises s (through cfv_solve).
+ * Returns CFV_ERR_NONPHYSICAL, with U_new undefined, when the residual of U
+ * meets a non-positive or NaN face density or pressure or is not finite. */
 cfv_status cfv_be_step(cfv_ctx* ctx, const double* U, double cfl, int32_t m, int32_t max_restarts, double rtol,
                        double* U_new, double* hist, int32_t hist_len, int32_t* iters, double* final_rel,
                        hipStream_t s);
@@ -212,10 +270,11 @@ typedef struct {
  * of every step, cfl_hist (host, nullable, max_iters) the CFL used, iters the
  * number of steps taken.  The stream is synchronised once per step for the
  * monitor (and once per GMRES iteration inside the solve).  A second state
- * buffer is owned by the context (allocated on first use).  If a step
- * produces a non-finite monitor value the march stops, U keeps the state
- * before that step, the step is counted in iters and recorded in hist, and
- * CFV_ERR_NONPHYSICAL is returned. */
+ * buffer is owned by the context (allocated on first use).  If a step meets
+ * a non-physical face state (cfv_be_step returns CFV_ERR_NONPHYSICAL; its
+ * monitors are recorded as NaN) or produces a non-finite monitor value, the
+ * march stops, U keeps the state before that step, the step is counted in
+ * iters and recorded in hist, and CFV_ERR_NONPHYSICAL is returned. */
 cfv_status cfv_steady(cfv_ctx* ctx, double* U, const cfv_steady_cfg* cfg, double* hist, double* cfl_hist,
                       int32_t* iters, hipStream_t s);
 
@@ -294,6 +353,12 @@ cfv_status cfv_ensemble_residual_jvp(cfv_ensemble* e, const double* const* U, co
  * only (the queue counters are cleared by a kernel, not a memset). */
 cfv_status cfv_ensemble_graph_capture(cfv_ensemble* e, hipStream_t s);
 cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s);
+/* Per-instance non-physical flags of the ensemble's runs (as
+ * cfv_status_flags; an ensemble keeps its own words, separate from its
+ * contexts'): synchronises s, writes n words to flags (host, nullable),
+ * clears them, and returns CFV_ERR_NONPHYSICAL when any instance met a
+ * non-physical face state. */
+cfv_status cfv_ensemble_status_flags(cfv_ensemble* e, int32_t* flags, hipStream_t s);
 /* Per-kernel event timing of eager runs, as cfv_timing_enable / _read. */
 cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on);
 cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, double* total_ms, int64_t* count,
@@ -312,9 +377,10 @@ cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, d
  * instance, the step's output) are 9 ncells each and must not alias.
  * hist (host, nullable, n x max_iters x 9) receives the log10 monitors, NaN
  * after an instance stopped; steps (host, nullable, n) the steps each
- * instance took; iters the lockstep steps run.  An instance whose step gives
- * a non-finite monitor keeps its previous state and stops; the call then
- * returns CFV_ERR_NONPHYSICAL after the others finish.  The ensemble's
+ * instance took; iters the lockstep steps run.  An instance whose step meets
+ * a non-physical face state (its flag word, cfv_ensemble_status_flags) or
+ * gives a non-finite monitor keeps its previous state and stops; the call
+ * then returns CFV_ERR_NONPHYSICAL after the others finish.  The ensemble's
  * binding is replaced by the step binding. */
 cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const* U_work, const cfv_steady_cfg* cfg,
                                double* hist, int32_t* steps, int32_t* iters, hipStream_t s);

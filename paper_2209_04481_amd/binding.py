@@ -40,10 +40,12 @@ class CfvError(RuntimeError):
 
 
 class CfvNonPhysical(CfvError):
-    """A march that produced a non-finite state; hist and cfls hold the steps
-    taken (the last one the failing step) and the state is the one before it."""
+    """Status 4: a non-positive or NaN face density or pressure, or a
+    non-finite solve.  From a march, hist and cfls hold the steps taken (the
+    last one the failing step) and the state is the one before it; from other
+    calls they are None."""
 
-    def __init__(self, msg, hist, cfls):
+    def __init__(self, msg, hist=None, cfls=None):
         super().__init__(msg)
         self.hist, self.cfls = hist, cfls
 
@@ -66,6 +68,7 @@ def lib():
         "cfv_grid_destroy": ([P], None),
         "cfv_grid_sizes": ([P, P, P, P], c_int32),
         "cfv_grid_faces_to_host": ([P, P, P, P], c_int32),
+        "cfv_grid_geometry_to_host": ([P, P, P, P, P], c_int32),
         "cfv_ctx_create": ([P, ctypes.POINTER(CfvParams), ctypes.POINTER(P)], c_int32),
         "cfv_ctx_destroy": ([P], None),
         "cfv_set_inner_br": ([P, P, c_int64, P], c_int32),
@@ -75,6 +78,8 @@ def lib():
         "cfv_jvp": ([P, P, P, P, P, P, P], c_int32),
         "cfv_vjp": ([P, P, P, P, P, P], c_int32),
         "cfv_local_dt": ([P, P, c_double, P, P], c_int32),
+        "cfv_status_flags": ([P, P, P], c_int32),
+        "cfv_ensemble_status_flags": ([P, P, P], c_int32),
         "cfv_efield": ([P, P, P, P, P], c_int32),
         "cfv_efree_state": ([P, P, P, P], c_int32),
         "cfv_monitor": ([P, P, P, P, P], c_int32),
@@ -111,6 +116,8 @@ def lib():
 
 
 def check(status: int):
+    if status == 4:
+        raise CfvNonPhysical(f"cfv status 4: {lib().cfv_last_error().decode()}")
     if status != 0:
         raise CfvError(f"cfv status {status}: {lib().cfv_last_error().decode()}")
 
@@ -179,6 +186,18 @@ class Grid:
         check(lib().cfv_grid_faces_to_host(self._h, L.ctypes.data_as(c_void_p), R.ctypes.data_as(c_void_p),
                                            K.ctypes.data_as(c_void_p)))
         return L, R, K
+
+    def geometry(self):
+        """Host geometry as the kernels build it: per face of the canonical
+        list its vector area S (L -> R, outward on the boundary) and
+        centroid, per cell its volume and centroid."""
+        S = np.empty((self.nfaces, 3), dtype=np.float64)
+        xf = np.empty((self.nfaces, 3), dtype=np.float64)
+        V = np.empty(self.ncells, dtype=np.float64)
+        xc = np.empty((self.ncells, 3), dtype=np.float64)
+        check(lib().cfv_grid_geometry_to_host(self._h, S.ctypes.data_as(c_void_p), xf.ctypes.data_as(c_void_p),
+                                              V.ctypes.data_as(c_void_p), xc.ctypes.data_as(c_void_p)))
+        return S, xf, V, xc
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -269,6 +288,15 @@ class Context:
         check(lib().cfv_jvp_dir(self._h, self._state(U, "U"), self._state(v, "v"), self._state(dU, "dU"), _ptr(dbr),
                                 float(eps), self._state(Jv, "Jv2"), ctypes.byref(h), _stream(stream)))
         return Jv, h.value
+
+    def status_flags(self, stream=None):
+        """The context's non-physical flag word since the last read (bit 0: a
+        face state with non-positive or NaN density or pressure); clears it."""
+        f = c_int32()
+        rc = lib().cfv_status_flags(self._h, ctypes.byref(f), _stream(stream))
+        if rc != 4:
+            check(rc)
+        return f.value
 
     def local_dt(self, U, cfl, out=None, stream=None):
         d = out if out is not None else self._new(self.grid.ncells)
@@ -499,6 +527,14 @@ class Ensemble:
         self.bind(U, v=v, R=R, Jv=Jv)
         self.run(stream)
         return R, Jv
+
+    def status_flags(self, stream=None):
+        """Per-instance non-physical flag words since the last read; clears them."""
+        f = np.zeros(len(self.contexts), dtype=np.int32)
+        rc = lib().cfv_ensemble_status_flags(self._h, f.ctypes.data_as(c_void_p), _stream(stream))
+        if rc != 4:
+            check(rc)
+        return f
 
     def capture(self, stream):
         """Capture one run of the bound ensemble into a graph (stream: a torch.cuda.Stream)."""

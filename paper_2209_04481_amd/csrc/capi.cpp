@@ -132,6 +132,7 @@ struct cfv_ctx {
   // steady-march workspace (allocated on first use)
   double* st_u = nullptr;     // 9 ncells: the other state of the march
   double* st_m = nullptr;     // 9 device scalars: the monitor
+  unsigned* dflag = nullptr;  // non-physical state word set by the kernels
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -142,6 +143,7 @@ struct cfv_ctx {
     d.pr = pr;
     d.br = dbr;
     d.bth = dbth;
+    d.flag = dflag;
     return d;
   }
 };
@@ -318,6 +320,37 @@ cfv_status cfv_grid_faces_to_host(const cfv_grid* g, int64_t* L, int64_t* R, int
   return CFV_OK;
 }
 
+cfv_status cfv_grid_geometry_to_host(const cfv_grid* g, double* S_f, double* x_f, double* V_c, double* x_c) {
+  if (!g || !S_f || !x_f || !V_c || !x_c) return fail(CFV_ERR_ARG, "null argument");
+  const cfv::Shape& s = g->g;
+  const cfv::GeomRef G = g->host_ref();
+  int64_t f = 0;
+  for (int64_t c = 0; c < s.ncells; ++c) {
+    int p, k, j, i;
+    cfv::decode(s, c, p, k, j, i);
+    const cfv::V3 xc = cfv::cell_centre(G, s, p, k, j, i);
+    x_c[3 * c] = xc.x;
+    x_c[3 * c + 1] = xc.y;
+    x_c[3 * c + 2] = xc.z;
+    V_c[c] = cfv::cell_volume(G, s, p, k, j, i);
+    for (int lf = 0; lf < 6; ++lf) {
+      const cfv::Nbr nb = cfv::neighbour(s, p, k, j, i, lf);
+      if (!(nb.id >= s.ncells || nb.id > c)) continue;
+      cfv::V3 S, xf;
+      bool own;
+      cfv::canon_face(G, s, p, k, j, i, lf, nb, c, S, xf, own);
+      S_f[3 * f] = S.x;
+      S_f[3 * f + 1] = S.y;
+      S_f[3 * f + 2] = S.z;
+      x_f[3 * f] = xf.x;
+      x_f[3 * f + 1] = xf.y;
+      x_f[3 * f + 2] = xf.z;
+      ++f;
+    }
+  }
+  return CFV_OK;
+}
+
 cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** out) {
   g_err.clear();
   if (!g || !prm || !out) return fail(CFV_ERR_ARG, "null argument");
@@ -351,7 +384,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
       (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
       (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector())) ||
-      (st = dmalloc(&c->slot, 1))) {
+      (st = dmalloc(&c->slot, 1)) || (st = dmalloc(&c->dflag, 1))) {
     cfv_ctx_destroy(c);
     return st;
   }
@@ -360,6 +393,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (e == hipSuccess) e = hipMemcpy(c->dr, g->r.data(), g->r.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(c->dbr, 0, size_t(g->g.nb) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->dbth, 0, size_t(g->g.nb) * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->dflag, 0, sizeof(unsigned));
   if (e != hipSuccess) {
     cfv_ctx_destroy(c);
     return hip_fail(e, "uploading grid tables");
@@ -375,6 +409,7 @@ void cfv_ctx_destroy(cfv_ctx* c) {
     if (b) (void)hipFree(b);
   if (c->dcn) (void)hipFree(c->dcn);
   if (c->slot) (void)hipFree(c->slot);
+  if (c->dflag) (void)hipFree(c->dflag);
   double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
                   c->dir_u, c->dir_g, c->dir_b, c->dir_s, c->st_u, c->st_m};
   for (double* b : kb)
@@ -434,6 +469,25 @@ cfv_status cfv_local_dt(cfv_ctx* c, const double* U, double cfl, double* diag, h
   if (!U || !diag) return fail(CFV_ERR_ARG, "null state or output");
   if (!(cfl > 0.0)) return fail(CFV_ERR_ARG, "cfl must be positive");
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, diag, c->W, s, c->tm()));
+  return CFV_OK;
+}
+
+// read and clear a device flag word (synchronises s)
+static cfv_status take_flags(unsigned* dflag, unsigned* out, hipStream_t s) {
+  unsigned h = 0;
+  CFV_HIP(hipMemcpyAsync(&h, dflag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  CFV_HIP(hipStreamSynchronize(s));
+  if (h) CFV_HIP(hipMemsetAsync(dflag, 0, sizeof(unsigned), s));
+  *out = h;
+  return CFV_OK;
+}
+
+cfv_status cfv_status_flags(cfv_ctx* c, int32_t* flags, hipStream_t s) {
+  if (cfv_status st = check_ctx(c)) return st;
+  unsigned h = 0;
+  if (cfv_status st = take_flags(c->dflag, &h, s)) return st;
+  if (flags) *flags = int32_t(h);
+  if (h & 1u) return fail(CFV_ERR_NONPHYSICAL, "a face state with non-positive or NaN density or pressure was met");
   return CFV_OK;
 }
 
@@ -529,6 +583,7 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
   CFV_HIP(cfv::launch_norm2(n, rhs, hd, c->part, s));
   CFV_HIP(hipMemcpyAsync(&bnorm, hd, sizeof(double), hipMemcpyDeviceToHost, s));
   CFV_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(bnorm)) return fail(CFV_ERR_NONPHYSICAL, "the right-hand side is not finite");
   int total = 0;
   double rel = bnorm > 0.0 ? 1.0 : 0.0;
   if (bnorm == 0.0) {
@@ -550,6 +605,7 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
     CFV_HIP(hipMemcpyAsync(&beta, hd, sizeof(double), hipMemcpyDeviceToHost, s));
     CFV_HIP(cfv::launch_div_dev(n, hd, r, V, s));
     CFV_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(beta)) return fail(CFV_ERR_NONPHYSICAL, "the Krylov residual is not finite");
     if (!(beta > 0.0)) break;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -567,7 +623,10 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
                                      hd + i + 1, c->part, s));
       CFV_HIP(hipMemcpyAsync(col.data(), hd, size_t(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       CFV_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j + 1; ++i) Hc(i, j) = col[i];
+      for (int i = 0; i <= j + 1; ++i) {
+        if (!std::isfinite(col[i])) return fail(CFV_ERR_NONPHYSICAL, "a Krylov projection is not finite");
+        Hc(i, j) = col[i];
+      }
       const double hnext = col[j + 1];
       if (hnext > 0.0) CFV_HIP(cfv::launch_div_dev(n, hd + j + 1, w, V + size_t(j + 1) * n, s));
       // Givens rotations on the new column
@@ -620,7 +679,13 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   const int64_t n = 9 * c->grid->g.ncells;
   // U_new holds the right-hand side -R(U) during the solve
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
+  CFV_HIP(hipMemsetAsync(c->dflag, 0, sizeof(unsigned), s));  // flags of earlier calls are not this step's
   CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
+  {
+    unsigned h = 0;
+    if (cfv_status st = take_flags(c->dflag, &h, s)) return st;
+    if (h & 1u) return fail(CFV_ERR_NONPHYSICAL, "the state has a face with non-positive or NaN density or pressure");
+  }
   CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
   if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
@@ -666,6 +731,13 @@ cfv_status cfv_steady(cfv_ctx* c, double* U, const cfv_steady_cfg* cfg, double* 
   while (done < cfg->max_iters) {
     const double cfl = std::min(std::ldexp(cfg->cfl0, done / cfg->every), cfg->cfl_max);
     out = cfv_be_step(c, cur, cfl, cfg->m, cfg->max_restarts, cfg->rtol, nxt, nullptr, 0, nullptr, nullptr, s);
+    if (out == CFV_ERR_NONPHYSICAL) {  // the step is counted, its monitors are NaN, U keeps the state before it
+      if (hist)
+        for (int v = 0; v < 9; ++v) hist[int64_t(done) * 9 + v] = std::nan("");
+      if (cfl_hist) cfl_hist[done] = cfl;
+      ++done;
+      break;
+    }
     if (out == CFV_OK) out = cfv_monitor(c, cur, nxt, c->st_m, s);
     double mon[9];
     if (out == CFV_OK) {
@@ -866,6 +938,7 @@ struct cfv_ensemble {
   double* step_part = nullptr;           // n x kStepBlocks partial sums
   cfv::StepLaunch step;
   double* mon = nullptr;                 // 9 n device scalars: monitors of the batched march
+  unsigned* dflags = nullptr;            // n non-physical state words, one per instance
 };
 
 namespace {
@@ -963,11 +1036,13 @@ cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning
   e->total = e->off[size_t(n)];
   cfv_status st;
   if ((st = dmalloc(&e->dargs, size_t(n))) || (st = dmalloc(&e->doff, size_t(n) + 1)) ||
-      (st = dmalloc(&e->dperm, size_t(e->total))) || (st = dmalloc(&e->dcnt, 2))) {
+      (st = dmalloc(&e->dperm, size_t(e->total))) || (st = dmalloc(&e->dcnt, 2)) ||
+      (st = dmalloc(&e->dflags, size_t(n)))) {
     cfv_ensemble_destroy(e);
     return st;
   }
   he = hipMemcpy(e->doff, e->off.data(), e->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(e->dflags, 0, size_t(n) * sizeof(unsigned));
   if (he != hipSuccess) {
     cfv_ensemble_destroy(e);
     return fail(CFV_ERR_HIP, hipGetErrorString(he));
@@ -984,7 +1059,7 @@ void cfv_ensemble_destroy(cfv_ensemble* e) {
   if (!e) return;
   drop_graph(e);
   void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt, e->step_args, e->step_sv, e->step_arena, e->step_part,
-                  e->mon};
+                  e->mon, e->dflags};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -1020,6 +1095,7 @@ cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const doub
       return fail(CFV_ERR_ARG, "null pointer for instance " + std::to_string(q));
     h[q] = cfv::MarchArgs{c->dev(), U[q], dual ? v[q] : nullptr, dbr ? dbr[q] : nullptr, c->W,
                           dual ? c->Wd : nullptr, R ? R[q] : nullptr, dual ? Jv[q] : nullptr};
+    h[q].d.flag = e->dflags + q;
   }
   CFV_HIP(hipMemcpy(e->dargs, h.data(), n * sizeof(cfv::MarchArgs), hipMemcpyHostToDevice));
   e->dual = dual;
@@ -1097,7 +1173,8 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
     v.sm = p;
     p += Y.size;
     v.nc = nc;
-    const cfv::DevGrid d = c->dev();
+    cfv::DevGrid d = c->dev();
+    d.flag = e->dflags + q;
     args[q] = cfv::MarchArgs{d, U[q], nullptr, nullptr, c->W, nullptr, U_new[q], nullptr};
     for (int j = 0; j < m; ++j)
       args[size_t(1 + j) * n + q] = cfv::MarchArgs{d, U[q], v.V + size_t(j) * n9, nullptr, c->W, c->Wd, nullptr, v.w};
@@ -1151,6 +1228,24 @@ cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s) {
   return CFV_OK;
 }
 
+cfv_status cfv_ensemble_status_flags(cfv_ensemble* e, int32_t* flags, hipStream_t s) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  const size_t n = e->ctx.size();
+  std::vector<unsigned> h(n);
+  CFV_HIP(hipMemcpyAsync(h.data(), e->dflags, n * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  CFV_HIP(hipStreamSynchronize(s));
+  CFV_HIP(hipMemsetAsync(e->dflags, 0, n * sizeof(unsigned), s));
+  int first = -1;
+  for (size_t q = 0; q < n; ++q) {
+    if (flags) flags[q] = int32_t(h[q]);
+    if ((h[q] & 1u) && first < 0) first = int(q);
+  }
+  if (first >= 0)
+    return fail(CFV_ERR_NONPHYSICAL, "instance " + std::to_string(first) +
+                                         " met a face with non-positive or NaN density or pressure");
+  return CFV_OK;
+}
+
 cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const* U_work, const cfv_steady_cfg* cfg,
                                double* hist, int32_t* steps, int32_t* iters, hipStream_t s) {
   if (!e) return fail(CFV_ERR_ARG, "null ensemble");
@@ -1169,6 +1264,8 @@ cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const*
   std::vector<char> active(n, 1);
   std::vector<int32_t> taken(n, 0);
   std::vector<double> mon(9 * n);
+  std::vector<unsigned> flg(n);
+  CFV_HIP(hipMemsetAsync(e->dflags, 0, n * sizeof(unsigned), s));
   if (hist)
     for (size_t a = 0; a < n * size_t(cfg->max_iters) * 9; ++a) hist[a] = std::nan("");
   cfv_status out = CFV_OK;
@@ -1188,13 +1285,15 @@ cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const*
       if (active[q]) out = cfv_monitor(e->ctx[q], U[q], U_work[q], e->mon + 9 * q, s);
     if (out == CFV_OK) {
       hipError_t he = hipMemcpyAsync(mon.data(), e->mon, 9 * n * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipMemcpyAsync(flg.data(), e->dflags, n * sizeof(unsigned), hipMemcpyDeviceToHost, s);
       if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he == hipSuccess) he = hipMemsetAsync(e->dflags, 0, n * sizeof(unsigned), s);
       if (he != hipSuccess) out = hip_fail(he, "monitor read-back");
     }
     if (out != CFV_OK) break;
     for (size_t q = 0; q < n; ++q) {
       if (!active[q]) continue;
-      bool finite = true;
+      bool finite = !(flg[q] & 1u);  // a non-physical face state makes the step's result meaningless
       for (int v = 0; v < 9; ++v) {
         const double x = std::log10(mon[9 * q + v]);
         if (std::isnan(x) || (std::isinf(x) && x > 0.0)) finite = false;

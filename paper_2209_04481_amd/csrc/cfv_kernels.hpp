@@ -15,7 +15,24 @@ struct DevGrid {
   Params pr;
   const double* br;  // inner-boundary B_r map, 6N^2, order (p, j, i)
   const double* bth = nullptr;  // inner-boundary B_theta map (large-E law), same order
+  unsigned* flag = nullptr;     // non-physical state word (bit 0), nullable
 };
+
+// A face state is physical when its density and pressure are positive (a NaN
+// fails too); the kernels record any other in the instance's flag word with
+// an integer OR (order-free, so results stay deterministic).
+template <class T>
+__host__ __device__ __forceinline__ bool physical(const T q[9]) {
+  return val(q[0]) > 0.0 && val(q[7]) > 0.0;
+}
+__host__ __device__ __forceinline__ void record_nonphysical(const DevGrid& d, bool bad) {
+  if (!bad || !d.flag) return;
+#if defined(__HIP_DEVICE_COMPILE__)
+  atomicOr(d.flag, 1u);
+#else
+  *d.flag |= 1u;
+#endif
+}
 
 // The first kernel argument read in place from the kernel-argument segment:
 // large descriptors (grid, parameters) are then loaded where they are used

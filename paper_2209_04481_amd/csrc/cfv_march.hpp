@@ -253,6 +253,11 @@ struct GradWG {
       ghost_prims(a.d, st.p, k, st.j, st.i, 1, st.P0, xc, T(0.0), gout, xG);
     }
     const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+    bool bad = false;
+    if constexpr (Faces) {
+      if (k == 0) bad = bad || !physical(gin);
+      if (k + 1 == g.Nr) bad = bad || !physical(gout);
+    }
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
       T qn[6];
@@ -268,10 +273,14 @@ struct GradWG {
         stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
       } else {  // instead of the gradient, the reconstructed state at each face centroid
 #pragma unroll
-        for (int lf = 0; lf < 6; ++lf)
-          gst(a.Q, (9 * lf + v) * g.ncells + c, val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z)));
+        for (int lf = 0; lf < 6; ++lf) {
+          const double qf = val(st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z));
+          gst(a.Q, (9 * lf + v) * g.ncells + c, qf);
+          if (v == 0 || v == 7) bad = bad || !(qf > 0.0);
+        }
       }
     }
+    if constexpr (Faces) record_nonphysical(a.d, bad);
     for (int v = 0; v < 9; ++v) {
       st.Pm[v] = st.P0[v];
       st.P0[v] = st.Pp[v];
@@ -289,6 +298,7 @@ struct FState {
   T accp[9];  // residual of layer k-1 without its top face
   T acc[9];   // residual of layer k so far
   T q3[9], q5[9];
+  bool bad;   // a face state of this column met a non-positive density or pressure
 };
 
 template <class T>
@@ -368,6 +378,7 @@ struct FluxWG {
     st.j = tm.j0 + t / kTI;
     st.i = tm.i0 + t % kTI;
     st.act = st.j < g.N && st.i < g.N;
+    st.bad = false;
     if (!st.act || tm.k0 == 0) return;
     // top-face state of the layer below the chunk
     st.col = column_of(g, st.p, st.j, st.i);
@@ -401,10 +412,12 @@ struct FluxWG {
       canon_face(G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
       T qb[9], F[9];
       recon(P, Gr, xf - xc, qb);
+      st.bad = st.bad || !physical(qb);
       if (k == 0) {
         T qG[9];
         V3 xG;
         ghost_prims(a.d, st.p, k, st.j, st.i, 0, P, xc, map_br<T>(a, st.col), qG, xG);
+        st.bad = st.bad || !physical(qG);
         rusanov(qb, qG, S, F, a.d.pr);
         for (int v = 0; v < 9; ++v) st.acc[v] = F[v];
       } else {
@@ -428,10 +441,12 @@ struct FluxWG {
       bool own;
       canon_face(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
       recon(P, Gr, xf - xc, st.qtop);
+      st.bad = st.bad || !physical(st.qtop);
       if (k == g.Nr - 1) {
         T qG[9], F[9];
         V3 xG;
         ghost_prims(a.d, st.p, k, st.j, st.i, 1, P, xc, T(0.0), qG, xG);
+        st.bad = st.bad || !physical(qG);
         rusanov(st.qtop, qG, S, F, a.d.pr);
         for (int v = 0; v < 9; ++v) st.acc[v] += F[v];
       }
@@ -444,6 +459,7 @@ struct FluxWG {
       canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
       T s[9];
       recon(P, Gr, xf - xc, s);
+      st.bad = st.bad || !physical(s);
       if (q == 0)
         for (int v = 0; v < 9; ++v) Sb[v * kNT + t] = s[v];
       else if (q == 2)
@@ -542,6 +558,7 @@ struct FluxWG {
 
   // the last layer of the chunk still needs the radial face above it
   __host__ __device__ static void finish(const MarchArgs& a, const TileMap& tm, FState<T>& st, int) {
+    record_nonphysical(a.d, st.act && st.bad);
     if (!st.act || tm.k1 >= a.d.g.Nr) return;
     const Shape& g = a.d.g;
     const int k = tm.k1;

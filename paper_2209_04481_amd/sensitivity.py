@@ -151,3 +151,21 @@ class Sensitivity:
             ctx.axpby(-1.0, dx, 1.0, dU)
             U = Un
         return self._objective(U), self._objective(dU)
+
+    def tangents(self, br: torch.Tensor, dbs):
+        """dL along each map direction of dbs by forward tangent sweeps that
+        share one forward trajectory (its solves done once); returns (L, [dL])."""
+        ctx = self.ctx
+        ctx.set_inner_br(br)
+        U = self.U0.clone()
+        dUs = [torch.zeros_like(U) for _ in dbs]
+        for _ in range(self.nsteps):
+            Un, x = self._step(U)
+            for dU, db in zip(dUs, dbs):
+                t = ctx.jvp(U, dU, dbr=db)
+                t2, _ = ctx.jvp_dir(U, x, dU, dbr=db, eps=self.eps)
+                ctx.axpby(1.0, t2, 1.0, t)
+                dx = self._solve(U, t, False)
+                ctx.axpby(-1.0, dx, 1.0, dU)
+            U = Un
+        return self._objective(U), [self._objective(dU) for dU in dUs]

@@ -53,6 +53,30 @@ def test_face_list_bit_exact_vs_geometric_matching(built, N, Nr, radial):
     assert np.array_equal(K.astype(np.int64), oK.numpy())
 
 
+@pytest.mark.parametrize("N,Nr,radial", [(8, 16, "geometric"), (5, 3, "log"), (3, 1, "log"), (6, 12, "bcind")])
+def test_geometry_to_host_matches_the_oracle_vertex_geometry(built, N, Nr, radial):
+    """cfv_grid_geometry_to_host (the kernels' separable geometry, rebuilt
+    from the per-column tables) against the oracle's cell geometry from the
+    vertices: per face of the canonical list the owner's vector area and
+    centroid, per cell its volume and centroid."""
+    from paper_2209_04481_amd import Grid
+    r = ci.radial_nodes(Nr, radial)
+    g = Grid(N, Nr, r)
+    S, xf, V, xc = g.geometry()
+    og = OracleGrid(N, Nr, r)
+    cells = torch.arange(og.ncells)
+    oxc, oV, oxf, oS = og.cell_geometry(cells)
+    nb = og.neighbours(cells)
+    emit = (nb >= og.ncells) | (nb > cells[:, None])       # the canonical list's rule
+    fS, fx = oS[emit].numpy(), oxf[emit].numpy()
+    assert S.shape == fS.shape
+    sc = np.abs(fS).max()
+    assert np.abs(S - fS).max() <= 1e-13 * sc
+    assert np.abs(xf - fx).max() <= 1e-13 * np.abs(fx).max()
+    assert np.abs(V - oV.numpy()).max() <= 1e-13 * oV.abs().max().item()
+    assert np.abs(xc - oxc.numpy()).max() <= 1e-13 * np.abs(oxc.numpy()).max()
+
+
 def test_grid_sizes_and_argument_errors(built):
     from paper_2209_04481_amd import CfvError, Grid
     g = Grid(6, 4, ci.radial_nodes(4, "log"))
