@@ -13,9 +13,14 @@ launches against 64 single-instance launches in sequence.
 Prints ONE JSON line.  `value` is the throughput of whole steps in Mcell/s
 (cells x steps / wall time of the timed region, inputs resident in HBM).
 Per-kernel durations come from HIP events recorded on the launch stream by
-the library over the timed region; the roofline entry is for the operation
-whose kernels take the most time, with its algorithmic bytes per cell.
-The CPU baseline times the oracle (test infrastructure) on a bounded sample.
+the library over the timed region.  The `roofline` entry is the residual's
+(the metric's HBM fraction is stated for the 13M-cell residual): its
+algorithmic bytes per cell times the cells, over its kernels' average time
+per launch; `roofline_ops` gives the same, with counter traffic and the FP64
+work against the vector peak, for the residual, the JVP and the VJP.
+The CPU baseline times the oracle (test infrastructure) on bounded samples:
+per operation on one thread and on all threads, with the host's nproc and
+CPU model.
 """
 from __future__ import annotations
 
@@ -65,35 +70,101 @@ def profile_record(prefix: str, match: dict):
     return None, None
 
 
-def cpu_baseline(inst, ncells_sample: int, workload: str):
-    """Oracle residual + JVP + VJP on a contiguous block of cells in the
-    middle of the shell (at most the whole shell)."""
+def host_cpu_info():
+    """nproc and the CPU model of the host (lscpu), for the baseline record."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip()
+        info["nproc"] = int(out)
+    except Exception:
+        pass
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
+def _oracle_sample(inst, n: int, seed: int):
+    """A contiguous block of n cells in the middle of the shell, with a JVP
+    direction on its distance-2 stencil and VJP weights on the block."""
     import torch
 
-    from oracle import mhd, solve
+    from oracle import mhd
     from oracle.grid import Grid as OGrid
-
     og = OGrid(inst.N, inst.Nr, inst.r_nodes)
     U = torch.from_numpy(inst.U)
     br = torch.from_numpy(inst.br)
-    n = min(ncells_sample, inst.ncells)
+    n = min(n, inst.ncells)
     start = (inst.ncells - n) // 2
     cells = torch.arange(start, start + n)
-    op = mhd.Params()
-    gen = torch.Generator().manual_seed(inst.seed)
-    vfull = torch.zeros_like(U)
+    gen = torch.Generator().manual_seed(seed)
+    v = torch.zeros_like(U)
     st = mhd._Stencil(og, cells)
-    vfull[:, st.D2] = torch.randn(9, st.D2.numel(), dtype=torch.float64, generator=gen) * U[:, st.D2].abs()
+    v[:, st.D2] = torch.randn(9, st.D2.numel(), dtype=torch.float64, generator=gen) * U[:, st.D2].abs()
     w = torch.randn(9, n, dtype=torch.float64, generator=gen)
-    t0 = time.perf_counter()
-    mhd.residual(og, U, br, op, cells=cells)
-    solve.jvp(og, U, br, op, vfull, cells=cells)
-    solve.vjp(og, U, br, op, w, cells=cells)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt / 1e6, "unit": "Mcell/s (residual+JVP+VJP step)",
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{n} contiguous cells of the {workload} workload (distance-2 stencil gathered), "
-                      f"{dt:.1f} s"}
+    return og, U, br, cells, v, w
+
+
+def cpu_baseline(insts: dict, ncells_sample: int = 10000, reps: int = 3):
+    """The oracle (plain float64 PyTorch CPU code) timed on the host: per
+    workload, the residual and the JVP on a contiguous block of cells, on one
+    thread and on all the threads torch uses, the median of `reps` runs each;
+    and the whole step (residual + JVP + VJP) on all threads, whose rate on
+    the first workload is the record's value."""
+    import statistics
+
+    import torch
+
+    from oracle import mhd, solve
+    info = host_cpu_info()
+    nthr = torch.get_num_threads()
+    per = {}
+    value = None
+    for name, inst in insts.items():
+        og, U, br, cells, v, w = _oracle_sample(inst, ncells_sample, inst.seed)
+        n = cells.numel()
+        op = mhd.Params()
+        ops = {"residual": lambda: mhd.residual(og, U, br, op, cells=cells),
+               "jvp": lambda: solve.jvp(og, U, br, op, v, cells=cells)}
+        rec = {}
+        for opn, fn in ops.items():
+            r = {}
+            for label, th in (("1_thread", 1), ("all_threads", nthr)):
+                torch.set_num_threads(th)
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    fn()
+                    ts.append(time.perf_counter() - t0)
+                r[label + "_mcells_per_s"] = round(n / statistics.median(ts) / 1e6, 5)
+            r["ideal_all_core_mcells_per_s"] = round(r["1_thread_mcells_per_s"] * info["nproc"], 4)
+            rec[opn] = r
+        torch.set_num_threads(nthr)
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            mhd.residual(og, U, br, op, cells=cells)
+            solve.jvp(og, U, br, op, v, cells=cells)
+            solve.vjp(og, U, br, op, w, cells=cells)
+            ts.append(time.perf_counter() - t0)
+        rec["step_all_threads_mcells_per_s"] = round(n / statistics.median(ts) / 1e6, 5)
+        rec["sample_cells"] = n
+        per[name] = rec
+        if value is None:
+            value = rec["step_all_threads_mcells_per_s"]
+    first = next(iter(insts))
+    return {"value": value, "unit": "Mcell/s (residual+JVP+VJP step)", "cores": nthr, "kind": "oracle",
+            "sample": f"{ncells_sample} contiguous cells (distance-2 stencil gathered) of each of the "
+                      f"{', '.join(insts)} workloads, median of {reps} runs; value: the {first} workload's step "
+                      f"on {nthr} threads",
+            "nproc": info["nproc"], "host": {k: v for k, v in info.items() if k != "nproc"},
+            "per_workload": per}
 
 
 def bench_solver(with_sensitivity: bool):
@@ -315,7 +386,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["tiny", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=786432)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 1 GiB buffer twice (reference dispatches for HBM counters)")
@@ -416,16 +487,36 @@ def main():
     op_ms = {}
     for op, ks in OP_KERNELS.items():
         op_ms[op] = sum(times[k][0] / times[k][1] for k in ks if k in times)
-    dom = max(op_ms, key=op_ms.get)
-    achieved = ALG_BYTES[dom] * nc / (op_ms[dom] * 1e-3) / 1e9
-    trec, traffic_src = profile_record("traffic-record", {"kernel": dom, "workload": args.workload})
-    traffic = trec["bytes_per_launch"] if trec else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_note": ("bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy; "
-                                 f"from {traffic_src}") if traffic_src else None,
-                "kernel": f"{dom} ({' + '.join(OP_KERNELS[dom])})", "avg_ms": round(op_ms[dom], 4),
-                "alg_bytes_per_cell": ALG_BYTES[dom]}
+    vrec, vsrc = profile_record("valu-record", {"workload": args.workload})
+
+    def op_roofline(op):
+        """HBM roofline of one operation (algorithmic bytes over its kernels'
+        average time per launch, from HIP events on the launch stream), the
+        counter traffic of the committed rocprofv3 record (null once the
+        kernel sources changed), and its FP64 work against the vector peak."""
+        achieved = ALG_BYTES[op] * nc / (op_ms[op] * 1e-3) / 1e9
+        trec, traffic_src = profile_record("traffic-record", {"kernel": op, "workload": args.workload})
+        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": trec["bytes_per_launch"] if trec else None,
+             "traffic_note": ("bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy; "
+                              f"from {traffic_src}") if traffic_src else None,
+             "kernel": f"{op} ({' + '.join(OP_KERNELS[op])})", "avg_ms": round(op_ms[op], 4),
+             "alg_bytes_per_cell": ALG_BYTES[op]}
+        if trec:
+            r["traffic_bytes_per_cell"] = round(trec["bytes_per_launch"] / nc, 1)
+        if vrec and op in vrec["flop_per_cell"]:
+            f = vrec["flop_per_cell"][op]
+            tf = f * nc / (op_ms[op] * 1e-3) / 1e12
+            r["fp64"] = {"flop_per_cell": f, "tflops": round(tf, 2), "peak_tflops": FP64_PEAK_TFLOPS,
+                         "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                         "floor_ms": round(f * nc / (FP64_PEAK_TFLOPS * 1e12) * 1e3, 4),
+                         "source": vsrc}
+        return r
+
+    # the headline is the residual's: the metric's "% of HBM roofline" is
+    # stated for the 13M-cell residual
+    roofline = op_roofline("residual")
+    roofline_ops = {op: op_roofline(op) for op in OP_KERNELS}
 
     out = {
         "metric": "Mcell-residuals/s and JVP+VJP/s FP64 at 13M cells; % of HBM roofline; ensemble speedup",
@@ -447,13 +538,13 @@ def main():
                               for op, v in per_step.items()},
         "kernels": {k: {"avg_ms": round(d["avg_ms"], 4), "launches": d["launches"]} for k, d in per_kernel.items()},
         "roofline": roofline,
+        "roofline_ops": roofline_ops,
         "step_r_from_jvp": {"mcells_per_s": round(nc * args.steps / (tf1 - tf0) / 1e6, 2),
                             "ms_per_step": round((tf1 - tf0) * 1e3 / args.steps, 4),
                             "max_rel_r_difference": r_diff,
                             "note": "the step with R written by the JVP launch (cfv_jvp with R) instead of a "
                                     "residual launch of its own; not the headline value"},
     }
-    vrec, vsrc = profile_record("valu-record", {"workload": args.workload})
     if vrec:
         out["fp64_valu"] = {
             op: {"flop_per_cell": f, "tflops": round(f * nc / (op_ms[op] * 1e-3) / 1e12, 2),
@@ -483,7 +574,10 @@ def main():
         out["ensemble"] = bench_ensemble(args.ensemble_reps, args.solve_reps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_sample, args.workload)
+        insts = {args.workload: inst}
+        if args.workload == "large":
+            insts["medium"] = ci.workload("medium")
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

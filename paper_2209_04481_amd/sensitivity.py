@@ -152,14 +152,17 @@ class Sensitivity:
             U = Un
         return self._objective(U), self._objective(dU)
 
-    def tangents(self, br: torch.Tensor, dbs):
+    def tangents(self, br: torch.Tensor, dbs, log=None):
         """dL along each map direction of dbs by forward tangent sweeps that
-        share one forward trajectory (its solves done once); returns (L, [dL])."""
+        share one forward trajectory (its solves done once); returns (L, [dL]).
+        log: optional callable given a line after every step."""
         ctx = self.ctx
         ctx.set_inner_br(br)
         U = self.U0.clone()
         dUs = [torch.zeros_like(U) for _ in dbs]
-        for _ in range(self.nsteps):
+        for n in range(self.nsteps):
+            if log is not None:
+                log(f"tangent sweeps: step {n + 1} of {self.nsteps}")
             Un, x = self._step(U)
             for dU, db in zip(dUs, dbs):
                 t = ctx.jvp(U, dU, dbr=db)

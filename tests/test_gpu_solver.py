@@ -193,7 +193,7 @@ def test_br_sensitivity_adjoint_matches_tangent(name, limiter, cfl, layer, ndir,
     assert sens.max_rel <= 1e-12
     dirs = _map_dirs(ctx, br, ndir)
     t0 = time.time()
-    Lt, dLs = sens.tangents(br, dirs)
+    Lt, dLs = sens.tangents(br, dirs, log=lambda s: print("  " + s, flush=True))
     print(f"  {ndir} tangent sweeps sharing one trajectory: {time.time() - t0:.2f} s")
     assert Lt == L
     for q, (d, dL) in enumerate(zip(dirs, dLs)):

@@ -110,6 +110,10 @@ def test_bench_cpu_baseline_record_on_a_small_shell():
     sys.path.insert(0, here)
     import bench
     inst = ci.make_instance(4, 3, "log", lmax=2, seed=5)
-    rec = bench.cpu_baseline(inst, 10 ** 6, "small")
-    assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] >= 1
-    assert rec["sample"].startswith(f"{inst.ncells} contiguous cells of the small workload")
+    rec = bench.cpu_baseline({"small": inst}, 10 ** 6, reps=1)
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] >= 1 and rec["nproc"] >= 1
+    small = rec["per_workload"]["small"]
+    assert small["sample_cells"] == inst.ncells
+    for op in ("residual", "jvp"):
+        assert small[op]["1_thread_mcells_per_s"] > 0 and small[op]["all_threads_mcells_per_s"] > 0
+    assert rec["value"] == small["step_all_threads_mcells_per_s"]
