@@ -478,8 +478,8 @@ def test_vjp_matches_central_differences_64_directions_medium(limiter):
     weight cancels (it is far smaller than |w| |Jv|), so its difference
     quotient's error is held relative to |w| |Jv|, its Cauchy-Schwarz bound:
     1e-6, the normwise accuracy of the difference quotient on the remaining
-    cells (see the JVP test); measured about 1e-9.  The median of the plain
-    relative errors stays below 1e-6 as well (measured 2e-7)."""
+    cells (see the JVP test).  The median of the plain relative errors stays
+    below 1e-6 as well (measured 2e-7)."""
     print(f"case: VJP vs central differences, medium, 64 directions, limiter {limiter}", flush=True)
     inst = ci.workload("medium")
     c = Case(inst, mhd.Params(limiter=limiter))
