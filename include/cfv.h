@@ -209,6 +209,18 @@ cfv_status cfv_norms(cfv_ctx* ctx, const double* a, const double* b, double* out
  * the implicit step (Section 2.1).  out: device, k doubles.  Fixed
  * reduction order.  Asynchronous. */
 cfv_status cfv_dots(cfv_ctx* ctx, const double* V, int32_t k, const double* w, double* out_dev, hipStream_t s);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the dot
+ * products of cfv_dots without a context, out[i] = <V_i, w> for k vectors V_i
+ * of n entries each stored back to back (device), w (device, n), out
+ * (device, k).  Nothing is allocated: the partial sums live in a static
+ * device array of 32 x 1024 doubles (256 KiB, held by each device the library
+ * runs on until the process ends), so 1 <= k <= 32 (CFV_ERR_ARG otherwise,
+ * before any device work).  The same kernels and launch shape as cfv_dots:
+ * the results are bitwise those of cfv_dots.  Calls that overlap on one
+ * device share that array and race: order them on one stream.
+ * Asynchronous. */
+cfv_status cfv_dots_noalloc(int64_t n, const double* V, int32_t k, const double* w, double* out, hipStream_t s);
 /* y = a*x + b*y over n device values (a, b scalars from the host): the
  * vector update of the Krylov solve and of the pseudo-time step (Section
  * 2.1).  Asynchronous. */

@@ -78,6 +78,7 @@ def lib():
         "cfv_jvp": ([P, P, P, P, P, P, P], c_int32),
         "cfv_vjp": ([P, P, P, P, P, P], c_int32),
         "cfv_local_dt": ([P, P, c_double, P, P], c_int32),
+        "cfv_dots_noalloc": ([c_int64, P, c_int32, P, P, P], c_int32),
         "cfv_status_flags": ([P, P, P], c_int32),
         "cfv_ensemble_status_flags": ([P, P, P], c_int32),
         "cfv_efield": ([P, P, P, P, P], c_int32),
@@ -161,6 +162,20 @@ def _ptr_array(ts, what):
     for q, t in enumerate(ts):
         arr[q] = _ptr(t).value if t is not None else None
     return arr
+
+
+def dots_noalloc(V, w, k=None, out=None, stream=None):
+    """out[i] = <V[i], w> for the first k rows of V (k <= 32) without a
+    context and without device allocation in the library (cfv_dots_noalloc);
+    V: (k, n) and w: (n,) contiguous float64 CUDA tensors, out: (k,) or new."""
+    import torch
+    k = V.shape[0] if k is None else int(k)
+    n = w.numel()
+    if V.numel() < k * n:
+        raise CfvError("V must hold k vectors of w's length")
+    o = out if out is not None else torch.empty(k, dtype=torch.float64, device=w.device)
+    check(lib().cfv_dots_noalloc(int(n), _ptr(V), int(k), _ptr(w), _ptr(o), _stream(stream)))
+    return o
 
 
 class Grid:

@@ -28,6 +28,8 @@ hipError_t launch_prim_delta_norms(int64_t nc, double gamma, const double* a, co
 int monitor_partials();
 hipError_t launch_norms(int64_t nc, const double* a, const double* b, double* out9, double* part, hipStream_t s);
 hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, double* out, double* part, hipStream_t s);
+hipError_t launch_dots_noalloc(int64_t n, const double* V, int k, const double* w, double* out, hipStream_t s);
+int dots_noalloc_max_vectors();
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
                       double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t);
@@ -521,6 +523,16 @@ cfv_status cfv_dots(cfv_ctx* c, const double* V, int32_t k, const double* w, dou
   if (!V || !w || !out) return fail(CFV_ERR_ARG, "null input or output");
   if (k < 1 || k > c->part_vectors) return fail(CFV_ERR_ARG, "k must be in 1..32");
   CFV_HIP(cfv::launch_dots(9 * c->grid->g.ncells, V, k, w, out, c->part, s));
+  return CFV_OK;
+}
+
+cfv_status cfv_dots_noalloc(int64_t n, const double* V, int32_t k, const double* w, double* out, hipStream_t s) {
+  if (!V || !w || !out) return fail(CFV_ERR_ARG, "null input or output");
+  if (n < 0) return fail(CFV_ERR_ARG, "n must be non-negative");
+  if (k < 1 || k > cfv::dots_noalloc_max_vectors())
+    return fail(CFV_ERR_ARG, "k must be in 1.." + std::to_string(cfv::dots_noalloc_max_vectors()) +
+                                 " (the static partial-sum array holds that many vectors)");
+  CFV_HIP(cfv::launch_dots_noalloc(n, V, k, w, out, s));
   return CFV_OK;
 }
 

@@ -7,6 +7,7 @@
 // partials in order.  No atomics, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <mutex>
 
 namespace cfv {
 
@@ -275,6 +276,47 @@ hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, doubl
   hipLaunchKernelGGL(dot_partials, dim3(kRGrid), dim3(kRBlock), 0, s, n, V, k, w, part);
   hipLaunchKernelGGL(fold_partials, dim3(k), dim3(kRBlock), 0, s, part, k, out, 0);
   return hipGetLastError();
+}
+
+// ------------------------------------------------ dots without allocation
+// The partial sums of the allocation-free dot products live in this
+// file-scope device array (each device holds its own copy until the process
+// ends).  Host code never uses the array's name as an address: its device
+// address is taken once per device, with that device current, and the
+// kernels get that pointer.  Calls on one device share the array, so calls
+// that overlap on one device race; every partial a call reads is written by
+// the same call first (nothing needs clearing).
+constexpr int kNoAllocMaxVectors = 32;
+__device__ __align__(256) double scratch[kNoAllocMaxVectors * kRGrid];
+
+int dots_noalloc_max_vectors() { return kNoAllocMaxVectors; }
+
+static hipError_t scratch_on_current_device(double** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+// the kernels of launch_dots with the partials in the device's static array
+// (the caller has checked 1 <= k <= kNoAllocMaxVectors)
+hipError_t launch_dots_noalloc(int64_t n, const double* V, int k, const double* w, double* out, hipStream_t s) {
+  double* part = nullptr;
+  const hipError_t e = scratch_on_current_device(&part);
+  if (e != hipSuccess) return e;
+  return launch_dots(n, V, k, w, out, part, s);
 }
 
 hipError_t launch_axpy_dot(int64_t n, const double* coef, const double* x, double* w, const double* y, double* out,
