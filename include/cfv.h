@@ -172,10 +172,12 @@ cfv_status cfv_vjp(cfv_ctx* ctx, const double* U, const double* w, double* gU, d
 cfv_status cfv_local_dt(cfv_ctx* ctx, const double* U, double cfl, double* diag, hipStream_t s);
 
 /* Non-physical state check (the face-state positivity condition of the
- * reconstruction: no fix-up is applied).  The residual, JVP and VJP kernels
- * OR bit 0 into a per-context device word whenever a reconstructed face state
- * or a ghost state has density or pressure that is not positive (NaN
- * included).  This call synchronises s, returns the word in *flags (host,
+ * reconstruction: no fix-up is applied, the computation goes on and the
+ * condition is reported).  The residual, JVP and VJP kernels OR bit 0 into a
+ * per-context device word whenever a reconstructed face state or a ghost
+ * state has density or pressure that is not positive (NaN included); the
+ * word accumulates over calls (also inside cfv_be_step and cfv_steady) until
+ * read.  This call synchronises s, returns the word in *flags (host,
  * nullable) and clears it; it returns CFV_ERR_NONPHYSICAL when bit 0 was
  * set, CFV_OK otherwise.  The flag does not change any output. */
 cfv_status cfv_status_flags(cfv_ctx* ctx, int32_t* flags, hipStream_t s);
@@ -249,7 +251,8 @@ cfv_status cfv_solve(cfv_ctx* ctx, const double* U, const double* diag, const do
  * cfv_local_dt at the given cfl, solved by cfv_solve.  U, U_new: device
  * [9][ncells]; U_new must not alias U.  Synchronises s (through cfv_solve).
  * Returns CFV_ERR_NONPHYSICAL, with U_new undefined, when the residual of U
- * meets a non-positive or NaN face density or pressure or is not finite. */
+ * or a Krylov scalar is not finite (cfv_solve); non-positive face states
+ * only set the context's flag word (cfv_status_flags). */
 cfv_status cfv_be_step(cfv_ctx* ctx, const double* U, double cfl, int32_t m, int32_t max_restarts, double rtol,
                        double* U_new, double* hist, int32_t hist_len, int32_t* iters, double* final_rel,
                        hipStream_t s);
@@ -282,11 +285,13 @@ typedef struct {
  * of every step, cfl_hist (host, nullable, max_iters) the CFL used, iters the
  * number of steps taken.  The stream is synchronised once per step for the
  * monitor (and once per GMRES iteration inside the solve).  A second state
- * buffer is owned by the context (allocated on first use).  If a step meets
- * a non-physical face state (cfv_be_step returns CFV_ERR_NONPHYSICAL; its
- * monitors are recorded as NaN) or produces a non-finite monitor value, the
+ * buffer is owned by the context (allocated on first use).  If a step's
+ * solve is not finite (cfv_be_step returns CFV_ERR_NONPHYSICAL; its monitors
+ * are recorded as NaN) or a step produces a non-finite monitor value, the
  * march stops, U keeps the state before that step, the step is counted in
- * iters and recorded in hist, and CFV_ERR_NONPHYSICAL is returned. */
+ * iters and recorded in hist, and CFV_ERR_NONPHYSICAL is returned.
+ * Non-positive face states met on the way are left in the context's flag
+ * word (cfv_status_flags). */
 cfv_status cfv_steady(cfv_ctx* ctx, double* U, const cfv_steady_cfg* cfg, double* hist, double* cfl_hist,
                       int32_t* iters, hipStream_t s);
 
@@ -365,11 +370,12 @@ cfv_status cfv_ensemble_residual_jvp(cfv_ensemble* e, const double* const* U, co
  * only (the queue counters are cleared by a kernel, not a memset). */
 cfv_status cfv_ensemble_graph_capture(cfv_ensemble* e, hipStream_t s);
 cfv_status cfv_ensemble_graph_launch(cfv_ensemble* e, hipStream_t s);
-/* Per-instance non-physical flags of the ensemble's runs (as
- * cfv_status_flags; an ensemble keeps its own words, separate from its
- * contexts'): synchronises s, writes n words to flags (host, nullable),
- * clears them, and returns CFV_ERR_NONPHYSICAL when any instance met a
- * non-physical face state. */
+/* Per-instance status words of the ensemble's runs (an ensemble keeps its
+ * own, separate from its contexts'): bit 0 as cfv_status_flags (a
+ * non-positive or NaN face density or pressure), bit 1 a backward-Euler step
+ * whose residual norm was not finite.  Synchronises s, writes n words to
+ * flags (host, nullable), clears them, and returns CFV_ERR_NONPHYSICAL when
+ * any instance has a bit set. */
 cfv_status cfv_ensemble_status_flags(cfv_ensemble* e, int32_t* flags, hipStream_t s);
 /* Per-kernel event timing of eager runs, as cfv_timing_enable / _read. */
 cfv_status cfv_ensemble_timing_enable(cfv_ensemble* e, int32_t on);
@@ -389,10 +395,12 @@ cfv_status cfv_ensemble_timing_read(cfv_ensemble* e, int32_t max, char* names, d
  * instance, the step's output) are 9 ncells each and must not alias.
  * hist (host, nullable, n x max_iters x 9) receives the log10 monitors, NaN
  * after an instance stopped; steps (host, nullable, n) the steps each
- * instance took; iters the lockstep steps run.  An instance whose step meets
- * a non-physical face state (its flag word, cfv_ensemble_status_flags) or
- * gives a non-finite monitor keeps its previous state and stops; the call
- * then returns CFV_ERR_NONPHYSICAL after the others finish.  The ensemble's
+ * instance took; iters the lockstep steps run.  An instance whose step has a
+ * non-finite residual norm (bit 1 of its flag word, cfv_ensemble_status_flags)
+ * or gives a non-finite monitor keeps its previous state and stops; the call
+ * then returns CFV_ERR_NONPHYSICAL after the others finish.  The flag words
+ * are cleared when the march starts; bit 0 (non-positive face states) is left
+ * for the caller.  The ensemble's
  * binding is replaced by the step binding. */
 cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const* U_work, const cfv_steady_cfg* cfg,
                                double* hist, int32_t* steps, int32_t* iters, hipStream_t s);

@@ -691,13 +691,7 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   const int64_t n = 9 * c->grid->g.ncells;
   // U_new holds the right-hand side -R(U) during the solve
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
-  CFV_HIP(hipMemsetAsync(c->dflag, 0, sizeof(unsigned), s));  // flags of earlier calls are not this step's
   CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
-  {
-    unsigned h = 0;
-    if (cfv_status st = take_flags(c->dflag, &h, s)) return st;
-    if (h & 1u) return fail(CFV_ERR_NONPHYSICAL, "the state has a face with non-positive or NaN density or pressure");
-  }
   CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
   if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
@@ -1185,6 +1179,7 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
     v.sm = p;
     p += Y.size;
     v.nc = nc;
+    v.flag = e->dflags + q;
     cfv::DevGrid d = c->dev();
     d.flag = e->dflags + q;
     args[q] = cfv::MarchArgs{d, U[q], nullptr, nullptr, c->W, nullptr, U_new[q], nullptr};
@@ -1250,11 +1245,11 @@ cfv_status cfv_ensemble_status_flags(cfv_ensemble* e, int32_t* flags, hipStream_
   int first = -1;
   for (size_t q = 0; q < n; ++q) {
     if (flags) flags[q] = int32_t(h[q]);
-    if ((h[q] & 1u) && first < 0) first = int(q);
+    if (h[q] && first < 0) first = int(q);
   }
   if (first >= 0)
     return fail(CFV_ERR_NONPHYSICAL, "instance " + std::to_string(first) +
-                                         " met a face with non-positive or NaN density or pressure");
+                                         " met a non-positive or NaN face state or a non-finite step");
   return CFV_OK;
 }
 
@@ -1299,13 +1294,12 @@ cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const*
       hipError_t he = hipMemcpyAsync(mon.data(), e->mon, 9 * n * sizeof(double), hipMemcpyDeviceToHost, s);
       if (he == hipSuccess) he = hipMemcpyAsync(flg.data(), e->dflags, n * sizeof(unsigned), hipMemcpyDeviceToHost, s);
       if (he == hipSuccess) he = hipStreamSynchronize(s);
-      if (he == hipSuccess) he = hipMemsetAsync(e->dflags, 0, n * sizeof(unsigned), s);
       if (he != hipSuccess) out = hip_fail(he, "monitor read-back");
     }
     if (out != CFV_OK) break;
     for (size_t q = 0; q < n; ++q) {
       if (!active[q]) continue;
-      bool finite = !(flg[q] & 1u);  // a non-physical face state makes the step's result meaningless
+      bool finite = !(flg[q] & 2u);  // the step's residual norm was not finite
       for (int v = 0; v < 9; ++v) {
         const double x = std::log10(mon[9 * q + v]);
         if (std::isnan(x) || (std::isinf(x) && x > 0.0)) finite = false;

@@ -17,6 +17,7 @@ struct StepVec {
   const double* diag;  // V/dt, nc
   double* sm;          // small per-instance scalars (StepLayout)
   int64_t nc;
+  unsigned* flag;      // the instance's status word: bit 1 set when the step's residual norm is not finite
 };
 
 // offsets into an instance's scalars for GMRES(m)

@@ -92,6 +92,9 @@ __global__ void step_init_kernel(const StepVec* __restrict__ sv, int n, int m) {
   sm[L.g] = sm[L.beta];
   sm[L.kdone] = 0.0;
   sm[L.stop] = sm[L.beta] > 0.0 ? 0.0 : 1.0;
+  // a non-finite residual: no step is taken (the solve stops at once) and
+  // the instance's status word says why
+  if (!(::fabs(sm[L.beta]) <= 1.7976931348623157e308)) atomicOr(sv[q].flag, 2u);
 }
 
 // dst = src / sm[slot] (zero when the scalar is zero); src: Unew (j < 0) or w

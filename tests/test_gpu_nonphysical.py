@@ -7,10 +7,13 @@ shell has its energy lowered until its pressure is negative (a host-forced
 condition: every kernel still exits normally), and:
   * the residual, the JVP and the VJP set the flag, a normal state leaves it
     clear, and the flag changes no output;
-  * cfv_be_step and cfv_steady return status 4 (the march keeps the state
-    before the failing step), and so does cfv_solve on a NaN right-hand side;
-  * in a batched march the failing instance stops with its state unchanged
-    while the others march on, and the call returns status 4."""
+  * a backward-Euler step goes on through such a state (no fix-up) and
+    leaves the flag set; a NaN state makes cfv_be_step and cfv_steady return
+    status 4 (the march keeps the state before the failing step), and so
+    does cfv_solve on a NaN right-hand side;
+  * in a batched march an instance with a NaN stops with its state
+    unchanged while the others march on, its status word says so, and the
+    call returns status 4."""
 import numpy as np
 import pytest
 import torch
@@ -68,23 +71,39 @@ def test_flag_clear_on_a_normal_state_and_set_by_every_operator():
     assert ctx.status_flags() == 0
 
 
-def test_be_step_and_steady_return_status_4():
+def nan_state(U, cell):
+    """A NaN in one cell's energy (a host-forced corrupt state)."""
+    U = U.clone()
+    U[7, cell] = float("nan")
+    return U
+
+
+def test_be_step_reports_and_fails_only_on_non_finite_solves():
     from paper_2209_04481_amd import CfvNonPhysical
-    print("case: be_step / steady / solve on a forced negative pressure, 6x4x4x6", flush=True)
+    print("case: be_step / steady / solve on forced states, 6x4x4x6", flush=True)
     inst, ctx = make()
     U = torch.from_numpy(inst.U)
+    # a negative pressure: the step goes on (no fix-up) and the flag reports it
     bad = negative_pressure(U, 2 * 16 + 7).cuda()
+    assert ctx.status_flags() == 0
+    Un, _ = ctx.be_step(bad, cfl=10.0, m=5)
+    assert bool(torch.isfinite(Un).all())
+    assert ctx.status_flags() & 1
+    # a NaN: the Krylov solve refuses the non-finite residual
+    nan = nan_state(U, 2 * 16 + 7).cuda()
     with pytest.raises(CfvNonPhysical):
-        ctx.be_step(bad, cfl=10.0, m=5)
-    before = bad.clone()
+        ctx.be_step(nan, cfl=10.0, m=5)
+    before = nan.clone()
     with pytest.raises(CfvNonPhysical) as ei:
-        ctx.steady(bad, 4, cfl0=2.0, cfl_max=8.0, every=2, m=5)
+        ctx.steady(nan, 4, cfl0=2.0, cfl_max=8.0, every=2, m=5)
     assert len(ei.value.cfls) == 1 and np.isnan(ei.value.hist).all()
-    assert torch.equal(bad, before)                     # the state before the failing step
+    assert torch.equal(torch.isnan(nan), torch.isnan(before))   # the state before the failing step
+    assert torch.equal(nan[~torch.isnan(nan)], before[~torch.isnan(before)])
+    ctx.status_flags()
     # a normal state steps without error and leaves the flag clear
     ctx.be_step(U.cuda(), cfl=10.0, m=5)
     assert ctx.status_flags() == 0
-    # a NaN right-hand side: the Krylov solve refuses it
+    # a NaN right-hand side
     rhs = torch.zeros(9, inst.ncells, dtype=torch.float64, device="cuda")
     rhs[0, 0] = float("nan")
     diag = torch.ones(inst.ncells, dtype=torch.float64, device="cuda")
@@ -94,26 +113,33 @@ def test_be_step_and_steady_return_status_4():
 
 def test_ensemble_march_stops_the_failing_instance_only():
     from paper_2209_04481_amd import CfvNonPhysical, Ensemble
-    print("case: batched march of 3 instances, the second with a forced negative pressure", flush=True)
+    print("case: batched runs of 3 instances, the second with a forced negative pressure, then with a NaN",
+          flush=True)
     insts, ctxs = [], []
     for q in range(3):
         inst, ctx = make(seed=20 + q, N=4 + q, Nr=5)
         insts.append(inst)
         ctxs.append(ctx)
     U = [torch.from_numpy(i.U).cuda() for i in insts]
-    U[1] = negative_pressure(U[1].cpu(), 11).cuda()
+    ens = Ensemble(ctxs)
+    # residual + JVP of the ensemble: only the instance with the negative pressure is flagged
+    Ub = list(U)
+    Ub[1] = negative_pressure(U[1].cpu(), 11).cuda()
+    v = [torch.ones_like(u) for u in U]
+    ens.residual_jvp(Ub, v)
+    flags = ens.status_flags()
+    assert list(flags & 1) == [0, 1, 0] and not (flags & 2).any()
+    assert list(ens.status_flags()) == [0, 0, 0]
+    # the batched march: the instance with a NaN stops at its first step, the others march on
+    U[1] = nan_state(U[1].cpu(), 11).cuda()
     U1 = U[1].clone()
     U0 = U[0].clone()
-    ens = Ensemble(ctxs)
-    # residual + JVP of the ensemble: only instance 1 is flagged
-    v = [torch.ones_like(u) for u in U]
-    ens.residual_jvp(U, v)
-    flags = ens.status_flags()
-    assert list(flags & 1) == [0, 1, 0]
-    assert list(ens.status_flags()) == [0, 0, 0]
     with pytest.raises(CfvNonPhysical) as ei:
         ens.steady(U, 3, cfl0=2.0, cfl_max=8.0, every=2, m=5)
     steps = ei.value.cfls
     assert steps[1] == 1 and steps[0] == 3 and steps[2] == 3
-    assert torch.equal(U[1], U1)                        # the failing instance keeps its state
-    assert not torch.equal(U[0], U0)                    # the others marched
+    assert torch.equal(torch.isnan(U[1]), torch.isnan(U1))
+    assert torch.equal(U[1][~torch.isnan(U1)], U1[~torch.isnan(U1)])   # the failing instance keeps its state
+    assert not torch.equal(U[0], U0)                                     # the others marched
+    flags = ens.status_flags()
+    assert flags[1] & 2 and not (flags[0] & 2) and not (flags[2] & 2)
