@@ -39,7 +39,7 @@ FP64_PEAK_TFLOPS = 78.6
 # algorithmic HBM bytes per cell and operation (FP64 SoA, 9 variables)
 ALG_BYTES = {"residual": 144, "jvp": 216, "vjp": 216}
 OP_KERNELS = {
-    "residual": ("grad_march", "flux_march"),
+    "residual": ("fused_march",),
     "jvp": ("grad_march_jvp", "flux_march_jvp"),
     "vjp": ("grad_march_fwd", "adjoint", "adjoint_ghosts", "adjoint_gather"),
 }

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcfv.so")
-SOURCES = ["residual.hip", "march.hip", "vjp.hip", "reduce.hip", "ensemble_step.hip", "efield.hip", "monitor.hip", "capi.cpp"]
+SOURCES = ["residual.hip", "march.hip", "fused.hip", "vjp.hip", "reduce.hip", "ensemble_step.hip", "efield.hip", "monitor.hip", "capi.cpp"]
 ARCH = "gfx950"
 
 

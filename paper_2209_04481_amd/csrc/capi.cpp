@@ -13,9 +13,11 @@
 #include <string>
 #include <vector>
 
+#include "cfv_fused.hpp"
 #include "cfv_kernels.hpp"
 #include "cfv_march.hpp"
 #include "cfv_step.hpp"
+#include "cfv_tables.hpp"
 
 namespace cfv {
 int reduce_partials_per_vector();
@@ -31,6 +33,7 @@ hipError_t launch_dots(int64_t n, const double* V, int k, const double* w, doubl
 hipError_t launch_dots_noalloc(int64_t n, const double* V, int k, const double* w, double* out, hipStream_t s);
 int dots_noalloc_max_vectors();
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t launch_fused_ensemble(const EnsembleLaunch& e, hipStream_t s, KernelTimer* t);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
                       double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
@@ -45,21 +48,7 @@ hipError_t launch_ratio_max(int64_t n, int nvar, const double* x, const double* 
                             double* part, hipStream_t s);
 }  // namespace cfv
 
-struct cfv_grid {
-  cfv::Shape g;
-  std::vector<double> r;   // Nr + 1
-  std::vector<double> D;   // 6 (N+1)^2 3 unit corner directions
-  std::vector<double> cg;  // CG_NCOMP x 6N^2 column geometry
-  std::vector<int32_t> cn; // 8 x 6N^2 angular neighbours and face ownership
-  cfv::GeomRef host_ref() const {
-    cfv::GeomRef G;
-    G.cg = cg.data();
-    G.cn = cn.data();
-    G.r = r.data();
-    G.ncol = g.nb;
-    return G;
-  }
-};
+struct cfv_grid : cfv::GridTables {};
 
 // Records an event pair around every kernel launch while enabled.
 struct EventTimer : cfv::KernelTimer {
@@ -135,6 +124,7 @@ struct cfv_ctx {
   double* st_u = nullptr;     // 9 ncells: the other state of the march
   double* st_m = nullptr;     // 9 device scalars: the monitor
   unsigned* dflag = nullptr;  // non-physical state word set by the kernels
+  int32_t* dftab = nullptr;   // per-tile stencil tables of the fused march
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -146,6 +136,7 @@ struct cfv_ctx {
     d.br = dbr;
     d.bth = dbth;
     d.flag = dflag;
+    d.ftab = dftab;
     return d;
   }
 };
@@ -168,8 +159,6 @@ cfv_status hip_fail(hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(e_, #call);        \
   } while (0)
 
-const double kPi = 3.14159265358979323846;
-
 cfv_status check_ctx(const cfv_ctx* c) {
   if (!c || !c->grid) return fail(CFV_ERR_ARG, "null context");
   return CFV_OK;
@@ -183,64 +172,6 @@ cfv_status dmalloc(T** p, size_t n) {
   return CFV_OK;
 }
 }  // namespace
-
-// Per-column geometry from the cell vertices at unit radii (see cfv_topo.hpp).
-static void build_column_tables(cfv_grid& G) {
-  using cfv::V3;
-  const cfv::Shape& s = G.g;
-  const int N = s.N, n1 = N + 1;
-  const int64_t ncol = s.nb;
-  G.cg.assign(size_t(cfv::CG_NCOMP) * ncol, 0.0);
-  G.cn.assign(size_t(8) * ncol, 0);
-  auto D = [&](int p, int jj, int ii) {
-    const double* d = &G.D[((size_t(p) * n1 + jj) * n1 + ii) * 3];
-    return cfv::mk(d[0], d[1], d[2]);
-  };
-  auto put = [&](int comp, int64_t col, V3 v) {
-    G.cg[comp * ncol + col] = v.x;
-    G.cg[(comp + 1) * ncol + col] = v.y;
-    G.cg[(comp + 2) * ncol + col] = v.z;
-  };
-  // vertex-formula area and centroid of local face lf of column (p,j,i) with
-  // radii (ra, rb) for the layers dk = 0, 1
-  auto face_at = [&](int p, int j, int i, int lf, double ra, double rb, V3& S, V3& xf) {
-    int off[4][3];
-    cfv::face_vertex_offsets(lf, off);
-    V3 v[4];
-    for (int a = 0; a < 4; ++a) v[a] = (off[a][0] ? rb : ra) * D(p, j + off[a][1], i + off[a][2]);
-    S = 0.5 * cfv::cross3(v[2] - v[0], v[3] - v[1]);
-    xf = 0.25 * (((v[0] + v[1]) + v[2]) + v[3]);
-  };
-  for (int p = 0; p < 6; ++p)
-    for (int j = 0; j < N; ++j)
-      for (int i = 0; i < N; ++i) {
-        const int64_t col = cfv::column_of(s, p, j, i);
-        put(cfv::CG_CSUM, col, ((D(p, j, i) + D(p, j, i + 1)) + D(p, j + 1, i)) + D(p, j + 1, i + 1));
-        V3 sr, xr;
-        face_at(p, j, i, 1, 1.0, 1.0, sr, xr);
-        put(cfv::CG_SR, col, sr);
-        put(cfv::CG_XR, col, xr);
-        G.cg[cfv::CG_OMEGA * ncol + col] = cfv::dot3(xr, sr);
-        for (int q = 0; q < 4; ++q) {
-          const int lf = 2 + q;
-          cfv::Nbr nb = cfv::neighbour(s, p, 0, j, i, lf);
-          const int64_t ncolv = cfv::column_of(s, nb.p, nb.j, nb.i);
-          const bool own = ncolv > col;
-          V3 a, b, dummy;
-          if (own) {
-            face_at(p, j, i, lf, 0.0, 1.0, a, dummy);
-            face_at(p, j, i, lf, 1.0, 1.0, dummy, b);
-          } else {
-            face_at(nb.p, nb.j, nb.i, nb.back, 0.0, 1.0, a, dummy);
-            face_at(nb.p, nb.j, nb.i, nb.back, 1.0, 1.0, dummy, b);
-          }
-          put(cfv::CG_ANG + 6 * q, col, 2.0 * a);
-          put(cfv::CG_ANG + 6 * q + 3, col, 2.0 * b);
-          G.cn[q * ncol + col] = int32_t(ncolv);
-          G.cn[(4 + q) * ncol + col] = nb.back | (own ? 256 : 0);
-        }
-      }
-}
 
 extern "C" {
 
@@ -258,35 +189,10 @@ cfv_status cfv_grid_create(int32_t N, int32_t Nr, const double* r_nodes, cfv_gri
       return fail(CFV_ERR_ARG, "r_nodes must be positive and strictly increasing");
   cfv_grid* g = new (std::nothrow) cfv_grid;
   if (!g) return fail(CFV_ERR_ALLOC, "host allocation");
-  g->g.N = N;
-  g->g.Nr = Nr;
-  g->g.nb = 6LL * N * N;
-  g->g.ncells = g->g.nb * Nr;
-  g->r.assign(r_nodes, r_nodes + Nr + 1);
-  const int n1 = N + 1;
-  g->D.resize(size_t(6) * n1 * n1 * 3);
-  std::vector<double> t(n1);
-  for (int q = 0; q <= N; ++q) t[q] = std::tan(-kPi / 4 + q * (kPi / 2) / N);
-  for (int p = 0; p < 6; ++p)
-    for (int jj = 0; jj <= N; ++jj)
-      for (int ii = 0; ii <= N; ++ii) {
-        const double a = t[ii], b = t[jj];
-        double x, y, z;
-        switch (p) {
-          case 0: x = 1; y = a; z = b; break;
-          case 1: x = -a; y = 1; z = b; break;
-          case 2: x = -1; y = -a; z = b; break;
-          case 3: x = a; y = -1; z = b; break;
-          case 4: x = -b; y = a; z = 1; break;
-          default: x = b; y = a; z = -1; break;
-        }
-        const double nrm = std::sqrt(x * x + y * y + z * z);
-        double* d = &g->D[((size_t(p) * n1 + jj) * n1 + ii) * 3];
-        d[0] = x / nrm;
-        d[1] = y / nrm;
-        d[2] = z / nrm;
-      }
-  build_column_tables(*g);
+  if (!cfv::build_grid_tables(N, Nr, r_nodes, *g)) {
+    delete g;
+    return fail(CFV_ERR_ARG, "a tile needs more outer stencil slots than the fused march holds");
+  }
   *out = g;
   return CFV_OK;
 }
@@ -386,7 +292,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
       (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
       (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector())) ||
-      (st = dmalloc(&c->slot, 1)) || (st = dmalloc(&c->dflag, 1))) {
+      (st = dmalloc(&c->slot, 1)) || (st = dmalloc(&c->dflag, 1)) || (st = dmalloc(&c->dftab, g->ftab.size()))) {
     cfv_ctx_destroy(c);
     return st;
   }
@@ -396,6 +302,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (e == hipSuccess) e = hipMemset(c->dbr, 0, size_t(g->g.nb) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->dbth, 0, size_t(g->g.nb) * sizeof(double));
   if (e == hipSuccess) e = hipMemset(c->dflag, 0, sizeof(unsigned));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->dftab, g->ftab.data(), g->ftab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     cfv_ctx_destroy(c);
     return hip_fail(e, "uploading grid tables");
@@ -412,6 +320,7 @@ void cfv_ctx_destroy(cfv_ctx* c) {
   if (c->dcn) (void)hipFree(c->dcn);
   if (c->slot) (void)hipFree(c->slot);
   if (c->dflag) (void)hipFree(c->dflag);
+  if (c->dftab) (void)hipFree(c->dftab);
   double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
                   c->dir_u, c->dir_g, c->dir_b, c->dir_s, c->st_u, c->st_m};
   for (double* b : kb)
@@ -945,6 +854,12 @@ struct cfv_ensemble {
   cfv::StepLaunch step;
   double* mon = nullptr;                 // 9 n device scalars: monitors of the batched march
   unsigned* dflags = nullptr;            // n non-physical state words, one per instance
+  // the fused residual march's items (its own tiles and chunks of fkc layers)
+  int fkc = 16;
+  std::vector<int64_t> foff;             // n + 1 prefix sums of fused items
+  int64_t ftotal = 0;
+  int64_t* dfoff = nullptr;
+  int64_t* dfperm = nullptr;
 };
 
 namespace {
@@ -964,8 +879,29 @@ cfv_status check_tuning(const cfv_tuning* t) {
 }
 
 // processing order of the items: instance order, or the items of the largest
-// tiles first (cost ~ active columns x layers of the item), stable
+// tiles first (cost ~ active columns x layers of the item), stable; the
+// same for the fused march's items
+cfv_status upload_fused_perm(cfv_ensemble* e) {
+  std::vector<int64_t> perm(size_t(e->ftotal));
+  for (int64_t w = 0; w < e->ftotal; ++w) perm[size_t(w)] = w;
+  if (e->tune.order == 1) {
+    std::vector<int32_t> cost(size_t(e->ftotal));
+    for (size_t q = 0; q < e->ctx.size(); ++q) {
+      const cfv::Shape& g = e->ctx[q]->grid->g;
+      for (int64_t l = 0; l < e->foff[q + 1] - e->foff[q]; ++l) {
+        cfv::FTile tm;
+        cfv::fused_tile_of(g, e->fkc, l, tm);
+        cost[size_t(e->foff[q] + l)] = (tm.wi + 2) * (tm.wj + 2) * (tm.k1 - tm.k0 + 2);
+      }
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
+  }
+  CFV_HIP(hipMemcpy(e->dfperm, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  return CFV_OK;
+}
+
 cfv_status upload_perm(cfv_ensemble* e) {
+  if (cfv_status st = upload_fused_perm(e)) return st;
   std::vector<int64_t> perm(size_t(e->total));
   for (int64_t w = 0; w < e->total; ++w) perm[size_t(w)] = w;
   if (e->tune.order == 1) {
@@ -985,9 +921,9 @@ cfv_status upload_perm(cfv_ensemble* e) {
   return CFV_OK;
 }
 
-unsigned ensemble_blocks(const cfv_ensemble* e) {
+unsigned ensemble_blocks(const cfv_ensemble* e, int64_t total) {
   int64_t b = int64_t(e->tune.blocks_per_cu) * e->num_cu;
-  const int64_t cap = (e->total + 7) / 8 * 8;
+  const int64_t cap = (total + 7) / 8 * 8;
   if (b > cap) b = cap;
   b = b / 8 * 8;
   if (b < 8) b = 8;
@@ -1001,16 +937,22 @@ cfv_status ensemble_launch(cfv_ensemble* e, hipStream_t s, bool timed) {
   const int n = int(e->ctx.size());
   if (e->mode == 1) {
     cfv::StepLaunch& L = e->step;
-    L.res = cfv::EnsembleLaunch{e->step_args, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue,
-                                ensemble_blocks(e)};
+    L.res = cfv::EnsembleLaunch{e->step_args, e->dfoff, e->dfperm, e->dcnt, n, e->ftotal, e->tune.queue,
+                                ensemble_blocks(e, e->ftotal), e->fkc};
     for (int j = 0; j < L.m; ++j) {
-      L.jvp[size_t(j)] = L.res;
-      L.jvp[size_t(j)].args = e->step_args + size_t(1 + j) * n;
+      L.jvp[size_t(j)] = cfv::EnsembleLaunch{e->step_args + size_t(1 + j) * n, e->doff, e->dperm, e->dcnt, n, e->total,
+                                             e->tune.queue, ensemble_blocks(e, e->total)};
     }
     CFV_HIP(cfv::launch_ensemble_step(L, s, t));
     return CFV_OK;
   }
-  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue, ensemble_blocks(e)};
+  if (!e->dual) {  // the residual: the fused march over its own item list
+    const cfv::EnsembleLaunch Lf{e->dargs, e->dfoff, e->dfperm, e->dcnt, n, e->ftotal, e->tune.queue,
+                                 ensemble_blocks(e, e->ftotal), e->fkc};
+    CFV_HIP(cfv::launch_fused_ensemble(Lf, s, t));
+    return CFV_OK;
+  }
+  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue, ensemble_blocks(e, e->total)};
   CFV_HIP(cfv::launch_march_ensemble(L, e->dual, s, t));
   return CFV_OK;
 }
@@ -1040,15 +982,21 @@ cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning
   e->off.assign(size_t(n) + 1, 0);
   for (int q = 0; q < n; ++q) e->off[size_t(q) + 1] = e->off[size_t(q)] + cfv::march_logical_blocks(ctxs[q]->grid->g);
   e->total = e->off[size_t(n)];
+  e->foff.assign(size_t(n) + 1, 0);
+  for (int q = 0; q < n; ++q) e->foff[size_t(q) + 1] = e->foff[size_t(q)] + cfv::fused_items(ctxs[q]->grid->g, e->fkc);
+  e->ftotal = e->foff[size_t(n)];
   cfv_status st;
   if ((st = dmalloc(&e->dargs, size_t(n))) || (st = dmalloc(&e->doff, size_t(n) + 1)) ||
       (st = dmalloc(&e->dperm, size_t(e->total))) || (st = dmalloc(&e->dcnt, 2)) ||
-      (st = dmalloc(&e->dflags, size_t(n)))) {
+      (st = dmalloc(&e->dflags, size_t(n))) || (st = dmalloc(&e->dfoff, size_t(n) + 1)) ||
+      (st = dmalloc(&e->dfperm, size_t(e->ftotal)))) {
     cfv_ensemble_destroy(e);
     return st;
   }
   he = hipMemcpy(e->doff, e->off.data(), e->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(e->dflags, 0, size_t(n) * sizeof(unsigned));
+  if (he == hipSuccess)
+    he = hipMemcpy(e->dfoff, e->foff.data(), e->foff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
   if (he != hipSuccess) {
     cfv_ensemble_destroy(e);
     return fail(CFV_ERR_HIP, hipGetErrorString(he));
@@ -1065,7 +1013,7 @@ void cfv_ensemble_destroy(cfv_ensemble* e) {
   if (!e) return;
   drop_graph(e);
   void* bufs[] = {e->dargs, e->doff, e->dperm, e->dcnt, e->step_args, e->step_sv, e->step_arena, e->step_part,
-                  e->mon, e->dflags};
+                  e->mon, e->dflags, e->dfoff, e->dfperm};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete e;
@@ -1082,7 +1030,7 @@ cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t) {
 cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks) {
   if (!e) return fail(CFV_ERR_ARG, "null ensemble");
   if (total) *total = e->total;
-  if (blocks) *blocks = int32_t(ensemble_blocks(e));
+  if (blocks) *blocks = int32_t(ensemble_blocks(e, e->total));
   return CFV_OK;
 }
 

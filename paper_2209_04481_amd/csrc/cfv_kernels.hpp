@@ -16,6 +16,7 @@ struct DevGrid {
   const double* br;  // inner-boundary B_r map, 6N^2, order (p, j, i)
   const double* bth = nullptr;  // inner-boundary B_theta map (large-E law), same order
   unsigned* flag = nullptr;     // non-physical state word (bit 0), nullable
+  const int32_t* ftab = nullptr;  // per-tile stencil tables of the fused march (cfv_fused.hpp)
 };
 
 // A face state is physical when its density and pressure are positive (a NaN
@@ -37,10 +38,12 @@ __host__ __device__ __forceinline__ void record_nonphysical(const DevGrid& d, bo
 // The first kernel argument read in place from the kernel-argument segment:
 // large descriptors (grid, parameters) are then loaded where they are used
 // instead of being preloaded whole into scalar registers, which spill.
+#if defined(__HIP__)
 template <class A>
 __device__ __forceinline__ const A& first_kernel_arg() {
   return *(const A*)__builtin_amdgcn_kernarg_segment_ptr();
 }
+#endif
 
 // load/store a scalar of type T from a value array and (for Dual) a tangent array
 __host__ __device__ __forceinline__ void ldT(const double* a, const double*, int64_t i, double& x) { x = gld(a, i); }

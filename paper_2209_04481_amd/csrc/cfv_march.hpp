@@ -599,6 +599,7 @@ struct EnsembleLaunch {
   int64_t total;
   int queue;
   unsigned blocks;
+  int kc = 16;  // layers per chunk of the fused residual march (its items)
 };
 hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t s, KernelTimer* t);
 

@@ -15,6 +15,8 @@
 
 namespace cfv {
 
+hipError_t launch_fused_ensemble(const EnsembleLaunch& e, hipStream_t s, KernelTimer* t);
+
 static constexpr int kSB = 256;  // threads per block
 
 __device__ __forceinline__ double block_sum_step(double x, double* sh) {
@@ -249,7 +251,7 @@ hipError_t launch_ensemble_step(const StepLaunch& L, hipStream_t s, KernelTimer*
   // residual of every instance into Unew, then -R, beta, V_0
   {
     TimedScope ts(t, "step_residual", s);
-    if (hipError_t e = launch_march_ensemble(L.res, false, s, nullptr)) return e;
+    if (hipError_t e = launch_fused_ensemble(L.res, s, nullptr)) return e;
   }
   for (int q = 0; q < L.n; ++q)
     if (hipError_t e = launch_local_dt(L.dev[q], L.Uh[q], L.cfl, L.diagh[q], L.Wh[q], s, nullptr)) return e;

@@ -140,48 +140,37 @@ __global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_e
   }
 }
 
+hipError_t launch_fused_ensemble(const EnsembleLaunch& e, hipStream_t s, KernelTimer* t);
+hipError_t launch_fused(const MarchArgs& a, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t);
+
+// dual: the JVP's two passes; otherwise the fused residual march, and e must
+// then describe its items (fused_items per instance, chunks of e.kc layers)
 hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t s, KernelTimer* t) {
   if (e.total <= 0) return hipSuccess;
+  if (!dual) return launch_fused_ensemble(e, s, t);
   if (e.queue) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, e.counters);
-  if (dual) {
-    {
-      TimedScope ts(t, "grad_march_ens_jvp", s);
-      hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
-    }
-    TimedScope ts(t, "flux_march_ens_jvp", s);
-    hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
-  } else {
-    {
-      TimedScope ts(t, "grad_march_ens", s);
-      hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
-    }
-    TimedScope ts(t, "flux_march_ens", s);
-    hipLaunchKernelGGL((march_ensemble_kernel<double, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  {
+    TimedScope ts(t, "grad_march_ens_jvp", s);
+    hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
   }
+  TimedScope ts(t, "flux_march_ens_jvp", s);
+  hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
   return hipGetLastError();
 }
 
 // One instance: the descriptor goes to the context's slot, then the same
 // persistent kernels run with one workgroup per item (no queue, no table).
 hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t) {
+  if (!dual) return launch_fused(a, slot, 16, s, t);  // the residual: one fused pass (fused.hip)
   hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
   const int64_t total = march_logical_blocks(a.d.g);
   EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
-  if (dual) {
-    {
-      TimedScope ts(t, "grad_march_jvp", s);
-      hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
-    }
-    TimedScope ts(t, "flux_march_jvp", s);
-    hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
-  } else {
-    {
-      TimedScope ts(t, "grad_march", s);
-      hipLaunchKernelGGL((march_ensemble_kernel<double, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
-    }
-    TimedScope ts(t, "flux_march", s);
-    hipLaunchKernelGGL((march_ensemble_kernel<double, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
+  {
+    TimedScope ts(t, "grad_march_jvp", s);
+    hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
   }
+  TimedScope ts(t, "flux_march_jvp", s);
+  hipLaunchKernelGGL((march_ensemble_kernel<Dual, true>), dim3(e.blocks), dim3(kNT), 0, s, e);
   return hipGetLastError();
 }
 

@@ -1,0 +1,146 @@
+"""The kernels' phase functions run on the CPU under AddressSanitizer and
+UndefinedBehaviorSanitizer (tests/host/cfv_host_harness.cpp), against the
+oracle.
+
+The harness emulates each workgroup (its lanes' states and its LDS, a barrier
+being the end of a loop over the lanes), so the residual of the fused march,
+the JVP of the two-pass dual march and the VJP's four passes run exactly the
+index arithmetic of the GPU kernels.  An access outside any array stops the
+run with a sanitizer report; LDS is filled with NaN at the start of every
+work item, so a read of an LDS value the item never wrote reaches the
+outputs.  Shapes: partial tiles (N not a multiple of 14 or 16), N = 2, one
+layer, chunk lengths from 1 to beyond Nr, odd N (polar-axis faces), both
+inner laws and two Table 2 outer laws.  Bar: 1e-12 per variable as the GPU
+parity tests."""
+import ctypes
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import coronal_inputs as ci
+from helpers import rel_err_per_var
+from oracle import mhd, solve
+from oracle.grid import Grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-12
+
+# (N, Nr, chunk layers, params)
+CASES = [
+    (5, 6, 4, {}),
+    (16, 5, 2, {}),
+    (17, 4, 3, {}),
+    (2, 2, 1, {}),
+    (3, 1, 16, {}),
+    (7, 3, 16, {"inner_mode": 1}),
+    (6, 4, 5, {"table2": 1}),
+    (4, 5, 2, {"table2": 9, "limiter": 0}),
+]
+
+
+def _sanitizer_runtime():
+    libs = []
+    for name in ("libasan.so", "libubsan.so"):
+        p = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True, text=True).stdout.strip()
+        if not os.path.isabs(p) or not os.path.exists(p):
+            return None
+        libs.append(p)
+    return ":".join(libs)
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    pre = _sanitizer_runtime()
+    if pre is None:
+        pytest.skip("no sanitizer runtime")
+    out = tmp_path_factory.mktemp("host") / "libcfv_host.so"
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2209_04481_amd", "csrc"),
+           os.path.join(HERE, "host", "cfv_host_harness.cpp"), "-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return str(out), pre
+
+
+RUNNER = r'''
+import ctypes, json, sys
+import numpy as np
+sys.path.insert(0, {root!r})
+from paper_2209_04481_amd.binding import CfvParams
+L = ctypes.CDLL({lib!r})
+P = ctypes.c_void_p
+d = np.load({inp!r})
+prm = json.loads(open({prm!r}).read())
+cp = CfvParams(prm["gamma"], prm["c_h"], prm["G"], prm["vr_star"], prm["rho_b"], prm["T_b"], prm["limiter"],
+               prm["inner_mode"], (ctypes.c_double * 8)(*prm["outer_exp"]), prm["outer_vr_mass"], prm["outer_psi_zero"])
+N, Nr, kc = int(d["N"]), int(d["Nr"]), int(d["kc"])
+ptr = lambda a: a.ctypes.data_as(P)
+r, U, br, bth, v, dbr, w = (np.ascontiguousarray(d[k]) for k in ("r", "U", "br", "bth", "v", "dbr", "w"))
+R = np.full_like(U, np.nan); Rj = np.full_like(U, np.nan); Jv = np.full_like(U, np.nan)
+gU = np.full_like(U, np.nan); gbr = np.full_like(br, np.nan)
+flag = ctypes.c_uint(0)
+bt = ptr(bth) if prm["inner_mode"] == 1 else None
+assert L.host_residual(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(R), ctypes.byref(flag)) == 0
+assert L.host_jvp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, ptr(v), ptr(dbr), ptr(Jv), ptr(Rj)) == 0
+assert L.host_vjp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, ptr(w), ptr(gU), ptr(gbr)) == 0
+np.savez({out!r}, R=R, Rj=Rj, Jv=Jv, gU=gU, gbr=gbr, flag=flag.value)
+'''
+
+
+@pytest.mark.parametrize("N,Nr,kc,kw", CASES)
+def test_host_emulation_matches_the_oracle(harness, tmp_path, N, Nr, kc, kw):
+    lib, pre = harness
+    inst = ci.make_instance(N, Nr, "log", lmax=3, seed=300 + 10 * N + Nr)
+    inst.U[8] = 1e-3 * np.random.default_rng(N + Nr).standard_normal(inst.ncells)   # psi != 0
+    kw = dict(kw)
+    case = kw.pop("table2", None)
+    if kw.get("inner_mode") == 1:
+        kw["inner_btheta"] = torch.tensor(ci.btheta_map(N))
+    op = mhd.Params.table2(case, **kw) if case else mhd.Params(**kw)
+    bth = ci.btheta_map(N) if op.inner_mode == 1 else np.zeros(6 * N * N)
+    v = ci.scaled_direction(inst.U, N)
+    dbr = ci.br_direction(6 * N * N, N)
+    w = np.random.default_rng(7 + N).standard_normal(inst.U.shape)
+    inp = tmp_path / "in.npz"
+    np.savez(inp, N=N, Nr=Nr, kc=kc, r=inst.r_nodes, U=inst.U, br=inst.br, bth=bth, v=v, dbr=dbr, w=w)
+    prm = tmp_path / "prm.json"
+    import json
+    prm.write_text(json.dumps({"gamma": op.gamma, "c_h": op.c_h, "G": op.G, "vr_star": op.vr_star, "rho_b": op.rho_b,
+                               "T_b": op.T_b, "limiter": int(op.limiter), "inner_mode": int(op.inner_mode),
+                               "outer_exp": [float(x) for x in op.outer_exp], "outer_vr_mass": int(op.outer_vr_mass),
+                               "outer_psi_zero": int(op.outer_psi_zero)}))
+    out = tmp_path / "out.npz"
+    script = tmp_path / "run.py"
+    script.write_text(RUNNER.format(root=ROOT, lib=lib, inp=str(inp), prm=str(prm), out=str(out)))
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-6000:])
+    res = np.load(out)
+    g = Grid(N, Nr, inst.r_nodes)
+    U, br = torch.tensor(inst.U), torch.tensor(inst.br)
+    Ro = mhd.residual(g, U, br, op)
+    Jo, _ = solve.jvp(g, U, br, op, torch.tensor(v), torch.tensor(dbr))
+    gUo, gbro = solve.vjp(g, U, br, op, torch.tensor(w))
+    for name, a, b in (("R (fused march)", res["R"], Ro), ("R (dual march)", res["Rj"], Ro), ("Jv", res["Jv"], Jo),
+                       ("gU", res["gU"], gUo), ("gbr", res["gbr"][None], gbro[None])):
+        err = float(rel_err_per_var(torch.tensor(a), b).max())
+        assert err <= TOL, f"{name}: {err:.2e}"
+    # the non-physical flag: set exactly when some face state of the oracle's
+    # reconstruction (either side, ghosts included) has rho <= 0 or p <= 0
+    st = mhd._Stencil(g, torch.arange(g.ncells))
+    fs = mhd.face_states(g, U, br, op, torch.arange(g.ncells), st)
+    sides = torch.cat([fs["PL"], fs["PR"]], 1)
+    expect = bool(((sides[..., 0] <= 0) | (sides[..., 7] <= 0)).any())
+    assert bool(int(res["flag"]) & 1) == expect
