@@ -319,10 +319,10 @@ cfv_status cfv_jvp_dir(cfv_ctx* ctx, const double* U, const double* v, const dou
 /* ------------------------------------------------------------ ensemble --
  * Many independent instances (different grids, B_r maps and states; the
  * magnetogram-driven ensembles the model is meant for) evaluated by one
- * persistent launch per pass.  The work items are (instance, 16x16 column
- * tile, chunk of 16 layers); every instance's items are the same ones its
- * single-instance launch runs, so each instance's outputs are bitwise those
- * of cfv_residual / cfv_jvp on its own context.  The contexts keep owning
+ * persistent launch per pass.  The work items are (instance, column tile,
+ * chunk of chunk_layers layers); each instance's outputs are bitwise those of
+ * cfv_residual / cfv_jvp on its own context (the outputs do not depend on the
+ * chunk length, see cfv_set_chunk_layers).  The contexts keep owning
  * their grid tables, B_r map and gradient workspaces, so one context may
  * appear in only one ensemble run at a time, and no two runs of ensembles
  * sharing a context may overlap. */
@@ -331,11 +331,13 @@ typedef struct {
                              contiguous eighth); 1: device work counter */
   int32_t blocks_per_cu;  /* persistent workgroups per compute unit, 1..16 */
   int32_t order;          /* 0: instance order; 1: largest items first */
+  int32_t chunk_layers;   /* radial layers per work item, 1..4096; 0: 16 */
 } cfv_tuning;
 /* ctxs: host array of n contexts on the current device (not owned). */
 cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning* t, cfv_ensemble** out);
 void cfv_ensemble_destroy(cfv_ensemble* e);
-/* Change the schedule (drops a captured graph). */
+/* Change the schedule (drops a captured graph; a new chunk length rebuilds
+ * the item lists, synchronously). */
 cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t);
 /* Number of work items and the workgroups a launch uses (host outputs). */
 cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks);
@@ -412,6 +414,15 @@ cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const*
  * total milliseconds and the launch count since the previous read, then
  * clears the record (n = number of names written). */
 cfv_status cfv_timing_enable(cfv_ctx* ctx, int32_t on);
+/* Work decomposition of the context's own launches: every march (the fused
+ * residual march, the dual JVP march, the VJP's gradient march) splits each
+ * column tile's Nr layers into chunks of kc layers (1..4096, default 16), one
+ * work item each.  A chunk re-reads the layers on either side of it, so
+ * longer chunks move fewer bytes, shorter ones give more work items on small
+ * grids.  Every output is bitwise the same for every kc: each face flux is
+ * evaluated once from the same states, and each cell sums its faces in a
+ * fixed order. */
+cfv_status cfv_set_chunk_layers(cfv_ctx* ctx, int32_t kc);
 cfv_status cfv_timing_read(cfv_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n);
 
 #ifdef __cplusplus

@@ -1,10 +1,15 @@
-"""Schedule autotuner for the ensemble launch.
+"""Work-item shape and schedule autotuner for the ensemble launch.
 
-Times every candidate schedule (static or queued item list, workgroups per
-compute unit, item order) on the ensemble's bound buffers with HIP events on
-the launch stream, keeps the fastest, and caches the choice in a JSON file
-keyed by the device name and the instance shapes.  The tile shape itself is
-fixed at compile time (16 x 16 columns, 16 layers per chunk).
+A work item is one column tile of one instance over a chunk of radial layers;
+the chunk length is the tile's depth, a runtime setting of the library
+(cfv_tuning.chunk_layers; the outputs do not depend on it).  The tuner times,
+on the ensemble's bound buffers with HIP events on the launch stream, every
+schedule (static or queued item list, workgroups per compute unit, item order)
+at the default depth, then every depth in CHUNKS with the fastest schedule,
+keeps the fastest pair, and caches the choice in a JSON file keyed by the
+device name, the operation, the instance shapes in their order and a hash of
+the loaded libcfv.so (a rebuilt library or a reordered ensemble is tuned
+afresh).
 """
 from __future__ import annotations
 
@@ -14,9 +19,10 @@ import os
 
 import torch
 
-from .binding import Ensemble, Tuning
+from .binding import LIB_PATH, Ensemble, Tuning
 
-CANDIDATES = [Tuning(q, b, o) for q in (0, 1) for b in (1, 2, 4) for o in (0, 1)]
+SCHEDULES = [Tuning(q, b, o) for q in (0, 1) for b in (1, 2, 4) for o in (0, 1)]
+CHUNKS = (4, 8, 12, 16, 24, 32, 64)
 
 
 def cache_path() -> str:
@@ -26,10 +32,24 @@ def cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2209_04481_amd", "ensemble_tuning.json")
 
 
+_LIB_HASH = None
+
+
+def library_hash() -> str:
+    global _LIB_HASH
+    if _LIB_HASH is None:
+        h = hashlib.sha1()
+        with open(LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _LIB_HASH = h.hexdigest()[:16]
+    return _LIB_HASH
+
+
 def cache_key(ens: Ensemble, dual: bool) -> str:
-    shapes = sorted((c.grid.N, c.grid.Nr) for c in ens.contexts)
+    shapes = [(c.grid.N, c.grid.Nr) for c in ens.contexts]
     h = hashlib.sha1(json.dumps(shapes).encode()).hexdigest()[:16]
-    return f"{torch.cuda.get_device_name()}|{'jvp' if dual else 'res'}|{len(shapes)}|{h}"
+    return f"{torch.cuda.get_device_name()}|{'jvp' if dual else 'res'}|{len(shapes)}|{h}|{library_hash()}"
 
 
 def _load(path):
@@ -55,7 +75,8 @@ def time_schedule(ens: Ensemble, tuning: Tuning, reps: int = 5, stream=None) -> 
 
 
 def autotune(ens: Ensemble, dual: bool = True, reps: int = 5, stream=None, use_cache: bool = True):
-    """Pick and set the fastest schedule; returns (tuning, {repr: ms})."""
+    """Pick and set the fastest schedule and chunk length; returns
+    (tuning, {repr: ms}) with every timed candidate."""
     path, key = cache_path(), cache_key(ens, dual)
     if use_cache:
         hit = _load(path).get(key)
@@ -63,8 +84,16 @@ def autotune(ens: Ensemble, dual: bool = True, reps: int = 5, stream=None, use_c
             t = Tuning(**hit["tuning"])
             ens.set_tuning(t)
             return t, hit.get("ms", {})
-    ms = {repr(t): time_schedule(ens, t, reps, stream) for t in CANDIDATES}
-    best = min(CANDIDATES, key=lambda t: ms[repr(t)])
+    ms = {}
+    stage1 = [Tuning(t.queue, t.blocks_per_cu, t.order, 0) for t in SCHEDULES]
+    for t in stage1:
+        ms[repr(t)] = time_schedule(ens, t, reps, stream)
+    best = min(stage1, key=lambda t: ms[repr(t)])
+    for kc in CHUNKS:
+        t = Tuning(best.queue, best.blocks_per_cu, best.order, kc)
+        ms[repr(t)] = time_schedule(ens, t, reps, stream)
+        if ms[repr(t)] < ms[repr(best)]:
+            best = t
     ens.set_tuning(best)
     if use_cache:
         data = _load(path)

@@ -26,7 +26,7 @@ class CfvParams(ctypes.Structure):
 
 
 class CfvTuning(ctypes.Structure):
-    _fields_ = [("queue", c_int32), ("blocks_per_cu", c_int32), ("order", c_int32)]
+    _fields_ = [("queue", c_int32), ("blocks_per_cu", c_int32), ("order", c_int32), ("chunk_layers", c_int32)]
 
 
 class CfvSteadyCfg(ctypes.Structure):
@@ -106,6 +106,7 @@ def lib():
         "cfv_ensemble_timing_enable": ([P, c_int32], c_int32),
         "cfv_ensemble_timing_read": ([P, c_int32, P, P, P, P], c_int32),
         "cfv_timing_enable": ([P, c_int32], c_int32),
+        "cfv_set_chunk_layers": ([P, c_int32], c_int32),
         "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
     for name, (args, res) in sig.items():
@@ -406,6 +407,10 @@ class Context:
     def timing_enable(self, on=True):
         check(lib().cfv_timing_enable(self._h, int(bool(on))))
 
+    def set_chunk_layers(self, kc: int):
+        """Layers per work item of this context's marches (outputs unchanged)."""
+        check(lib().cfv_set_chunk_layers(self._h, int(kc)))
+
     def timing_read(self, max_names=32):
         """{kernel name: (total ms, launches)} since the previous read."""
         return _timing_read(lib().cfv_timing_read, self._h, max_names)
@@ -416,19 +421,22 @@ class Context:
 
 
 class Tuning:
-    """Schedule of the ensemble launch (cfv_tuning)."""
+    """Schedule and work-item shape of the ensemble launch (cfv_tuning);
+    chunk_layers 0 is the library's default (16)."""
 
-    def __init__(self, queue: int = 1, blocks_per_cu: int = 2, order: int = 1):
+    def __init__(self, queue: int = 1, blocks_per_cu: int = 2, order: int = 1, chunk_layers: int = 0):
         self.queue, self.blocks_per_cu, self.order = int(queue), int(blocks_per_cu), int(order)
+        self.chunk_layers = int(chunk_layers)
 
     def c(self):
-        return CfvTuning(self.queue, self.blocks_per_cu, self.order)
+        return CfvTuning(self.queue, self.blocks_per_cu, self.order, self.chunk_layers)
 
     def as_dict(self):
-        return {"queue": self.queue, "blocks_per_cu": self.blocks_per_cu, "order": self.order}
+        return {"queue": self.queue, "blocks_per_cu": self.blocks_per_cu, "order": self.order,
+                "chunk_layers": self.chunk_layers}
 
     def __repr__(self):
-        return f"Tuning({self.queue}, {self.blocks_per_cu}, {self.order})"
+        return f"Tuning({self.queue}, {self.blocks_per_cu}, {self.order}, {self.chunk_layers})"
 
 
 class Ensemble:

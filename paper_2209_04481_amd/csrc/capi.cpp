@@ -35,7 +35,7 @@ int dots_noalloc_max_vectors();
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_fused_ensemble(const EnsembleLaunch& e, hipStream_t s, KernelTimer* t);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t);
+                      double* A, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
 hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s);
@@ -125,6 +125,7 @@ struct cfv_ctx {
   double* st_m = nullptr;     // 9 device scalars: the monitor
   unsigned* dflag = nullptr;  // non-physical state word set by the kernels
   int32_t* dftab = nullptr;   // per-tile stencil tables of the fused march
+  int chunk = cfv::kKC;       // layers per work item of the marches
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -158,6 +159,8 @@ cfv_status hip_fail(hipError_t e, const char* where) {
     hipError_t e_ = (call);                                  \
     if (e_ != hipSuccess) return hip_fail(e_, #call);        \
   } while (0)
+
+constexpr int kMaxChunk = 4096;  // largest chunk length (layers per work item)
 
 cfv_status check_ctx(const cfv_ctx* c) {
   if (!c || !c->grid) return fail(CFV_ERR_ARG, "null context");
@@ -355,7 +358,7 @@ cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, R, nullptr};
-  CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, c->chunk, s, c->tm()));
   return CFV_OK;
 }
 
@@ -364,14 +367,14 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
   cfv::MarchArgs a{c->dev(), U, v, dbr, c->W, c->Wd, R, Jv};
-  CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
   return CFV_OK;
 }
 
 cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
-  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
   return CFV_OK;
 }
 
@@ -474,10 +477,10 @@ static cfv_status ensure_krylov(cfv_ctx* c, int m) {
 static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag, int transpose, const double* x,
                                  double* w, hipStream_t s) {
   if (transpose) {
-    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, s, c->tm()));
+    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
   }
   CFV_HIP(cfv::launch_add_diag(c->grid->g.ncells, diag, x, w, s));
   return CFV_OK;
@@ -600,7 +603,7 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   const int64_t n = 9 * c->grid->g.ncells;
   // U_new holds the right-hand side -R(U) during the solve
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
-  CFV_HIP(cfv::launch_march(a, c->slot, false, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, c->chunk, s, c->tm()));
   CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
   if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
@@ -735,10 +738,10 @@ cfv_status cfv_vjp_dir(cfv_ctx* c, const double* U, const double* w, const doubl
   // + side into the outputs, - side into the workspace
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, c->chunk, s, c->tm()));
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, gU2, s));
   if (gbr2) CFV_HIP(cfv::launch_axpby(nb, -ih, gbm, ih, gbr2, s));
@@ -774,13 +777,13 @@ cfv_status cfv_jvp_dir(cfv_ctx* c, const double* U, const double* v, const doubl
   CFV_HIP(cfv::launch_axpby(n, h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dp, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, Jv2};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
   }
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dm, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, c->dir_g};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
   }
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, Jv2, s));
@@ -854,8 +857,8 @@ struct cfv_ensemble {
   cfv::StepLaunch step;
   double* mon = nullptr;                 // 9 n device scalars: monitors of the batched march
   unsigned* dflags = nullptr;            // n non-physical state words, one per instance
-  // the fused residual march's items (its own tiles and chunks of fkc layers)
-  int fkc = 16;
+  // the fused residual march's items (its own tiles, chunks of kc layers)
+  int kc = cfv::kKC;                     // layers per item of both marches
   std::vector<int64_t> foff;             // n + 1 prefix sums of fused items
   int64_t ftotal = 0;
   int64_t* dfoff = nullptr;
@@ -873,8 +876,8 @@ void drop_graph(cfv_ensemble* e) {
 cfv_status check_tuning(const cfv_tuning* t) {
   if (!t) return fail(CFV_ERR_ARG, "null tuning");
   if ((t->queue != 0 && t->queue != 1) || t->blocks_per_cu < 1 || t->blocks_per_cu > 16 ||
-      (t->order != 0 && t->order != 1))
-    return fail(CFV_ERR_ARG, "tuning: queue 0|1, blocks_per_cu 1..16, order 0|1");
+      (t->order != 0 && t->order != 1) || t->chunk_layers < 0 || t->chunk_layers > kMaxChunk)
+    return fail(CFV_ERR_ARG, "tuning: queue 0|1, blocks_per_cu 1..16, order 0|1, chunk_layers 0..4096");
   return CFV_OK;
 }
 
@@ -890,7 +893,7 @@ cfv_status upload_fused_perm(cfv_ensemble* e) {
       const cfv::Shape& g = e->ctx[q]->grid->g;
       for (int64_t l = 0; l < e->foff[q + 1] - e->foff[q]; ++l) {
         cfv::FTile tm;
-        cfv::fused_tile_of(g, e->fkc, l, tm);
+        cfv::fused_tile_of(g, e->kc, l, tm);
         cost[size_t(e->foff[q] + l)] = (tm.wi + 2) * (tm.wj + 2) * (tm.k1 - tm.k0 + 2);
       }
     }
@@ -910,7 +913,7 @@ cfv_status upload_perm(cfv_ensemble* e) {
       const cfv::Shape& g = e->ctx[q]->grid->g;
       for (int64_t l = 0; l < e->off[q + 1] - e->off[q]; ++l) {
         cfv::TileMap tm;
-        cfv::tile_of_logical(g, l, tm);
+        cfv::tile_of_logical(g, l, tm, e->kc);
         const int wi = std::min(cfv::kTI, g.N - tm.i0), wj = std::min(cfv::kTJ, g.N - tm.j0);
         cost[size_t(e->off[q] + l)] = wi * wj * (tm.k1 - tm.k0);
       }
@@ -919,6 +922,36 @@ cfv_status upload_perm(cfv_ensemble* e) {
   }
   CFV_HIP(hipMemcpy(e->dperm, perm.data(), perm.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   return CFV_OK;
+}
+
+// the item lists of both marches for chunks of e->kc layers: prefix sums per
+// instance, device copies (reallocated when they grow) and the processing order
+cfv_status build_items(cfv_ensemble* e) {
+  const size_t n = e->ctx.size();
+  const int64_t old_total = e->dperm ? e->total : 0, old_ftotal = e->dfperm ? e->ftotal : 0;
+  e->off.assign(n + 1, 0);
+  e->foff.assign(n + 1, 0);
+  for (size_t q = 0; q < n; ++q) {
+    const cfv::Shape& g = e->ctx[q]->grid->g;
+    e->off[q + 1] = e->off[q] + cfv::march_logical_blocks(g, e->kc);
+    e->foff[q + 1] = e->foff[q] + cfv::fused_items(g, e->kc);
+  }
+  e->total = e->off[n];
+  e->ftotal = e->foff[n];
+  cfv_status st;
+  if (e->total > old_total) {
+    if (e->dperm) (void)hipFree(e->dperm);
+    e->dperm = nullptr;
+    if ((st = dmalloc(&e->dperm, size_t(e->total)))) return st;
+  }
+  if (e->ftotal > old_ftotal) {
+    if (e->dfperm) (void)hipFree(e->dfperm);
+    e->dfperm = nullptr;
+    if ((st = dmalloc(&e->dfperm, size_t(e->ftotal)))) return st;
+  }
+  CFV_HIP(hipMemcpy(e->doff, e->off.data(), e->off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  CFV_HIP(hipMemcpy(e->dfoff, e->foff.data(), e->foff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  return upload_perm(e);
 }
 
 unsigned ensemble_blocks(const cfv_ensemble* e, int64_t total) {
@@ -938,21 +971,22 @@ cfv_status ensemble_launch(cfv_ensemble* e, hipStream_t s, bool timed) {
   if (e->mode == 1) {
     cfv::StepLaunch& L = e->step;
     L.res = cfv::EnsembleLaunch{e->step_args, e->dfoff, e->dfperm, e->dcnt, n, e->ftotal, e->tune.queue,
-                                ensemble_blocks(e, e->ftotal), e->fkc};
+                                ensemble_blocks(e, e->ftotal), e->kc};
     for (int j = 0; j < L.m; ++j) {
       L.jvp[size_t(j)] = cfv::EnsembleLaunch{e->step_args + size_t(1 + j) * n, e->doff, e->dperm, e->dcnt, n, e->total,
-                                             e->tune.queue, ensemble_blocks(e, e->total)};
+                                             e->tune.queue, ensemble_blocks(e, e->total), e->kc};
     }
     CFV_HIP(cfv::launch_ensemble_step(L, s, t));
     return CFV_OK;
   }
   if (!e->dual) {  // the residual: the fused march over its own item list
     const cfv::EnsembleLaunch Lf{e->dargs, e->dfoff, e->dfperm, e->dcnt, n, e->ftotal, e->tune.queue,
-                                 ensemble_blocks(e, e->ftotal), e->fkc};
+                                 ensemble_blocks(e, e->ftotal), e->kc};
     CFV_HIP(cfv::launch_fused_ensemble(Lf, s, t));
     return CFV_OK;
   }
-  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue, ensemble_blocks(e, e->total)};
+  cfv::EnsembleLaunch L{e->dargs, e->doff, e->dperm, e->dcnt, n, e->total, e->tune.queue, ensemble_blocks(e, e->total),
+                        e->kc};
   CFV_HIP(cfv::launch_march_ensemble(L, e->dual, s, t));
   return CFV_OK;
 }
@@ -979,29 +1013,20 @@ cfv_status cfv_ensemble_create(cfv_ctx* const* ctxs, int32_t n, const cfv_tuning
     delete e;
     return fail(CFV_ERR_HIP, "cannot query the compute unit count");
   }
-  e->off.assign(size_t(n) + 1, 0);
-  for (int q = 0; q < n; ++q) e->off[size_t(q) + 1] = e->off[size_t(q)] + cfv::march_logical_blocks(ctxs[q]->grid->g);
-  e->total = e->off[size_t(n)];
-  e->foff.assign(size_t(n) + 1, 0);
-  for (int q = 0; q < n; ++q) e->foff[size_t(q) + 1] = e->foff[size_t(q)] + cfv::fused_items(ctxs[q]->grid->g, e->fkc);
-  e->ftotal = e->foff[size_t(n)];
+  e->kc = t->chunk_layers ? t->chunk_layers : cfv::kKC;
   cfv_status st;
   if ((st = dmalloc(&e->dargs, size_t(n))) || (st = dmalloc(&e->doff, size_t(n) + 1)) ||
-      (st = dmalloc(&e->dperm, size_t(e->total))) || (st = dmalloc(&e->dcnt, 2)) ||
-      (st = dmalloc(&e->dflags, size_t(n))) || (st = dmalloc(&e->dfoff, size_t(n) + 1)) ||
-      (st = dmalloc(&e->dfperm, size_t(e->ftotal)))) {
+      (st = dmalloc(&e->dcnt, 2)) || (st = dmalloc(&e->dflags, size_t(n))) ||
+      (st = dmalloc(&e->dfoff, size_t(n) + 1))) {
     cfv_ensemble_destroy(e);
     return st;
   }
-  he = hipMemcpy(e->doff, e->off.data(), e->off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-  if (he == hipSuccess) he = hipMemset(e->dflags, 0, size_t(n) * sizeof(unsigned));
-  if (he == hipSuccess)
-    he = hipMemcpy(e->dfoff, e->foff.data(), e->foff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  he = hipMemset(e->dflags, 0, size_t(n) * sizeof(unsigned));
   if (he != hipSuccess) {
     cfv_ensemble_destroy(e);
     return fail(CFV_ERR_HIP, hipGetErrorString(he));
   }
-  if ((st = upload_perm(e))) {
+  if ((st = build_items(e))) {
     cfv_ensemble_destroy(e);
     return st;
   }
@@ -1024,7 +1049,10 @@ cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t) {
   if (cfv_status st = check_tuning(t)) return st;
   e->tune = *t;
   drop_graph(e);
-  return upload_perm(e);
+  const int kc = t->chunk_layers ? t->chunk_layers : cfv::kKC;
+  if (kc == e->kc) return upload_perm(e);
+  e->kc = kc;
+  return build_items(e);
 }
 
 cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks) {
@@ -1299,6 +1327,13 @@ cfv_status cfv_timing_enable(cfv_ctx* c, int32_t on) {
 cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
   if (cfv_status st = check_ctx(c)) return st;
   return timing_read(c->timer, max, names, total_ms, count, n);
+}
+
+cfv_status cfv_set_chunk_layers(cfv_ctx* c, int32_t kc) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (kc < 1 || kc > kMaxChunk) return fail(CFV_ERR_ARG, "chunk layers: 1..4096");
+  c->chunk = kc;
+  return CFV_OK;
 }
 
 }  // extern "C"

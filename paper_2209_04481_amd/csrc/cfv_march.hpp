@@ -7,7 +7,7 @@
 namespace cfv {
 
 constexpr int kTI = 16, kTJ = 16, kNT = kTI * kTJ;  // tile of columns
-constexpr int kKC = 16;                             // radial layers per chunk
+constexpr int kKC = 16;                             // radial layers per chunk (default)
 
 struct MarchArgs {
   DevGrid d;
@@ -26,17 +26,20 @@ struct TileMap {
   int p, j0, i0, k0, k1;
 };
 
-__host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g) {
-  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kKC - 1) / kKC;
+// work items (tile, chunk of kc layers) of one instance
+__host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g, int kc) {
+  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kc - 1) / kc;
   return 6 * ntj * nti * nch;
 }
 
-// launch size: a multiple of 8 so that the remap below is a bijection
-__host__ __device__ __forceinline__ int64_t march_blocks(const Shape& g) { return (march_logical_blocks(g) + 7) / 8 * 8; }
+// launch size: a multiple of 8 so that the XCD split is a bijection
+__host__ __device__ __forceinline__ int64_t march_blocks(const Shape& g, int kc) {
+  return (march_logical_blocks(g, kc) + 7) / 8 * 8;
+}
 
 // logical block l (chunk fastest, then tile i, tile j, panel) -> tile and chunk
-__host__ __device__ __forceinline__ void tile_of_logical(const Shape& g, int64_t l, TileMap& tm) {
-  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kKC - 1) / kKC;
+__host__ __device__ __forceinline__ void tile_of_logical(const Shape& g, int64_t l, TileMap& tm, int kc) {
+  const int64_t nti = (g.N + kTI - 1) / kTI, ntj = (g.N + kTJ - 1) / kTJ, nch = (g.Nr + kc - 1) / kc;
   int64_t r = l;
   const int ch = int(r % nch);
   r /= nch;
@@ -46,19 +49,8 @@ __host__ __device__ __forceinline__ void tile_of_logical(const Shape& g, int64_t
   tm.p = int(r / ntj);
   tm.j0 = tj * kTJ;
   tm.i0 = ti * kTI;
-  tm.k0 = ch * kKC;
-  tm.k1 = tm.k0 + kKC < g.Nr ? tm.k0 + kKC : g.Nr;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
-// give each XCD a contiguous range of (tile, chunk) so that neighbouring
-// tiles and chunks, which re-read each other's edge cells, share an L2.
-__host__ __device__ __forceinline__ bool tile_of(const Shape& g, int64_t b, int64_t nb, TileMap& tm) {
-  const int64_t per = nb / 8;
-  const int64_t l = (b % 8) * per + b / 8;
-  if (l >= march_logical_blocks(g)) return false;
-  tile_of_logical(g, l, tm);
-  return true;
+  tm.k0 = ch * kc;
+  tm.k1 = tm.k0 + kc < g.Nr ? tm.k0 + kc : g.Nr;
 }
 
 // ------------------------------------------------------------- small helpers
@@ -161,17 +153,31 @@ struct GradWG {
       const int pos = plane_pos(ti + dx, tj + dy);
       cs[pos] = cn.x; cs[kPlane + pos] = cn.y; cs[2 * kPlane + pos] = cn.z;
     }
-    load_prims(a, cell_index(g, st.p, tm.k0, st.j, st.i), st.P0);
-    if (tm.k0 > 0) load_prims(a, cell_index(g, st.p, tm.k0 - 1, st.j, st.i), st.Pm);
+    for (int v = 0; v < 9; ++v) st.Pm[v] = st.P0[v] = st.Pp[v] = T(0.0);
   }
 
-  __host__ __device__ static void publish(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
+  // First layer of the march of a chunk [k0, k1): the layers k0 - 1 and k0
+  // enter the registers through the warm-up iterations k < k0, which run this
+  // phase alone, so every layer's primitives come from the same code whatever
+  // the chunk length (and the outputs with them, bit for bit).
+  __host__ __device__ static int first_layer(const TileMap& tm) { return tm.k0 >= 1 ? tm.k0 - 2 : -1; }
+
+  // layer k: load the primitives of layer k + 1; publish layer k's in LDS
+  // (a warm-up iteration only shifts the registers instead)
+  __host__ __device__ static void publish(const MarchArgs& a, const TileMap& tm, GState<T>& st, int t, int k,
                                           double* lds) {
     if (!st.act) return;
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     const int ti = t % kTI, tj = t / kTI;
-    if (k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
+    if (k + 1 >= 0 && k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
+    if (k < tm.k0) {
+      for (int v = 0; v < 9; ++v) {
+        st.Pm[v] = st.P0[v];
+        st.P0[v] = st.Pp[v];
+      }
+      return;
+    }
     T* L = lds_as<T>(lds);
     const int me = plane_pos(ti, tj);
     for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
@@ -379,19 +385,23 @@ struct FluxWG {
     st.i = tm.i0 + t % kTI;
     st.act = st.j < g.N && st.i < g.N;
     st.bad = false;
-    if (!st.act || tm.k0 == 0) return;
-    // top-face state of the layer below the chunk
-    st.col = column_of(g, st.p, st.j, st.i);
-    const int km = tm.k0 - 1;
-    const int64_t c = cell_index(g, st.p, km, st.j, st.i);
-    T P[9], Gr[27];
-    load_prims(a, c, P);
-    load_grad(a, c, Gr);
-    const V3 xc = cell_centre(a.d.G, g, st.p, km, st.j, st.i);
-    const V3 xf = gld(a.d.G.r, tm.k0) * cg3(a.d.G, CG_XR, st.col);
-    recon(P, Gr, xf - xc, st.qtop);
+    for (int v = 0; v < 9; ++v) st.qtop[v] = T(0.0);
   }
 
+  // Layers of the march of a chunk [k0, k1): a warm-up iteration k0 - 1
+  // gives the top-face state of the layer below the chunk, a cool-down
+  // iteration k1 the flux through the chunk's top face, both from the same
+  // code as every other layer's (so the outputs do not depend on the chunk
+  // length, bit for bit).
+  __host__ __device__ static int first_layer(const TileMap& tm) { return tm.k0 > 0 ? tm.k0 - 1 : 0; }
+  __host__ __device__ static int last_layer(const Shape& g, const TileMap& tm) {
+    return tm.k1 < g.Nr ? tm.k1 : tm.k1 - 1;
+  }
+
+  // layer k's face states and its bottom face's flux, which completes the
+  // residual of layer k - 1.  A warm-up layer (k < k0) runs this phase alone
+  // for its top-face state, a cool-down layer (k = k1) for the flux through
+  // the chunk's top face; what else they compute is overwritten or unused.
   __host__ __device__ static void states(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
                                          double* lds) {
     if (!st.act) return;
@@ -556,32 +566,18 @@ struct FluxWG {
     (void)tm;
   }
 
-  // the last layer of the chunk still needs the radial face above it
-  __host__ __device__ static void finish(const MarchArgs& a, const TileMap& tm, FState<T>& st, int) {
+  __host__ __device__ static void finish(const MarchArgs& a, const TileMap&, FState<T>& st, int) {
     record_nonphysical(a.d, st.act && st.bad);
-    if (!st.act || tm.k1 >= a.d.g.Nr) return;
-    const Shape& g = a.d.g;
-    const int k = tm.k1;
-    const int64_t c = cell_index(g, st.p, k, st.j, st.i);
-    T P[9], Gr[27], qb[9], F[9];
-    load_prims(a, c, P);
-    load_grad(a, c, Gr);
-    V3 S, xf;
-    bool own;
-    canon_face(a.d.G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
-    recon(P, Gr, xf - cell_centre(a.d.G, g, st.p, k, st.j, st.i), qb);
-    rusanov(st.qtop, qb, S, F, a.d.pr);
-    for (int v = 0; v < 9; ++v) st.accp[v] += F[v];
-    store_res(a, c - int64_t(g.N) * g.N, st.accp);
   }
 };
 
 // One instance; slot: device memory for one descriptor, owned by the caller
 // (calls sharing a slot must be ordered on one stream).
-hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t);
+// kc: layers per work item (chunk)
+hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, int kc, hipStream_t s, KernelTimer* t);
 // The gradient pass alone (double): limited gradients into a.G and, when
 // a.P is set, the primitives into a.P.
-hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, hipStream_t s, KernelTimer* t);
+hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t);
 
 // Ensemble launch: n instances described by args[n] (device), with
 // item_off[n + 1] (device) the prefix sums of march_logical_blocks per
@@ -599,7 +595,7 @@ struct EnsembleLaunch {
   int64_t total;
   int queue;
   unsigned blocks;
-  int kc = 16;  // layers per chunk of the fused residual march (its items)
+  int kc = kKC;  // layers per chunk (the items' depth), for both marches
 };
 hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t s, KernelTimer* t);
 

@@ -31,8 +31,9 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   const int t = threadIdx.x;
   GState<T> st;
   GradWG<T>::init(a, tm, st, t, lds);
-  for (int k = tm.k0; k < tm.k1; ++k) {
+  for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
+    if (k < tm.k0) continue;  // warm-up: registers only
     if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
@@ -45,8 +46,10 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
   const int t = threadIdx.x;
   FState<T> st;
   FluxWG<T>::init(a, tm, st, t);
-  for (int k = tm.k0; k < tm.k1; ++k) {
+  const int kl = FluxWG<T>::last_layer(a.d.g, tm);
+  for (int k = FluxWG<T>::first_layer(tm); k <= kl; ++k) {
     FluxWG<T>::states(a, tm, st, t, k, lds);
+    if (k < tm.k0 || k >= tm.k1) continue;  // warm-up or cool-down: registers only
     // the second wavefront also loads the ring of out-of-tile neighbour states
     if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, t - kNT / 4, k, lds);
     __syncthreads();
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_e
     const int inst = e.n > 1 ? int(uniform(find_instance(e.item_off, e.n, w))) : 0;
     const MarchArgs& a = e.args[inst];
     TileMap tm;
-    tile_of_logical(a.d.g, e.n > 1 ? w - e.item_off[inst] : w, tm);
+    tile_of_logical(a.d.g, e.n > 1 ? w - e.item_off[inst] : w, tm, e.kc);
     __syncthreads();  // the previous item's LDS reads are done
     if (Flux)
       flux_march_tile<T>(a, tm, lds);
@@ -160,11 +163,11 @@ hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t
 
 // One instance: the descriptor goes to the context's slot, then the same
 // persistent kernels run with one workgroup per item (no queue, no table).
-hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStream_t s, KernelTimer* t) {
-  if (!dual) return launch_fused(a, slot, 16, s, t);  // the residual: one fused pass (fused.hip)
+hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, int kc, hipStream_t s, KernelTimer* t) {
+  if (!dual) return launch_fused(a, slot, kc, s, t);  // the residual: one fused pass (fused.hip)
   hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
-  const int64_t total = march_logical_blocks(a.d.g);
-  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
+  const int64_t total = march_logical_blocks(a.d.g, kc);
+  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g, kc)), kc};
   {
     TimedScope ts(t, "grad_march_jvp", s);
     hipLaunchKernelGGL((march_ensemble_kernel<Dual, false>), dim3(e.blocks), dim3(kNT), 0, s, e);
@@ -174,10 +177,10 @@ hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, hipStream_t s, KernelTimer* t) {
+hipError_t launch_march_grad(const MarchArgs& a, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t) {
   hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
-  const int64_t total = march_logical_blocks(a.d.g);
-  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g))};
+  const int64_t total = march_logical_blocks(a.d.g, kc);
+  EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g, kc)), kc};
   TimedScope ts(t, "grad_march_fwd", s);
   if (a.Q)
     hipLaunchKernelGGL((march_ensemble_kernel<double, false, true>), dim3(e.blocks), dim3(kNT), 0, s, e);

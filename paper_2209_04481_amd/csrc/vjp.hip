@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double
 }
 
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, MarchArgs* slot, hipStream_t s, KernelTimer* t) {
+                      double* A, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t) {
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
   // pass 1: the forward gradient march writes the primitives (rows 0..8 of
@@ -71,7 +71,7 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
   double* Q = A + int64_t(63) * nc;
   double* Gg = A + int64_t(63 + 54) * nc;
   MarchArgs fa{d, U, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W, Q};
-  hipError_t e = launch_march_grad(fa, slot, s, t);
+  hipError_t e = launch_march_grad(fa, slot, kc, s, t);
   if (e != hipSuccess) return e;
   {
     TimedScope ts(t, "adjoint", s);

@@ -92,16 +92,20 @@ void fused_residual(const MarchArgs& a, int kc) {
 
 // the two-pass march (gradient pass, then flux pass), as march.hip runs it
 template <class T, bool Faces = false>
-void grad_march(const MarchArgs& a) {
+void grad_march(const MarchArgs& a, int kc) {
   const Shape& g = a.d.g;
   std::vector<double> lds(size_t(GradWG<T>::kLds));
   std::vector<GState<T>> st(kNT);
-  for (int64_t l = 0; l < march_logical_blocks(g); ++l) {
+  for (int64_t l = 0; l < march_logical_blocks(g, kc); ++l) {
     TileMap tm;
-    tile_of_logical(g, l, tm);
+    tile_of_logical(g, l, tm, kc);
     std::fill(lds.begin(), lds.end(), kPoison);
     for (int t = 0; t < kNT; ++t) GradWG<T>::init(a, tm, st[t], t, lds.data());
-    for (int k = tm.k0; k < tm.k1; ++k) {
+    for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
+      if (k < tm.k0) {
+        for (int t = 0; t < kNT; ++t) GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
+        continue;
+      }
       for (int t = 0; t < kNT; ++t) {
         GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
         if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, t - kNT / 4, k, lds.data());
@@ -112,16 +116,20 @@ void grad_march(const MarchArgs& a) {
 }
 
 template <class T>
-void flux_march(const MarchArgs& a) {
+void flux_march(const MarchArgs& a, int kc) {
   const Shape& g = a.d.g;
   std::vector<double> lds(size_t(FluxWG<T>::kLds));
   std::vector<FState<T>> st(kNT);
-  for (int64_t l = 0; l < march_logical_blocks(g); ++l) {
+  for (int64_t l = 0; l < march_logical_blocks(g, kc); ++l) {
     TileMap tm;
-    tile_of_logical(g, l, tm);
+    tile_of_logical(g, l, tm, kc);
     std::fill(lds.begin(), lds.end(), kPoison);
     for (int t = 0; t < kNT; ++t) FluxWG<T>::init(a, tm, st[t], t);
-    for (int k = tm.k0; k < tm.k1; ++k) {
+    for (int k = FluxWG<T>::first_layer(tm); k <= FluxWG<T>::last_layer(g, tm); ++k) {
+      if (k < tm.k0 || k >= tm.k1) {
+        for (int t = 0; t < kNT; ++t) FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
+        continue;
+      }
       for (int t = 0; t < kNT; ++t) {
         FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
         if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, t - kNT / 4, k, lds.data());
@@ -150,23 +158,26 @@ int host_residual(int N, int Nr, const double* r, const cfv_params* p, const dou
   return 0;
 }
 
-// Jv = J_U v + J_b dbr (dbr nullable) by the dual two-pass march; R (nullable)
-// receives the residual it evaluates along.
+// Jv = J_U v + J_b dbr (dbr nullable) by the dual two-pass march with chunks
+// of kc layers; R (nullable) receives the residual it evaluates along.
 int host_jvp(int N, int Nr, const double* r, const cfv_params* p, const double* U, const double* br,
-             const double* bth, const double* v, const double* dbr, double* Jv, double* R) {
+             const double* bth, int kc, const double* v, const double* dbr, double* Jv, double* R) {
+  if (kc < 1) return 1;
   HostShell s(N, Nr, r, p, br, bth);
   if (!s.ok) return 1;
   const int64_t nc = s.t.g.ncells;
   std::vector<double> G(size_t(27) * nc, kPoison), Gd(size_t(27) * nc, kPoison);
   MarchArgs a{s.d, U, v, dbr, G.data(), Gd.data(), R, Jv};
-  grad_march<Dual>(a);
-  flux_march<Dual>(a);
+  grad_march<Dual>(a, kc);
+  flux_march<Dual>(a, kc);
   return 0;
 }
 
-// gU = J_U^T w and gbr = J_b^T w (gbr nullable) by the adjoint passes.
+// gU = J_U^T w and gbr = J_b^T w (gbr nullable) by the adjoint passes, the
+// forward gradient march in chunks of kc layers.
 int host_vjp(int N, int Nr, const double* r, const cfv_params* p, const double* U, const double* br,
-             const double* bth, const double* w, double* gU, double* gbr) {
+             const double* bth, int kc, const double* w, double* gU, double* gbr) {
+  if (kc < 1) return 1;
   HostShell s(N, Nr, r, p, br, bth);
   if (!s.ok) return 1;
   const Shape& g = s.t.g;
@@ -177,7 +188,7 @@ int host_vjp(int N, int Nr, const double* r, const cfv_params* p, const double* 
   double* Gg = A.data() + int64_t(63 + 54) * nc;
   // pass 1: primitives and face states
   MarchArgs fa{s.d, U, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, W.data(), Q};
-  grad_march<double, true>(fa);
+  grad_march<double, true>(fa, kc);
   // pass 2: the adjoint of each cell, with the block window of 256 cells
   std::vector<double> lW(size_t(63) * kVBlock), lw(size_t(9) * kVBlock);
   for (int64_t c0 = 0; c0 < nc; c0 += kVBlock) {

@@ -1,6 +1,6 @@
 """GPU checks of the batched ensemble launch: every instance's residual and
 JVP equal, bit for bit, those of its own single-instance launch, for every
-schedule, and a captured graph replays to the same bits."""
+schedule and chunk length, and a captured graph replays to the same bits."""
 import numpy as np
 import pytest
 import torch
@@ -44,12 +44,13 @@ def _same(a, b):
     return torch.equal(a, b) or bool(((a == b) | (torch.isnan(a) & torch.isnan(b))).all())
 
 
-@pytest.mark.parametrize("queue,bpc,order", [(0, 1, 0), (0, 2, 1), (1, 1, 0), (1, 4, 1)])
-def test_ensemble_matches_single_instance_launches(setup, queue, bpc, order):
+@pytest.mark.parametrize("queue,bpc,order,kc", [(0, 1, 0, 0), (0, 2, 1, 5), (1, 1, 0, 1), (1, 4, 1, 64),
+                                                (1, 2, 1, 8)])
+def test_ensemble_matches_single_instance_launches(setup, queue, bpc, order, kc):
     from paper_2209_04481_amd import Ensemble, Tuning
     ctxs, U, v, dbr, R1, J1, R0 = setup
-    print(f"case: ensemble schedule queue={queue} bpc={bpc} order={order}", flush=True)
-    ens = Ensemble(ctxs, Tuning(queue, bpc, order))
+    print(f"case: ensemble schedule queue={queue} bpc={bpc} order={order} chunk={kc}", flush=True)
+    ens = Ensemble(ctxs, Tuning(queue, bpc, order, kc))
     R = [torch.full_like(u, float("nan")) for u in U]
     J = [torch.full_like(u, float("nan")) for u in U]
     ens.bind(U, v=v, dbr=dbr, R=R, Jv=J)
@@ -91,9 +92,32 @@ def test_ensemble_graph_replays_match_eager(setup):
         torch.cuda.synchronize()
 
 
-def test_ensemble_rejects_bad_bindings(setup):
-    from paper_2209_04481_amd import CfvError, Ensemble
+def test_ensemble_chunk_change_after_binding(setup):
+    """set_tuning with a new chunk length rebuilds the item lists (longer and
+    shorter ones) under a bound run; the outputs keep their bits."""
+    from paper_2209_04481_amd import Ensemble, Tuning
     ctxs, U, v, dbr, R1, J1, R0 = setup
+    print("case: ensemble chunk change after binding", flush=True)
+    ens = Ensemble(ctxs, Tuning(1, 2, 1, 16))
+    R = [torch.empty_like(u) for u in U]
+    J = [torch.empty_like(u) for u in U]
+    ens.bind(U, v=v, dbr=dbr, R=R, Jv=J)
+    for kc in (2, 40, 3, 0):
+        for t in R + J:
+            t.fill_(float("nan"))
+        ens.set_tuning(Tuning(0, 2, 1, kc))
+        ens.run()
+        torch.cuda.synchronize()
+        for q in range(len(U)):
+            assert _same(R[q], R1[q]) and _same(J[q], J1[q]), f"chunk {kc}, instance {q}"
+
+
+def test_ensemble_rejects_bad_bindings(setup):
+    from paper_2209_04481_amd import CfvError, Ensemble, Tuning
+    ctxs, U, v, dbr, R1, J1, R0 = setup
+    for kc in (-1, 4097):
+        with pytest.raises(CfvError):
+            Ensemble(ctxs, Tuning(1, 2, 1, kc))
     ens = Ensemble(ctxs)
     with pytest.raises(CfvError):
         ens.run()  # nothing bound
@@ -105,9 +129,9 @@ def test_ensemble_rejects_bad_bindings(setup):
         ens.replay(torch.cuda.Stream())  # nothing captured
 
 
-def test_autotune_picks_a_listed_schedule(setup, tmp_path, monkeypatch):
+def test_autotune_picks_a_listed_schedule_and_depth(setup, tmp_path, monkeypatch):
     from paper_2209_04481_amd import Ensemble
-    from paper_2209_04481_amd.autotune import CANDIDATES, autotune
+    from paper_2209_04481_amd.autotune import CHUNKS, SCHEDULES, autotune
     ctxs, U, v, dbr, R1, J1, R0 = setup
     monkeypatch.setenv("CFV_TUNE_CACHE", str(tmp_path / "tune.json"))
     ens = Ensemble(ctxs)
@@ -115,7 +139,9 @@ def test_autotune_picks_a_listed_schedule(setup, tmp_path, monkeypatch):
     J = [torch.empty_like(u) for u in U]
     ens.bind(U, v=v, R=R, Jv=J)
     best, ms = autotune(ens, reps=2)
-    assert repr(best) in {repr(t) for t in CANDIDATES} and len(ms) == len(CANDIDATES)
+    sched = {(t.queue, t.blocks_per_cu, t.order) for t in SCHEDULES}
+    assert (best.queue, best.blocks_per_cu, best.order) in sched and best.chunk_layers in (0,) + tuple(CHUNKS)
+    assert len(ms) == len(SCHEDULES) + len(CHUNKS) and min(ms.values()) == ms[repr(best)]
     again, _ = autotune(ens, reps=2)  # from the cache
     assert repr(again) == repr(best)
     ens.run()

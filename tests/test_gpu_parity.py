@@ -121,6 +121,38 @@ def test_dot_product_identity_tiny(tiny):
     assert abs(lhs - rhs) <= 1e-12 * float((w * Jv).abs().sum())
 
 
+@pytest.mark.parametrize("N,Nr", [(6, 10), (17, 23)])
+def test_chunk_length_leaves_every_output_unchanged(N, Nr):
+    """The chunk length (layers per work item) changes only the work
+    decomposition: residual, JVP (with R) and VJP (with the B_r gradient) are
+    bitwise those of the default chunk, for chunks of 1 layer, partial last
+    chunks and one chunk longer than the shell."""
+    from paper_2209_04481_amd import CfvError
+    print(f"case: chunk lengths on {N}x{Nr}", flush=True)
+    c = Case(ci.make_instance(N, Nr, "log", lmax=4, seed=N + Nr))
+    v = torch.tensor(ci.scaled_direction(c.inst.U, 5)).cuda()
+    dbr = torch.tensor(ci.br_direction(c.grid.nb, 5)).cuda()
+    w = torch.randn(9, c.inst.ncells, dtype=torch.float64, generator=torch.Generator().manual_seed(6)).cuda()
+
+    def outputs():
+        R = c.ctx.residual(c.Ud)
+        Rj = torch.empty_like(c.Ud)
+        Jv = c.ctx.jvp(c.Ud, v, dbr, R=Rj)
+        gU, gbr = c.ctx.vjp(c.Ud, w)
+        torch.cuda.synchronize()
+        return R, Rj, Jv, gU, gbr
+
+    ref = outputs()
+    for kc in (1, 3, 7, Nr, 4096):
+        c.ctx.set_chunk_layers(kc)
+        for name, a, b in zip(("R", "R(jvp)", "Jv", "gU", "gbr"), outputs(), ref):
+            assert torch.equal(a, b), f"{name} with chunk {kc}"
+    for kc in (0, 4097):
+        with pytest.raises(CfvError):
+            c.ctx.set_chunk_layers(kc)
+    c.ctx.set_chunk_layers(16)
+
+
 @pytest.mark.parametrize("limiter", [0, 1])
 def test_parity_log_grid_ragged(limiter):
     """A grid whose cell count (6*6*6*10 = 2160) is not a multiple of the block."""

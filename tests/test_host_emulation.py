@@ -92,8 +92,8 @@ gU = np.full_like(U, np.nan); gbr = np.full_like(br, np.nan)
 flag = ctypes.c_uint(0)
 bt = ptr(bth) if prm["inner_mode"] == 1 else None
 assert L.host_residual(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(R), ctypes.byref(flag)) == 0
-assert L.host_jvp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, ptr(v), ptr(dbr), ptr(Jv), ptr(Rj)) == 0
-assert L.host_vjp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, ptr(w), ptr(gU), ptr(gbr)) == 0
+assert L.host_jvp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(v), ptr(dbr), ptr(Jv), ptr(Rj)) == 0
+assert L.host_vjp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(w), ptr(gU), ptr(gbr)) == 0
 np.savez({out!r}, R=R, Rj=Rj, Jv=Jv, gU=gU, gbr=gbr, flag=flag.value)
 '''
 
@@ -144,3 +144,36 @@ def test_host_emulation_matches_the_oracle(harness, tmp_path, N, Nr, kc, kw):
     sides = torch.cat([fs["PL"], fs["PR"]], 1)
     expect = bool(((sides[..., 0] <= 0) | (sides[..., 7] <= 0)).any())
     assert bool(int(res["flag"]) & 1) == expect
+
+
+def test_host_emulation_outputs_do_not_depend_on_the_chunk_length(harness, tmp_path):
+    """Residual, JVP and VJP of one shell for chunks of 1, 2, 5, 16 and 40
+    layers (Nr = 11): bitwise equal, since every face flux is evaluated once
+    from the same states and every cell sums its faces in a fixed order."""
+    lib, pre = harness
+    N, Nr = 7, 11
+    inst = ci.make_instance(N, Nr, "log", lmax=3, seed=77)
+    op = mhd.Params()
+    v = ci.scaled_direction(inst.U, 3)
+    dbr = ci.br_direction(6 * N * N, 3)
+    w = np.random.default_rng(8).standard_normal(inst.U.shape)
+    prm = tmp_path / "prm.json"
+    import json
+    prm.write_text(json.dumps({"gamma": op.gamma, "c_h": op.c_h, "G": op.G, "vr_star": op.vr_star, "rho_b": op.rho_b,
+                               "T_b": op.T_b, "limiter": int(op.limiter), "inner_mode": 0,
+                               "outer_exp": [float(x) for x in op.outer_exp], "outer_vr_mass": int(op.outer_vr_mass),
+                               "outer_psi_zero": int(op.outer_psi_zero)}))
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    res = {}
+    for kc in (16, 1, 2, 5, 40):
+        inp, out, script = tmp_path / f"in{kc}.npz", tmp_path / f"out{kc}.npz", tmp_path / f"run{kc}.py"
+        np.savez(inp, N=N, Nr=Nr, kc=kc, r=inst.r_nodes, U=inst.U, br=inst.br, bth=np.zeros(6 * N * N), v=v,
+                 dbr=dbr, w=w)
+        script.write_text(RUNNER.format(root=ROOT, lib=lib, inp=str(inp), prm=str(prm), out=str(out)))
+        r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
+        assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-6000:])
+        res[kc] = np.load(out)
+    for kc in (1, 2, 5, 40):
+        for name in ("R", "Rj", "Jv", "gU", "gbr"):
+            assert np.array_equal(res[kc][name], res[16][name]), f"{name} with chunk {kc}"
