@@ -344,52 +344,48 @@ struct FusedWG {
     const GeomRef& G = a.d.G;
     T* L = lds_as<T>(lds);
     const int bi = st.bi, bj = st.bj;
-    if (st.role == 1) {
-      {
-        V3 S, xf;
-        bool own;
-        canon_face(G, g, st.p, k, st.j, st.i, 3, Nbr{}, 0, S, xf, own);
-        T qo[9], F[9];
-        for (int v = 0; v < 9; ++v) qo[v] = L[kSW + v * kFL + t + 1];
-        face_flux(own, st.qE, qo, S, F, a.d.pr);
-        for (int v = 0; v < 9; ++v) {
-          const T f = own ? F[v] : -F[v];
-          st.acc[v] += f;
-          L[kFE + v * kFL + t] = f;
-        }
-      }
-      {
-        V3 S, xf;
-        bool own;
-        canon_face(G, g, st.p, k, st.j, st.i, 5, Nbr{}, 0, S, xf, own);
-        const bool ring_n = bj == tm.wj;  // the north neighbour is a ring cell: its shared-face state
-        T qo[9], F[9];
-        for (int v = 0; v < 9; ++v) qo[v] = L[(ring_n ? kSW : kSS) + v * kFL + t + kFB];
-        face_flux(own, st.qN, qo, S, F, a.d.pr);
-        for (int v = 0; v < 9; ++v) {
-          const T f = own ? F[v] : -F[v];
-          st.acc[v] += f;
-          L[kFN + v * kFL + t] = f;
-        }
-      }
-    } else if (st.role == 2 && (bi == 0 || bj == 0)) {
-      // the face between this ring cell and the inner cell east (bi == 0) or
-      // north (bj == 0) of it, in that inner cell's frame
+    const bool inner = st.role == 1;
+    // First face, one evaluation for both kinds of lane (a wavefront holds
+    // both): an inner lane's east face, or the face between a west (south)
+    // ring lane and the inner cell east (north) of it, in that inner cell's
+    // frame.  Stored signed from the lane toward its east or north neighbour.
+    if (inner || (st.role == 2 && (bi == 0 || bj == 0))) {
       const bool west = bi == 0;
-      const int tn = west ? t + 1 : t + kFB;
-      int ip, ij, ii;
-      column_pji(g, gld(table(a, tm) + kFTabCol, tn), ip, ij, ii);
+      const int tn = inner ? t + 1 : west ? t + 1 : t + kFB;  // the other side's lane
+      int fp = st.p, fj = st.j, fi = st.i;
+      if (!inner) column_pji(g, gld(table(a, tm) + kFTabCol, tn), fp, fj, fi);
       V3 S, xf;
       bool own;
-      canon_face(G, g, ip, k, ij, ii, west ? 2 : 4, Nbr{}, 0, S, xf, own);
-      T qi[9], qr[9], F[9];
+      canon_face(G, g, fp, k, fj, fi, inner ? 3 : west ? 2 : 4, Nbr{}, 0, S, xf, own);
+      T qs[9], qo[9], F[9];
       for (int v = 0; v < 9; ++v) {
-        qi[v] = L[(west ? kSW : kSS) + v * kFL + tn];
-        qr[v] = L[kSW + v * kFL + t];
+        qs[v] = inner ? st.qE[v] : L[(west ? kSW : kSS) + v * kFL + tn];
+        qo[v] = L[kSW + v * kFL + (inner ? tn : t)];
       }
-      face_flux(own, qi, qr, S, F, a.d.pr);
-      // out of the inner cell through its west / south face is toward this lane
-      for (int v = 0; v < 9; ++v) L[(west ? kFE : kFN) + v * kFL + t] = own ? -F[v] : F[v];
+      face_flux(own, qs, qo, S, F, a.d.pr);
+      // an inner lane's flux leaves it eastward; a ring lane's leaves the
+      // inner cell through its west / south face, toward the ring lane
+      const bool neg = inner ? !own : own;
+      for (int v = 0; v < 9; ++v) {
+        const T f = neg ? -F[v] : F[v];
+        if (inner) st.acc[v] += f;
+        L[(inner || west ? kFE : kFN) + v * kFL + t] = f;
+      }
+    }
+    // second face: an inner lane's north face
+    if (inner) {
+      V3 S, xf;
+      bool own;
+      canon_face(G, g, st.p, k, st.j, st.i, 5, Nbr{}, 0, S, xf, own);
+      const bool ring_n = bj == tm.wj;  // the north neighbour is a ring cell: its shared-face state
+      T qo[9], F[9];
+      for (int v = 0; v < 9; ++v) qo[v] = L[(ring_n ? kSW : kSS) + v * kFL + t + kFB];
+      face_flux(own, st.qN, qo, S, F, a.d.pr);
+      for (int v = 0; v < 9; ++v) {
+        const T f = own ? F[v] : -F[v];
+        st.acc[v] += f;
+        L[kFN + v * kFL + t] = f;
+      }
     }
   }
 
