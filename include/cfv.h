@@ -416,12 +416,14 @@ cfv_status cfv_ensemble_steady(cfv_ensemble* e, double* const* U, double* const*
 cfv_status cfv_timing_enable(cfv_ctx* ctx, int32_t on);
 /* Work decomposition of the context's own launches: every march (the fused
  * residual march, the dual JVP march, the VJP's gradient march) splits each
- * column tile's Nr layers into chunks of kc layers (1..4096, default 16), one
- * work item each.  A chunk re-reads the layers on either side of it, so
- * longer chunks move fewer bytes, shorter ones give more work items on small
- * grids.  Every output is bitwise the same for every kc: each face flux is
- * evaluated once from the same states, and each cell sums its faces in a
- * fixed order. */
+ * column tile's Nr layers into chunks of kc layers (1..4096), one work item
+ * each.  kc = 0 (the default) lets each march balance its items over the
+ * device's compute units: of the chunk counts, the one with the fewest
+ * rounds of items times layers marched per item.  A chunk also marches the
+ * layers on either side of it, so longer chunks move fewer bytes, shorter
+ * ones give more work items on small grids.  Every output is bitwise the
+ * same for every kc: each face flux is evaluated once from the same states,
+ * and each cell sums its faces in a fixed order. */
 cfv_status cfv_set_chunk_layers(cfv_ctx* ctx, int32_t kc);
 cfv_status cfv_timing_read(cfv_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n);
 

@@ -408,7 +408,8 @@ class Context:
         check(lib().cfv_timing_enable(self._h, int(bool(on))))
 
     def set_chunk_layers(self, kc: int):
-        """Layers per work item of this context's marches (outputs unchanged)."""
+        """Layers per work item of this context's marches, 0 = balanced per
+        march (the default); the outputs do not change."""
         check(lib().cfv_set_chunk_layers(self._h, int(kc)))
 
     def timing_read(self, max_names=32):

@@ -125,7 +125,10 @@ struct cfv_ctx {
   double* st_m = nullptr;     // 9 device scalars: the monitor
   unsigned* dflag = nullptr;  // non-physical state word set by the kernels
   int32_t* dftab = nullptr;   // per-tile stencil tables of the fused march
-  int chunk = cfv::kKC;       // layers per work item of the marches
+  int chunk = 0;              // layers per work item of the marches (0: balanced_chunk per march)
+  int fused_chunk = cfv::kKC;  // the balanced choices for this grid and device
+  int dual_chunk = cfv::kKC;
+  int march_chunk(bool dual) const { return chunk ? chunk : dual ? dual_chunk : fused_chunk; }
   cfv::DevGrid dev() const {
     cfv::DevGrid d;
     d.g = grid->g;
@@ -274,6 +277,16 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (!c) return fail(CFV_ERR_ALLOC, "host allocation");
   c->grid = g;
   CFV_HIP(hipGetDevice(&c->device));
+  {
+    int cus = 0;
+    CFV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    if (cus < 1) cus = 1;
+    // one workgroup of either march per compute unit (LDS and registers)
+    const cfv::Shape& sh = g->g;
+    const int64_t dual_tiles = 6LL * ((sh.N + cfv::kTI - 1) / cfv::kTI) * ((sh.N + cfv::kTJ - 1) / cfv::kTJ);
+    c->fused_chunk = cfv::balanced_chunk(cfv::fused_tile_count(sh), sh.Nr, cus);
+    c->dual_chunk = cfv::balanced_chunk(dual_tiles, sh.Nr, cus);
+  }
   c->pr.gamma = prm->gamma;
   c->pr.c_h = prm->c_h;
   c->pr.G = prm->G;
@@ -358,7 +371,7 @@ cfv_status cfv_residual(cfv_ctx* c, const double* U, double* R, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !R) return fail(CFV_ERR_ARG, "null state or output");
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, R, nullptr};
-  CFV_HIP(cfv::launch_march(a, c->slot, false, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, c->march_chunk(false), s, c->tm()));
   return CFV_OK;
 }
 
@@ -367,14 +380,14 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
   cfv::MarchArgs a{c->dev(), U, v, dbr, c->W, c->Wd, R, Jv};
-  CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   return CFV_OK;
 }
 
 cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
-  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
   return CFV_OK;
 }
 
@@ -477,10 +490,10 @@ static cfv_status ensure_krylov(cfv_ctx* c, int m) {
 static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag, int transpose, const double* x,
                                  double* w, hipStream_t s) {
   if (transpose) {
-    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
+    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   CFV_HIP(cfv::launch_add_diag(c->grid->g.ncells, diag, x, w, s));
   return CFV_OK;
@@ -603,7 +616,7 @@ cfv_status cfv_be_step(cfv_ctx* c, const double* U, double cfl, int32_t m, int32
   const int64_t n = 9 * c->grid->g.ncells;
   // U_new holds the right-hand side -R(U) during the solve
   cfv::MarchArgs a{c->dev(), U, nullptr, nullptr, c->W, nullptr, U_new, nullptr};
-  CFV_HIP(cfv::launch_march(a, c->slot, false, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_march(a, c->slot, false, c->march_chunk(false), s, c->tm()));
   CFV_HIP(cfv::launch_axpby(n, 0.0, U_new, -1.0, U_new, s));
   CFV_HIP(cfv::launch_local_dt(c->dev(), U, cfl, c->kry_d, c->W, s, c->tm()));
   if (cfv_status st = cfv_solve(c, U, c->kry_d, U_new, 0, m, max_restarts, rtol, c->kry_x, hist, hist_len, iters,
@@ -738,10 +751,10 @@ cfv_status cfv_vjp_dir(cfv_ctx* c, const double* U, const double* w, const doubl
   // + side into the outputs, - side into the workspace
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, c->chunk, s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, gU2, s));
   if (gbr2) CFV_HIP(cfv::launch_axpby(nb, -ih, gbm, ih, gbr2, s));
@@ -777,13 +790,13 @@ cfv_status cfv_jvp_dir(cfv_ctx* c, const double* U, const double* v, const doubl
   CFV_HIP(cfv::launch_axpby(n, h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dp, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, Jv2};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dm, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, c->dir_g};
-    CFV_HIP(cfv::launch_march(a, c->slot, true, c->chunk, s, c->tm()));
+    CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, Jv2, s));
@@ -1331,7 +1344,7 @@ cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_m
 
 cfv_status cfv_set_chunk_layers(cfv_ctx* c, int32_t kc) {
   if (cfv_status st = check_ctx(c)) return st;
-  if (kc < 1 || kc > kMaxChunk) return fail(CFV_ERR_ARG, "chunk layers: 1..4096");
+  if (kc < 0 || kc > kMaxChunk) return fail(CFV_ERR_ARG, "chunk layers: 0 (balanced) or 1..4096");
   c->chunk = kc;
   return CFV_OK;
 }

@@ -32,6 +32,26 @@ __host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g,
   return 6 * ntj * nti * nch;
 }
 
+// Chunk length for a march over `tiles` column tiles of Nr layers with
+// `slots` workgroups resident at once: of the chunk counts n, the one that
+// minimises the rounds of work items times the layers an item marches (its
+// own, plus one warm-up and one cool-down layer); kc = ceil(Nr / n).
+inline int balanced_chunk(int64_t tiles, int Nr, int64_t slots) {
+  int best = Nr;
+  int64_t best_cost = -1;
+  for (int n = 1; n <= Nr; ++n) {
+    const int kc = (Nr + n - 1) / n;
+    if ((Nr + kc - 1) / kc != n) continue;  // the same chunks as a smaller n
+    const int64_t rounds = (tiles * n + slots - 1) / slots;
+    const int64_t cost = rounds * (kc + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = kc;
+    }
+  }
+  return best;
+}
+
 // launch size: a multiple of 8 so that the XCD split is a bijection
 __host__ __device__ __forceinline__ int64_t march_blocks(const Shape& g, int kc) {
   return (march_logical_blocks(g, kc) + 7) / 8 * 8;

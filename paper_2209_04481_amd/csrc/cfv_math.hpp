@@ -118,7 +118,8 @@ struct Params {
 template <class T>
 __host__ __device__ __forceinline__ void cons_to_prim(const T u[9], T q[9], double gamma) {
   T rho = u[0];
-  T vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
+  T irho = 1.0 / rho;
+  T vx = u[1] * irho, vy = u[2] * irho, vz = u[3] * irho;
   T v2 = vx * vx + vy * vy + vz * vz;
   T B2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
   q[0] = rho; q[1] = vx; q[2] = vy; q[3] = vz;
@@ -157,16 +158,17 @@ __host__ __device__ __forceinline__ T side_speed(const T q[9], V3 n, double gamm
 }
 
 // F += wf * (F(q).n) + wu * U(q): one side's share of the Rusanov flux
+// (igm1 = 1 / (gamma - 1))
 template <class T>
 __host__ __device__ __forceinline__ void side_accumulate(const T q[9], V3 n, double wf, T wu, T F[9],
-                                                         double gamma, double c_h) {
+                                                         double igm1, double c_h) {
   T rho = q[0], vx = q[1], vy = q[2], vz = q[3], bx = q[4], by = q[5], bz = q[6], p = q[7], psi = q[8];
   T vn = vx * n.x + vy * n.y + vz * n.z;
   T bn = bx * n.x + by * n.y + bz * n.z;
   T B2 = bx * bx + by * by + bz * bz;
   T v2 = vx * vx + vy * vy + vz * vz;
   T pT = p + 0.5 * B2;
-  T E = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
+  T E = p * igm1 + 0.5 * rho * v2 + 0.5 * B2;
   T rvn = rho * vn;
   T vb = vx * bx + vy * by + vz * bz;
   F[0] += wf * rvn + wu * rho;
@@ -184,7 +186,7 @@ __host__ __device__ __forceinline__ void side_accumulate(const T q[9], V3 n, dou
 template <class T>
 __host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], double gamma, double c_h) {
   for (int v = 0; v < 9; ++v) F[v] = T(0.0);
-  side_accumulate(q, n, 1.0, T(0.0), F, gamma, c_h);
+  side_accumulate(q, n, 1.0, T(0.0), F, 1.0 / (gamma - 1.0), c_h);
   return side_speed(q, n, gamma);
 }
 
@@ -199,8 +201,9 @@ __host__ __device__ __forceinline__ T rusanov(const T qL[9], const T qR[9], V3 S
   s = pick_max(s, T(pr.c_h));
   const T hs = 0.5 * s;
   for (int v = 0; v < 9; ++v) F[v] = T(0.0);
-  side_accumulate(qL, n, 0.5, hs, F, pr.gamma, pr.c_h);
-  side_accumulate(qR, n, 0.5, -hs, F, pr.gamma, pr.c_h);
+  const double igm1 = 1.0 / (pr.gamma - 1.0);  // invariant: hoisted out of the marches' loops
+  side_accumulate(qL, n, 0.5, hs, F, igm1, pr.c_h);
+  side_accumulate(qR, n, 0.5, -hs, F, igm1, pr.c_h);
   for (int v = 0; v < 9; ++v) F[v] = F[v] * area;
   return s;
 }

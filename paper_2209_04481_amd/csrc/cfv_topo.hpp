@@ -153,7 +153,7 @@ __host__ __device__ __forceinline__ V3 cell_centre(const GeomRef& G, const Shape
 
 __host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
   const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
-  return (r1 * r1 * r1 - r0 * r0 * r0) * gld(G.cg, CG_OMEGA * G.ncol + column_of(g, p, j, i)) / 3.0;
+  return (r1 * r1 * r1 - r0 * r0 * r0) * gld(G.cg, CG_OMEGA * G.ncol + column_of(g, p, j, i)) * (1.0 / 3.0);
 }
 
 // canonical geometry of the face across local face lf of cell (p,k,j,i): the

@@ -125,8 +125,8 @@ def test_dot_product_identity_tiny(tiny):
 def test_chunk_length_leaves_every_output_unchanged(N, Nr):
     """The chunk length (layers per work item) changes only the work
     decomposition: residual, JVP (with R) and VJP (with the B_r gradient) are
-    bitwise those of the default chunk, for chunks of 1 layer, partial last
-    chunks and one chunk longer than the shell."""
+    bitwise those of the default (balanced) chunks, for chunks of 1 layer,
+    partial last chunks and one chunk longer than the shell."""
     from paper_2209_04481_amd import CfvError
     print(f"case: chunk lengths on {N}x{Nr}", flush=True)
     c = Case(ci.make_instance(N, Nr, "log", lmax=4, seed=N + Nr))
@@ -143,14 +143,13 @@ def test_chunk_length_leaves_every_output_unchanged(N, Nr):
         return R, Rj, Jv, gU, gbr
 
     ref = outputs()
-    for kc in (1, 3, 7, Nr, 4096):
+    for kc in (1, 3, 7, 16, Nr, 4096, 0):
         c.ctx.set_chunk_layers(kc)
         for name, a, b in zip(("R", "R(jvp)", "Jv", "gU", "gbr"), outputs(), ref):
             assert torch.equal(a, b), f"{name} with chunk {kc}"
-    for kc in (0, 4097):
+    for kc in (-1, 4097):
         with pytest.raises(CfvError):
             c.ctx.set_chunk_layers(kc)
-    c.ctx.set_chunk_layers(16)
 
 
 @pytest.mark.parametrize("limiter", [0, 1])
