@@ -86,8 +86,10 @@ struct FuState {
   int p, j, i;       // the lane's cell (a ring cell in its own panel's coordinates)
   int64_t col;
   int nb[4];         // positions of the angular neighbours (local face order)
+  int32_t ncol[4];   // columns of the angular neighbours (the stencil geometry)
+  int32_t fcol;      // west / south ring lanes: the column of the inner cell across the shared face
   int back;          // ring: the local face shared with the tile
-  int64_t ocol;      // the outer slot this lane loads (lanes 0..63), -1: none
+  int64_t obase;     // the outer slot this lane loads (lanes 0..63): its cell at layer 0, -1: none
   bool bad;          // met a non-physical face state
   T Un[9];           // conservative state of the next layer (prefetched)
   T On[9];           // the outer slot's conservative state of the next layer
@@ -100,7 +102,7 @@ struct FuState {
 // six neighbours' centroids (mirrored ghost centres on the boundary) and of
 // the six face centroids.  ncol: the columns of its angular neighbours.
 __host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int p, int k, int j, int i,
-                                                          const int64_t ncol[4], V3& xc, V3 dx[6], V3 dxf[6]) {
+                                                          const int32_t ncol[4], V3& xc, V3 dx[6], V3 dxf[6]) {
   const double rs = 0.125 * (gld(G.r, k) + gld(G.r, k + 1));
   xc = rs * cg3(G, CG_CSUM, column_of(g, p, j, i));
 #pragma unroll
@@ -165,7 +167,16 @@ struct FusedWG {
       st.nb[3] = tt + kFB;
       st.back = 2;
     }
-    st.ocol = t < kOuterSlots ? int64_t(gld(tab + kFTabOcol, t)) : -1;
+    const int64_t ocol = t < kOuterSlots ? int64_t(gld(tab + kFTabOcol, t)) : -1;
+    st.obase = -1;
+    if (ocol >= 0) {
+      int op, oj, oi;
+      column_pji(g, ocol, op, oj, oi);
+      st.obase = cell_index(g, op, 0, oj, oi);
+    }
+    // per-item constants the layers reuse (loaded once, not per layer)
+    for (int q = 0; q < 4; ++q) st.ncol[q] = gld(G.cn, q * G.ncol + st.col);
+    st.fcol = st.role == 2 && (st.bi == 0 || st.bj == 0) ? gld(tab + kFTabCol, st.bi == 0 ? t + 1 : t + kFB) : 0;
     // layers kb - 1 and kb of the block into LDS; the next layer prefetched
     T* L = lds_as<T>(lds);
     for (int kk = kb > 0 ? kb - 1 : kb; kk <= kb; ++kk) {
@@ -175,12 +186,7 @@ struct FusedWG {
       for (int v = 0; v < 9; ++v) L[plane(kk) + v * kFL + t] = q[v];
     }
     if (kb + 1 < g.Nr) load_cons(a, cell_index(g, st.p, kb + 1, st.j, st.i), st.Un);
-    if (st.ocol >= 0) {
-      int op, oj, oi;
-      column_pji(g, st.ocol, op, oj, oi);
-      load_cons(a, cell_index(g, op, kb, oj, oi), st.On);
-    }
-    (void)G;
+    if (st.obase >= 0) load_cons(a, st.obase + int64_t(kb) * g.N * g.N, st.On);
   }
 
   // ------------------------------------------------------------- publish
@@ -196,15 +202,11 @@ struct FusedWG {
       for (int v = 0; v < 9; ++v) L[plane(k + 1) + v * kFL + t] = q[v];
       if (k + 2 < g.Nr) load_cons(a, cell_index(g, st.p, k + 2, st.j, st.i), st.Un);
     }
-    if (st.ocol >= 0) {
+    if (st.obase >= 0) {
       T q[9];
       cons_to_prim(st.On, q, a.d.pr.gamma);
       for (int v = 0; v < 9; ++v) L[kPO + v * kOuterSlots + t] = q[v];
-      if (k + 1 < g.Nr) {
-        int op, oj, oi;
-        column_pji(g, st.ocol, op, oj, oi);
-        load_cons(a, cell_index(g, op, k + 1, oj, oi), st.On);
-      }
+      if (k + 1 < g.Nr) load_cons(a, st.obase + int64_t(k + 1) * g.N * g.N, st.On);
     }
     (void)tm;
   }
@@ -228,10 +230,8 @@ struct FusedWG {
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     T* L = lds_as<T>(lds);
-    int64_t ncol[4];
-    for (int q = 0; q < 4; ++q) ncol[q] = gld(G.cn, q * G.ncol + st.col);
     V3 xc, dx[6], dxf[6];
-    stencil_geometry(G, g, st.p, k, st.j, st.i, ncol, xc, dx, dxf);
+    stencil_geometry(G, g, st.p, k, st.j, st.i, st.ncol, xc, dx, dxf);
     const LsqWeights W(dx);
     T P0[9];
     for (int v = 0; v < 9; ++v) P0[v] = L[plane(k) + v * kFL + t];
@@ -352,11 +352,9 @@ struct FusedWG {
     if (inner || (st.role == 2 && (bi == 0 || bj == 0))) {
       const bool west = bi == 0;
       const int tn = inner ? t + 1 : west ? t + 1 : t + kFB;  // the other side's lane
-      int fp = st.p, fj = st.j, fi = st.i;
-      if (!inner) column_pji(g, gld(table(a, tm) + kFTabCol, tn), fp, fj, fi);
       V3 S, xf;
       bool own;
-      canon_face(G, g, fp, k, fj, fi, inner ? 3 : west ? 2 : 4, Nbr{}, 0, S, xf, own);
+      canon_face_col(G, inner ? st.col : int64_t(st.fcol), k, inner ? 3 : west ? 2 : 4, S, xf, own);
       T qs[9], qo[9], F[9];
       for (int v = 0; v < 9; ++v) {
         qs[v] = inner ? st.qE[v] : L[(west ? kSW : kSS) + v * kFL + tn];

@@ -160,9 +160,8 @@ __host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const S
 // owner's vector area (pointing from the owner to the other side), the
 // owner's centroid, and whether (p,k,j,i) is the owner.  The owner of a face
 // is the cell with the lower index, or the interior cell on the boundary.
-__host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
-                                           const Nbr&, int64_t, V3& S, V3& xf, bool& owner) {
-  const int64_t col = column_of(g, p, j, i);
+__host__ __device__ __forceinline__ void canon_face_col(const GeomRef& G, int64_t col, int k, int lf, V3& S, V3& xf,
+                                                        bool& owner) {
   if (lf < 2) {
     const double r = gld(G.r, k + lf);
     const V3 sr = cg3(G, CG_SR, col);
@@ -177,6 +176,11 @@ __host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shap
   S = (0.5 * (r1 * r1 - r0 * r0)) * cg3(G, CG_ANG + 6 * q, col);
   xf = (0.25 * (r0 + r1)) * cg3(G, CG_ANG + 6 * q + 3, col);
   owner = (gld(G.cn, (4 + q) * G.ncol + col) >> 8) != 0;
+}
+
+__host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
+                                           const Nbr&, int64_t, V3& S, V3& xf, bool& owner) {
+  canon_face_col(G, column_of(g, p, j, i), k, lf, S, xf, owner);
 }
 
 // vector area pointing out of cell (p,k,j,i) and centroid of its face lf
