@@ -98,10 +98,14 @@ __host__ __device__ __forceinline__ void recon(const T P[9], const T Gr[27], V3 
   for (int v = 0; v < 9; ++v) q[v] = P[v] + (Gr[3 * v] * d.x + Gr[3 * v + 1] * d.y + Gr[3 * v + 2] * d.z);
 }
 
+// column -> (panel, j, i); columns are below 2^31 (32-bit division)
 __host__ __device__ __forceinline__ void column_pji(const Shape& g, int64_t col, int& p, int& j, int& i) {
-  i = int(col % g.N);
-  j = int((col / g.N) % g.N);
-  p = int(col / (int64_t(g.N) * g.N));
+  const uint32_t n = uint32_t(g.N);
+  uint32_t t = uint32_t(col);
+  i = int(t % n);
+  t /= n;
+  j = int(t % n);
+  p = int(t / n);
 }
 
 template <class T>

@@ -57,13 +57,17 @@ __host__ __device__ __forceinline__ int64_t cell_index(const Shape& g, int p, in
   return ((int64_t(p) * g.Nr + k) * g.N + j) * g.N + i;
 }
 
+// (cell indices are below 2^31, which cfv_grid_create enforces: 32-bit
+// unsigned division, far cheaper on the GPU than 64-bit)
 __host__ __device__ __forceinline__ void decode(const Shape& g, int64_t c, int& p, int& k, int& j, int& i) {
-  i = int(c % g.N);
-  int64_t t = c / g.N;
-  j = int(t % g.N);
-  t /= g.N;
-  k = int(t % g.Nr);
-  p = int(t / g.Nr);
+  const uint32_t n = uint32_t(g.N), nr = uint32_t(g.Nr);
+  uint32_t t = uint32_t(c);
+  i = int(t % n);
+  t /= n;
+  j = int(t % n);
+  t /= n;
+  k = int(t % nr);
+  p = int(t / nr);
 }
 
 struct Nbr {
