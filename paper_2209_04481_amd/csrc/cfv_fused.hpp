@@ -86,7 +86,9 @@ struct FuState {
   int p, j, i;       // the lane's cell (a ring cell in its own panel's coordinates)
   int64_t col;
   int nb[4];         // positions of the angular neighbours (local face order)
-  int32_t ncol[4];   // columns of the angular neighbours (the stencil geometry)
+  int32_t ncol[4];   // columns of the angular neighbours
+  V3 cc;             // the column's centroid sum: a layer's centroid is rs_k cc
+  V3 dn[4], fe[4];   // per unit rs_k: angular neighbours' centroid and face-centroid offsets
   int32_t fcol;      // west / south ring lanes: the column of the inner cell across the shared face
   int back;          // ring: the local face shared with the tile
   int64_t obase;     // the outer slot this lane loads (lanes 0..63): its cell at layer 0, -1: none
@@ -100,23 +102,36 @@ struct FuState {
 
 // Geometry of a cell's gradient stencil at layer k: centroid, offsets of the
 // six neighbours' centroids (mirrored ghost centres on the boundary) and of
-// the six face centroids.  ncol: the columns of its angular neighbours.
-__host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int p, int k, int j, int i,
-                                                          const int32_t ncol[4], V3& xc, V3 dx[6], V3 dxf[6]) {
-  const double rs = 0.125 * (gld(G.r, k) + gld(G.r, k + 1));
-  xc = rs * cg3(G, CG_CSUM, column_of(g, p, j, i));
+// the six face centroids.  The shell is separable: a layer's centroid is
+// rs_k cc (rs_k = (r_k + r_k+1) / 8, cc the column's centroid sum) and an
+// angular face's centroid 2 rs_k b_q, so the angular offsets are rs_k times
+// per-column constants (dn, fe) that the work item loads once.
+__host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int64_t col, int k,
+                                                          V3 cc, const V3 dn[4], const V3 fe[4], V3& xc, V3 dx[6],
+                                                          V3 dxf[6]) {
+  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+  const double rs = 0.125 * (r0 + r1);
+  xc = rs * cc;
 #pragma unroll
-  for (int lf = 0; lf < 6; ++lf) {
-    V3 S, xf;
-    bool own;
-    canon_face(G, g, p, k, j, i, lf, Nbr{}, 0, S, xf, own);
-    dxf[lf] = xf - xc;
-    if (lf == 0)
-      dx[0] = (k > 0 ? cell_centre(G, g, p, k - 1, j, i) : ghost_centre(xc, S, xf)) - xc;
-    else if (lf == 1)
-      dx[1] = (k + 1 < g.Nr ? cell_centre(G, g, p, k + 1, j, i) : ghost_centre(xc, S, xf)) - xc;
-    else
-      dx[lf] = rs * cg3(G, CG_CSUM, ncol[lf - 2]) - xc;
+  for (int q = 0; q < 4; ++q) {
+    dx[2 + q] = rs * dn[q];
+    dxf[2 + q] = rs * fe[q];
+  }
+  const V3 xr = cg3(G, CG_XR, col);
+  const V3 xf0 = r0 * xr, xf1 = r1 * xr;
+  dxf[0] = xf0 - xc;
+  dxf[1] = xf1 - xc;
+  if (k > 0) {
+    dx[0] = (0.125 * (gld(G.r, k - 1) + r0) - rs) * cc;
+  } else {
+    const V3 sr = cg3(G, CG_SR, col);
+    dx[0] = ghost_centre(xc, (r0 * r0) * sr, xf0) - xc;
+  }
+  if (k + 1 < g.Nr) {
+    dx[1] = (0.125 * (r1 + gld(G.r, k + 2)) - rs) * cc;
+  } else {
+    const V3 sr = cg3(G, CG_SR, col);
+    dx[1] = ghost_centre(xc, (r1 * r1) * sr, xf1) - xc;
   }
 }
 
@@ -176,6 +191,11 @@ struct FusedWG {
     }
     // per-item constants the layers reuse (loaded once, not per layer)
     for (int q = 0; q < 4; ++q) st.ncol[q] = gld(G.cn, q * G.ncol + st.col);
+    st.cc = cg3(G, CG_CSUM, st.col);
+    for (int q = 0; q < 4; ++q) {
+      st.dn[q] = cg3(G, CG_CSUM, st.ncol[q]) - st.cc;
+      st.fe[q] = 2.0 * cg3(G, CG_ANG + 6 * q + 3, st.col) - st.cc;
+    }
     st.fcol = st.role == 2 && (st.bi == 0 || st.bj == 0) ? gld(tab + kFTabCol, st.bi == 0 ? t + 1 : t + kFB) : 0;
     // layers kb - 1 and kb of the block into LDS; the next layer prefetched
     T* L = lds_as<T>(lds);
@@ -231,7 +251,7 @@ struct FusedWG {
     const GeomRef& G = a.d.G;
     T* L = lds_as<T>(lds);
     V3 xc, dx[6], dxf[6];
-    stencil_geometry(G, g, st.p, k, st.j, st.i, st.ncol, xc, dx, dxf);
+    stencil_geometry(G, g, st.col, k, st.cc, st.dn, st.fe, xc, dx, dxf);
     const LsqWeights W(dx);
     T P0[9];
     for (int v = 0; v < 9; ++v) P0[v] = L[plane(k) + v * kFL + t];
@@ -252,7 +272,7 @@ struct FusedWG {
     {
       V3 S, xf;
       bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, inner ? 2 : st.back, Nbr{}, 0, S, xf, own);
+      canon_face_col(G, st.col, k, inner ? 2 : st.back, S, xf, own);
       dw = xf - xc;
     }
     T qB[9], qT[9];

