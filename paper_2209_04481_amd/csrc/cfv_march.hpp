@@ -143,7 +143,28 @@ struct GState {
   int64_t col;
   bool act;
   T Pm[9], P0[9], Pp[9];
+  int64_t rc0;  // ring threads: the ring slot's cell at layer 0 (-1: no slot)
 };
+
+// Ring slot r (0..63) of a tile: the out-of-tile neighbour across one edge
+// face of the tile (kind 0: east of row idx's last cell, 1: north of column
+// idx's last cell, 2: west of row idx's first cell, 3: south of column idx's
+// first cell).  Returns false for a slot beyond a partial tile; otherwise the
+// tile cell (ti, tj), the face direction q (0..3: W, E, S, N) and the
+// neighbour's column.
+__host__ __device__ __forceinline__ bool ring_slot(const MarchArgs& a, const TileMap& tm, int r, int& ti, int& tj,
+                                                   int& q, int64_t& ncol) {
+  const Shape& g = a.d.g;
+  const int kind = r >> 4, idx = r & 15;
+  const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
+  const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
+  ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
+  tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
+  q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
+  if (ti > tiL || tj > tjL) return false;
+  ncol = gld(a.d.G.cn, q * a.d.G.ncol + column_of(g, tm.p, tm.j0 + tj, tm.i0 + ti));
+  return true;
+}
 
 template <class T>
 struct GradWG {
@@ -163,6 +184,16 @@ struct GradWG {
     st.j = tm.j0 + tj;
     st.i = tm.i0 + ti;
     st.act = st.j < g.N && st.i < g.N;
+    st.rc0 = -1;
+    if (t >= kNT / 4 && t < kNT / 2) {  // the ring slot's neighbour cell, decoded once per item
+      int ti2, tj2, q;
+      int64_t ncol;
+      if (ring_slot(a, tm, t - kNT / 4, ti2, tj2, q, ncol)) {
+        int np, nj, ni;
+        column_pji(g, ncol, np, nj, ni);
+        st.rc0 = cell_index(g, np, 0, nj, ni);
+      }
+    }
     if (!st.act) return;
     st.col = column_of(g, st.p, st.j, st.i);
     double* cs = lds + 9 * kPlane * kTw;
@@ -216,21 +247,20 @@ struct GradWG {
   // in every wavefront): kind 0 east of row idx's last cell, 1 north of
   // column idx's last cell, 2 west of row idx's first cell, 3 south of
   // column idx's first cell.
-  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, int r, int k, double* lds) {
+  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, const GState<T>& st, int r, int k,
+                                       double* lds) {
     const Shape& g = a.d.g;
+    if (st.rc0 < 0) return;
     const int kind = r >> 4, idx = r & 15;
     const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
     const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
     const int ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
     const int tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
     const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
-    if (ti > tiL || tj > tjL) return;
     int dx, dy;
     dir_offset(q, dx, dy);
-    int np, nj, ni;
-    column_pji(g, gld(a.d.G.cn, q * a.d.G.ncol + column_of(g, tm.p, tm.j0 + tj, tm.i0 + ti)), np, nj, ni);
     T qn[9];
-    load_prims(a, cell_index(g, np, k, nj, ni), qn);
+    load_prims(a, st.rc0 + int64_t(k) * g.N * g.N, qn);
     T* L = lds_as<T>(lds);
     const int pos = plane_pos(ti + dx, tj + dy);
     for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
@@ -329,6 +359,8 @@ struct FState {
   T acc[9];   // residual of layer k so far
   T q3[9], q5[9];
   bool bad;   // a face state of this column met a non-positive density or pressure
+  int64_t rc0;   // ring threads: the ring slot's neighbour cell at layer 0 (-1: no slot)
+  int32_t rcol;  // and its column
 };
 
 template <class T>
@@ -366,22 +398,21 @@ struct FluxWG {
     return (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
   }
 
-  // state of cell (column ncol, layer k) reconstructed at the face centroid xf
-  __host__ __device__ static void remote_state(const MarchArgs& a, int64_t ncol, int k, V3 xf, T q[9]) {
-    const Shape& g = a.d.g;
-    int np, nj, ni;
-    column_pji(g, ncol, np, nj, ni);
-    const int64_t c = cell_index(g, np, k, nj, ni);
+  // state of cell c (column col, layer k) reconstructed at the face centroid xf
+  __host__ __device__ static void remote_state_at(const MarchArgs& a, int64_t c, int32_t col, int k, V3 xf, T q[9]) {
+    const GeomRef& G = a.d.G;
     T P[9], Gr[27];
     load_prims(a, c, P);
     load_grad(a, c, Gr);
-    recon(P, Gr, xf - cell_centre(a.d.G, g, np, k, nj, ni), q);
+    recon(P, Gr, xf - (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * cg3(G, CG_CSUM, col), q);
   }
 
   // ring slot r of layer k: the state of the out-of-tile neighbour across
   // one edge face of the tile, on that face (one wavefront loads all 64)
-  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, int r, int k, double* lds) {
+  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, const FState<T>& st, int r, int k,
+                                       double* lds) {
     const Shape& g = a.d.g;
+    if (st.rc0 < 0) return;
     const int kind = r >> 4, idx = r & 15;
     const int tiL = last_ti(g, tm), tjL = last_tj(g, tm);
     // kind 0: east face of row idx's last cell; 1: north face of column idx's
@@ -390,14 +421,12 @@ struct FluxWG {
     const int ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
     const int tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
     const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
-    if (ti > tiL || tj > tjL) return;
     const int j = tm.j0 + tj, i = tm.i0 + ti;
     V3 S, xf;
     bool own;
     canon_face(a.d.G, g, tm.p, k, j, i, 2 + q, Nbr{}, 0, S, xf, own);
-    const int64_t nbcol = gld(a.d.G.cn, q * a.d.G.ncol + column_of(g, tm.p, j, i));
     T qo[9];
-    remote_state(a, nbcol, k, xf, qo);
+    remote_state_at(a, st.rc0 + int64_t(k) * g.N * g.N, st.rcol, k, xf, qo);
     T* Rg = lds_as<T>(lds) + kRingOff;
     for (int v = 0; v < 9; ++v) Rg[v * kRing + r] = qo[v];
   }
@@ -410,6 +439,18 @@ struct FluxWG {
     st.act = st.j < g.N && st.i < g.N;
     st.bad = false;
     for (int v = 0; v < 9; ++v) st.qtop[v] = T(0.0);
+    st.rc0 = -1;
+    st.rcol = 0;
+    if (t >= kNT / 4 && t < kNT / 4 + kRing) {  // the ring's neighbour cell, decoded once per item
+      int ti, tj, q;
+      int64_t ncol;
+      if (ring_slot(a, tm, t - kNT / 4, ti, tj, q, ncol)) {
+        int np, nj, ni;
+        column_pji(g, ncol, np, nj, ni);
+        st.rc0 = cell_index(g, np, 0, nj, ni);
+        st.rcol = int32_t(ncol);
+      }
+    }
   }
 
   // Layers of the march of a chunk [k0, k1): a warm-up iteration k0 - 1

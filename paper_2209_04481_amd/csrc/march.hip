@@ -34,7 +34,7 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
     if (k < tm.k0) continue;  // warm-up: registers only
-    if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, t - kNT / 4, k, lds);
+    if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
     __syncthreads();
@@ -51,7 +51,7 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
     FluxWG<T>::states(a, tm, st, t, k, lds);
     if (k < tm.k0 || k >= tm.k1) continue;  // warm-up or cool-down: registers only
     // the second wavefront also loads the ring of out-of-tile neighbour states
-    if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, t - kNT / 4, k, lds);
+    if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     FluxWG<T>::faces(a, tm, st, t, k, lds);
     __syncthreads();

@@ -108,7 +108,7 @@ void grad_march(const MarchArgs& a, int kc) {
       }
       for (int t = 0; t < kNT; ++t) {
         GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
-        if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, t - kNT / 4, k, lds.data());
+        if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
       }
       for (int t = 0; t < kNT; ++t) GradWG<T>::template compute<Faces>(a, tm, st[t], t, k, lds.data());
     }
@@ -132,7 +132,7 @@ void flux_march(const MarchArgs& a, int kc) {
       }
       for (int t = 0; t < kNT; ++t) {
         FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
-        if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, t - kNT / 4, k, lds.data());
+        if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
       }
       for (int t = 0; t < kNT; ++t) FluxWG<T>::faces(a, tm, st[t], t, k, lds.data());
       for (int t = 0; t < kNT; ++t) FluxWG<T>::accumulate(a, tm, st[t], t, k, lds.data());
