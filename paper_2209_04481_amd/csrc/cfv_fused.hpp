@@ -89,6 +89,10 @@ struct FuState {
   int32_t ncol[4];   // columns of the angular neighbours
   V3 cc;             // the column's centroid sum: a layer's centroid is rs_k cc
   V3 dn[4], fe[4];   // per unit rs_k: angular neighbours' centroid and face-centroid offsets
+  V3 fa, na;         // area vectors per unit (r_k+1^2 - r_k^2) / 2 of the flux phase's first and second faces
+  bool fown, nown;   // and whether their table orientation points away from the evaluating cell
+  V3 sr, xr;         // radial faces per unit radius: area vector r^2 sr, centroid r xr
+  double om;         // the column's solid-angle factor: volume (r_k+1^3 - r_k^3) om / 3
   int32_t fcol;      // west / south ring lanes: the column of the inner cell across the shared face
   int back;          // ring: the local face shared with the tile
   int64_t obase;     // the outer slot this lane loads (lanes 0..63): its cell at layer 0, -1: none
@@ -106,8 +110,8 @@ struct FuState {
 // rs_k cc (rs_k = (r_k + r_k+1) / 8, cc the column's centroid sum) and an
 // angular face's centroid 2 rs_k b_q, so the angular offsets are rs_k times
 // per-column constants (dn, fe) that the work item loads once.
-__host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int64_t col, int k,
-                                                          V3 cc, const V3 dn[4], const V3 fe[4], V3& xc, V3 dx[6],
+__host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int k, V3 cc, V3 sr,
+                                                          V3 xr, const V3 dn[4], const V3 fe[4], V3& xc, V3 dx[6],
                                                           V3 dxf[6]) {
   const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
   const double rs = 0.125 * (r0 + r1);
@@ -117,20 +121,17 @@ __host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, cons
     dx[2 + q] = rs * dn[q];
     dxf[2 + q] = rs * fe[q];
   }
-  const V3 xr = cg3(G, CG_XR, col);
   const V3 xf0 = r0 * xr, xf1 = r1 * xr;
   dxf[0] = xf0 - xc;
   dxf[1] = xf1 - xc;
   if (k > 0) {
     dx[0] = (0.125 * (gld(G.r, k - 1) + r0) - rs) * cc;
   } else {
-    const V3 sr = cg3(G, CG_SR, col);
     dx[0] = ghost_centre(xc, (r0 * r0) * sr, xf0) - xc;
   }
   if (k + 1 < g.Nr) {
     dx[1] = (0.125 * (r1 + gld(G.r, k + 2)) - rs) * cc;
   } else {
-    const V3 sr = cg3(G, CG_SR, col);
     dx[1] = ghost_centre(xc, (r1 * r1) * sr, xf1) - xc;
   }
 }
@@ -192,28 +193,42 @@ struct FusedWG {
     // per-item constants the layers reuse (loaded once, not per layer)
     for (int q = 0; q < 4; ++q) st.ncol[q] = gld(G.cn, q * G.ncol + st.col);
     st.cc = cg3(G, CG_CSUM, st.col);
+    st.sr = cg3(G, CG_SR, st.col);
+    st.xr = cg3(G, CG_XR, st.col);
+    st.om = gld(G.cg, CG_OMEGA * G.ncol + st.col);
     for (int q = 0; q < 4; ++q) {
       st.dn[q] = cg3(G, CG_CSUM, st.ncol[q]) - st.cc;
       st.fe[q] = 2.0 * cg3(G, CG_ANG + 6 * q + 3, st.col) - st.cc;
     }
     st.fcol = st.role == 2 && (st.bi == 0 || st.bj == 0) ? gld(tab + kFTabCol, st.bi == 0 ? t + 1 : t + kFB) : 0;
-    // layers kb - 1 and kb of the block into LDS; the next layer prefetched
-    T* L = lds_as<T>(lds);
-    for (int kk = kb > 0 ? kb - 1 : kb; kk <= kb; ++kk) {
-      T u[9], q[9];
-      load_cons(a, cell_index(g, st.p, kk, st.j, st.i), u);
-      cons_to_prim(u, q, a.d.pr.gamma);
-      for (int v = 0; v < 9; ++v) L[plane(kk) + v * kFL + t] = q[v];
+    {
+      // the flux phase's faces: an inner lane's east (q = 1) and north (3)
+      // faces, an edge ring lane's inner neighbour's west (0) or south (2)
+      const bool inner = st.role == 1;
+      const int64_t fc = inner ? st.col : int64_t(st.fcol);
+      const int fq = inner ? 1 : st.bi == 0 ? 0 : 2;
+      st.fa = cg3(G, CG_ANG + 6 * fq, fc);
+      st.fown = (gld(G.cn, (4 + fq) * G.ncol + fc) >> 8) != 0;
+      st.na = cg3(G, CG_ANG + 6 * 3, st.col);
+      st.nown = (gld(G.cn, (4 + 3) * G.ncol + st.col) >> 8) != 0;
     }
-    if (kb + 1 < g.Nr) load_cons(a, cell_index(g, st.p, kb + 1, st.j, st.i), st.Un);
+    // the first layer the block publishes (the planes of layers kb - 1 and
+    // kb fill through publish_block steps before layer kb, the same code as
+    // every later layer's, so that every plane holds the same bits whatever
+    // the chunk length); its state loaded ahead
+    (void)lds;
+    load_cons(a, cell_index(g, st.p, kb > 0 ? kb - 1 : 0, st.j, st.i), st.Un);
     if (st.obase >= 0) load_cons(a, st.obase + int64_t(kb) * g.N * g.N, st.On);
   }
 
+  // the publish steps before layer kb: k = first_publish(kb) .. kb - 1
+  __host__ __device__ static int first_publish(int kb) { return (kb > 0 ? kb - 1 : 0) - 1; }
+
   // ------------------------------------------------------------- publish
-  // Step k: the prefetched layer k + 1 of the block and layer k of the outer
-  // slots to LDS (as primitives); then the loads of layers k + 2 and k + 1.
-  __host__ __device__ static void publish(const MarchArgs& a, const FTile& tm, FuState<T>& st, int t, int k,
-                                          double* lds) {
+  // Step k: the prefetched layer k + 1 of the block to LDS (as primitives),
+  // then the load of layer k + 2; and (publish) layer k of the outer slots,
+  // then the load of their layer k + 1.
+  __host__ __device__ static void publish_block(const MarchArgs& a, FuState<T>& st, int t, int k, double* lds) {
     const Shape& g = a.d.g;
     T* L = lds_as<T>(lds);
     if (k + 1 < g.Nr) {
@@ -222,6 +237,13 @@ struct FusedWG {
       for (int v = 0; v < 9; ++v) L[plane(k + 1) + v * kFL + t] = q[v];
       if (k + 2 < g.Nr) load_cons(a, cell_index(g, st.p, k + 2, st.j, st.i), st.Un);
     }
+  }
+
+  __host__ __device__ static void publish(const MarchArgs& a, const FTile& tm, FuState<T>& st, int t, int k,
+                                          double* lds) {
+    const Shape& g = a.d.g;
+    T* L = lds_as<T>(lds);
+    publish_block(a, st, t, k, lds);
     if (st.obase >= 0) {
       T q[9];
       cons_to_prim(st.On, q, a.d.pr.gamma);
@@ -251,7 +273,7 @@ struct FusedWG {
     const GeomRef& G = a.d.G;
     T* L = lds_as<T>(lds);
     V3 xc, dx[6], dxf[6];
-    stencil_geometry(G, g, st.col, k, st.cc, st.dn, st.fe, xc, dx, dxf);
+    stencil_geometry(G, g, k, st.cc, st.sr, st.xr, st.dn, st.fe, xc, dx, dxf);
     const LsqWeights W(dx);
     T P0[9];
     for (int v = 0; v < 9; ++v) P0[v] = L[plane(k) + v * kFL + t];
@@ -286,16 +308,18 @@ struct FusedWG {
       T gx, gy, gz;
       limited_grad(W, dxf, a.d.pr.limiter, P0[v], qn, gx, gy, gz);
       const T p0 = P0[v];
+      // every mode computes and publishes the same states (the warm-up and
+      // cool-down layers' are overwritten before any flux phase reads them):
+      // no branch on the mode here, so one code path, and one rounding,
+      // serves every layer whatever the chunk length
       qB[v] = p0 + (gx * dxf[0].x + gy * dxf[0].y + gz * dxf[0].z);
       qT[v] = p0 + (gx * dxf[1].x + gy * dxf[1].y + gz * dxf[1].z);
-      if (mode == 0) {
-        st.qE[v] = p0 + (gx * dxf[3].x + gy * dxf[3].y + gz * dxf[3].z);
-        st.qN[v] = p0 + (gx * dxf[5].x + gy * dxf[5].y + gz * dxf[5].z);
-        const T qW = p0 + (gx * dw.x + gy * dw.y + gz * dw.z);  // a ring lane's: on the shared face
-        const T qS = p0 + (gx * dxf[4].x + gy * dxf[4].y + gz * dxf[4].z);
-        L[kSW + v * kFL + t] = qW;
-        L[kSS + v * kFL + t] = qS;
-      }
+      st.qE[v] = p0 + (gx * dxf[3].x + gy * dxf[3].y + gz * dxf[3].z);
+      st.qN[v] = p0 + (gx * dxf[5].x + gy * dxf[5].y + gz * dxf[5].z);
+      const T qW = p0 + (gx * dw.x + gy * dw.y + gz * dw.z);  // a ring lane's: on the shared face
+      const T qS = p0 + (gx * dxf[4].x + gy * dxf[4].y + gz * dxf[4].z);
+      L[kSW + v * kFL + t] = qW;
+      L[kSS + v * kFL + t] = qS;
     }
     if (!inner) return;
     if (mode == 1) {  // warm-up: the top state only
@@ -306,9 +330,9 @@ struct FusedWG {
     st.bad = st.bad || !physical(qB);
     // the bottom face closes layer k - 1 (stored when the chunk owns it)
     {
-      V3 S, xf;
-      bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
+      const double r0 = gld(G.r, k);
+      V3 S = (r0 * r0) * st.sr;
+      if (k == 0) S = mk(-S.x, -S.y, -S.z);  // the inner boundary face, outward
       T F[9];
       if (k == 0) {
         rusanov(qB, gin, S, F, a.d.pr);
@@ -338,7 +362,8 @@ struct FusedWG {
       u[0] = P0[0];
       for (int d = 1; d < 4; ++d) u[d] = P0[0] * P0[d];
       for (int v = 4; v < 9; ++v) u[v] = T(0.0);
-      gravity_source(u, xc, cell_volume(G, g, st.p, k, st.j, st.i), a.d.pr.G, src);
+      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      gravity_source(u, xc, (r1 * r1 * r1 - r0 * r0 * r0) * st.om * (1.0 / 3.0), a.d.pr.G, src);
       for (int v = 0; v < 9; ++v) st.acc[v] -= src[v];
     }
     for (int v = 0; v < 9; ++v) st.qtop[v] = qT[v];
@@ -372,9 +397,9 @@ struct FusedWG {
     if (inner || (st.role == 2 && (bi == 0 || bj == 0))) {
       const bool west = bi == 0;
       const int tn = inner ? t + 1 : west ? t + 1 : t + kFB;  // the other side's lane
-      V3 S, xf;
-      bool own;
-      canon_face_col(G, inner ? st.col : int64_t(st.fcol), k, inner ? 3 : west ? 2 : 4, S, xf, own);
+      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      const V3 S = (0.5 * (r1 * r1 - r0 * r0)) * st.fa;
+      const bool own = st.fown;
       T qs[9], qo[9], F[9];
       for (int v = 0; v < 9; ++v) {
         qs[v] = inner ? st.qE[v] : L[(west ? kSW : kSS) + v * kFL + tn];
@@ -392,9 +417,9 @@ struct FusedWG {
     }
     // second face: an inner lane's north face
     if (inner) {
-      V3 S, xf;
-      bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 5, Nbr{}, 0, S, xf, own);
+      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      const V3 S = (0.5 * (r1 * r1 - r0 * r0)) * st.na;
+      const bool own = st.nown;
       const bool ring_n = bj == tm.wj;  // the north neighbour is a ring cell: its shared-face state
       T qo[9], F[9];
       for (int v = 0; v < 9; ++v) qo[v] = L[(ring_n ? kSW : kSS) + v * kFL + t + kFB];

@@ -22,6 +22,7 @@ __device__ __forceinline__ void fused_march_tile(const MarchArgs& a, const FTile
   const int ke = tm.k1 < g.Nr ? tm.k1 : tm.k1 - 1;
   FuState<T> st;
   FusedWG<T>::init(a, tm, st, t, kb, lds);
+  for (int k = FusedWG<T>::first_publish(kb); k < kb; ++k) FusedWG<T>::publish_block(a, st, t, k, lds);
   for (int k = kb; k <= ke; ++k) {
     const int mode = k < tm.k0 ? 1 : k >= tm.k1 ? 2 : 0;
     FusedWG<T>::publish(a, tm, st, t, k, lds);

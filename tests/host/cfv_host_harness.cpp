@@ -77,6 +77,8 @@ void fused_residual(const MarchArgs& a, int kc) {
     const int kb = tm.k0 > 0 ? tm.k0 - 1 : 0;
     const int ke = tm.k1 < g.Nr ? tm.k1 : tm.k1 - 1;
     for (int t = 0; t < kFL; ++t) WG::init(a, tm, st[t], t, kb, lds.data());
+    for (int k = WG::first_publish(kb); k < kb; ++k)
+      for (int t = 0; t < kFL; ++t) WG::publish_block(a, st[t], t, k, lds.data());
     for (int k = kb; k <= ke; ++k) {
       const int mode = k < tm.k0 ? 1 : k >= tm.k1 ? 2 : 0;
       for (int t = 0; t < kFL; ++t) WG::publish(a, tm, st[t], t, k, lds.data());
