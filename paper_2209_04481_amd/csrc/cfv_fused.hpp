@@ -89,6 +89,7 @@ struct FuState {
   int32_t ncol[4];   // columns of the angular neighbours
   V3 cc;             // the column's centroid sum: a layer's centroid is rs_k cc
   V3 dn[4], fe[4];   // per unit rs_k: angular neighbours' centroid and face-centroid offsets
+  V3 fw;             // per unit rs_k: the centroid offset of an inner lane's west face, a ring lane's shared face
   V3 fa, na;         // area vectors per unit (r_k+1^2 - r_k^2) / 2 of the flux phase's first and second faces
   bool fown, nown;   // and whether their table orientation points away from the evaluating cell
   V3 sr, xr;         // radial faces per unit radius: area vector r^2 sr, centroid r xr
@@ -193,6 +194,10 @@ struct FusedWG {
     // per-item constants the layers reuse (loaded once, not per layer)
     for (int q = 0; q < 4; ++q) st.ncol[q] = gld(G.cn, q * G.ncol + st.col);
     st.cc = cg3(G, CG_CSUM, st.col);
+    {
+      const int bq = (st.role == 1 ? 2 : st.back) - 2;  // the face, 0..3 (a lane without a cell: west)
+      st.fw = 2.0 * cg3(G, CG_ANG + 6 * (bq >= 0 && bq < 4 ? bq : 0) + 3, st.col) - st.cc;
+    }
     st.sr = cg3(G, CG_SR, st.col);
     st.xr = cg3(G, CG_XR, st.col);
     st.om = gld(G.cg, CG_OMEGA * G.ncol + st.col);
@@ -288,15 +293,9 @@ struct FusedWG {
     }
     const bool inner = st.role == 1;
     // the west face of an inner lane, the shared face of a ring lane: its
-    // centroid offset from the face tables (indexing dxf by a run-time value
-    // would put the array in scratch memory)
-    V3 dw;
-    {
-      V3 S, xf;
-      bool own;
-      canon_face_col(G, st.col, k, inner ? 2 : st.back, S, xf, own);
-      dw = xf - xc;
-    }
+    // centroid offset, rs_k times the item's constant (indexing dxf by a
+    // run-time face would put the array in scratch memory)
+    const V3 dw = (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * st.fw;
     T qB[9], qT[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
