@@ -30,8 +30,8 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
   const double bn2 = bn * bn * irho;
   const double s = a2 + b2;
   const double disc = s * s - 4.0 * a2 * bn2;
-  const double sd = disc > 0.0 ? ::sqrt(disc) : 0.0;
-  const double cf = ::sqrt(0.5 * (s + sd));
+  const double sd = disc > 0.0 ? sqrt_nonneg(disc) : 0.0;
+  const double cf = sqrt_nonneg(0.5 * (s + sd));
 
   // adjoints of the intermediates from the flux components
   double rvnb = Fb[0] + Fb[1] * vx + Fb[2] * vy + Fb[3] * vz;

@@ -47,14 +47,38 @@ __host__ __device__ __forceinline__ Dual operator/(double a, Dual b) {
 }
 __host__ __device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 __host__ __device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+// Square root on the GPU: the hardware reciprocal square root refined by
+// Goldschmidt's iteration (one coupled step for sqrt(x) and 1/(2 sqrt(x)),
+// then two Newton corrections of the root), the sequence the compiler
+// expands sqrt into, without its rescaling of inputs below 2^-767 and its
+// special-value fix-ups: the same bits for every other finite positive x.
+// Here x = 0 gives 0 and negative or non-finite x NaN (no state of the
+// method takes the roots of such tiny values).  On the host, sqrt.
+__host__ __device__ __forceinline__ double sqrt_nonneg(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x == 0.0 ? 0.0 : g;
+#else
+  return ::sqrt(x);
+#endif
+}
+
 __host__ __device__ __forceinline__ Dual sqrt(Dual a) {
-  double s = ::sqrt(a.v);
+  double s = sqrt_nonneg(a.v);
   return Dual(s, a.d / (2.0 * s));
 }
 
 __host__ __device__ __forceinline__ double val(double a) { return a; }
 __host__ __device__ __forceinline__ double val(Dual a) { return a.v; }
-__host__ __device__ __forceinline__ double dsqrt(double a) { return ::sqrt(a); }
+__host__ __device__ __forceinline__ double dsqrt(double a) { return sqrt_nonneg(a); }
 __host__ __device__ __forceinline__ Dual dsqrt(Dual a) { return sqrt(a); }
 template <class T> __host__ __device__ __forceinline__ T tabs(T a) { return val(a) < 0.0 ? -a : a; }
 // min/max that keep the first argument on ties; the pick follows the values
@@ -101,7 +125,7 @@ __host__ __device__ __forceinline__ double dot3(V3 a, V3 b) { return a.x * b.x +
 __host__ __device__ __forceinline__ V3 cross3(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-__host__ __device__ __forceinline__ double norm3(V3 a) { return ::sqrt(dot3(a, a)); }
+__host__ __device__ __forceinline__ double norm3(V3 a) { return sqrt_nonneg(dot3(a, a)); }
 
 // --------------------------------------------------------------- parameters
 struct Params {
