@@ -425,6 +425,17 @@ cfv_status cfv_timing_enable(cfv_ctx* ctx, int32_t on);
  * same for every kc: each face flux is evaluated once from the same states,
  * and each cell sums its faces in a fixed order. */
 cfv_status cfv_set_chunk_layers(cfv_ctx* ctx, int32_t kc);
+/* Preconditioner of the context's GMRES solves (cfv_solve, and through it
+ * cfv_be_step and cfv_steady): kind 0 none (the default; the step of
+ * Section 2.1 as read here), 1 Jacobi: right preconditioning by the solve's
+ * own diagonal, (diag + J) D^-1 y = rhs with x = D^-1 y and D = diag per cell
+ * (for the backward-Euler step V/dt, proportional under the local time step
+ * to the diagonal of V/dt plus the first-order flux Jacobian).  The history
+ * still reports |rhs - (diag + J) x| / |rhs|.  With kind 1 every diag entry
+ * must be positive (a zero gives non-finite iterates, which the solve
+ * reports as CFV_ERR_NONPHYSICAL).  The batched ensemble step is not
+ * preconditioned. */
+cfv_status cfv_set_preconditioner(cfv_ctx* ctx, int32_t kind);
 cfv_status cfv_timing_read(cfv_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n);
 
 #ifdef __cplusplus

@@ -73,11 +73,18 @@ def eq2(a, b):
     return torch.log10(torch.sqrt((d * d).sum(-1)))
 
 
-def gmres(matvec, rhs, m: int = 30, tol: float = 0.0):
+def gmres(matvec, rhs, m: int = 30, tol: float = 0.0, precond=None):
     """Unrestarted GMRES(m) from x0 = 0 with modified Gram-Schmidt.
+
+    With precond (a function applying M^-1), right preconditioning: GMRES
+    runs on the operator A M^-1 and returns x = M^-1 y; the residual of
+    A x = rhs is the same as that of A M^-1 y = rhs.
 
     Returns x and the list of relative residual norms |r_j| / |rhs| after
     each iteration j = 1..m (from the Givens-rotated least-squares system)."""
+    if precond is not None:
+        y, hist = gmres(lambda v: matvec(precond(v)), rhs, m, tol)
+        return precond(y), hist
     beta = torch.linalg.norm(rhs)
     Vs = [rhs / beta]
     H = torch.zeros(m + 1, m, dtype=DT)
@@ -119,8 +126,9 @@ def gmres(matvec, rhs, m: int = 30, tol: float = 0.0):
     return x, hist
 
 
-def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None):
-    """One backward-Euler pseudo-time step: (D + J) x = -R, U <- U + x."""
+def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None, jacobi: bool = False):
+    """One backward-Euler pseudo-time step: (D + J) x = -R, U <- U + x;
+    jacobi: GMRES right-preconditioned by D (one value per cell)."""
     R = mhd.residual(grid, U, br, prm)
     if diag is None:
         diag = local_dt_diag(grid, U, br, prm, cfl)
@@ -129,7 +137,7 @@ def be_step(grid: Grid, U, br, prm, cfl: float = 1e3, m: int = 30, diag=None):
         Jx, _ = jvp(grid, U, br, prm, x)
         return diag[None, :] * x + Jx
 
-    x, hist = gmres(A, -R, m)
+    x, hist = gmres(A, -R, m, precond=(lambda v: v / diag[None, :]) if jacobi else None)
     return U + x, hist, R
 
 

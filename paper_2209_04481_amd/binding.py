@@ -107,6 +107,7 @@ def lib():
         "cfv_ensemble_timing_read": ([P, c_int32, P, P, P, P], c_int32),
         "cfv_timing_enable": ([P, c_int32], c_int32),
         "cfv_set_chunk_layers": ([P, c_int32], c_int32),
+        "cfv_set_preconditioner": ([P, c_int32], c_int32),
         "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
     for name, (args, res) in sig.items():
@@ -406,6 +407,11 @@ class Context:
 
     def timing_enable(self, on=True):
         check(lib().cfv_timing_enable(self._h, int(bool(on))))
+
+    def set_preconditioner(self, kind: int):
+        """GMRES preconditioner of this context's solves: 0 none, 1 Jacobi
+        (right preconditioning by the solve's diagonal)."""
+        check(lib().cfv_set_preconditioner(self._h, int(kind)))
 
     def set_chunk_layers(self, kc: int):
         """Layers per work item of this context's marches, 0 = balanced per

@@ -39,6 +39,7 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
 int64_t vjp_workspace_doubles(const Shape& g);
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
 hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s);
+hipError_t launch_div_diag(int64_t nc, const double* diag, const double* x, double* y, hipStream_t s);
 hipError_t launch_lincomb(int64_t n, int k, const double* y, const double* V, double* x, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s);
 hipError_t launch_axpy_dot(int64_t n, const double* coef, const double* x, double* w, const double* y, double* out,
@@ -125,6 +126,7 @@ struct cfv_ctx {
   double* st_m = nullptr;     // 9 device scalars: the monitor
   unsigned* dflag = nullptr;  // non-physical state word set by the kernels
   int32_t* dftab = nullptr;   // per-tile stencil tables of the fused march
+  int precond = 0;            // GMRES preconditioner: 0 none, 1 Jacobi (right, by the diagonal)
   int chunk = 0;              // layers per work item of the marches (0: balanced_chunk per march)
   int fused_chunk = cfv::kKC;  // the balanced choices for this grid and device
   int dual_chunk = cfv::kKC;
@@ -550,6 +552,10 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
     bool stop = false;
     for (int j = 0; j < m; ++j) {
       double* vj = V + size_t(j) * n;
+      if (c->precond == 1) {  // right preconditioning: w = A D^-1 v_j (r is free inside the cycle)
+        CFV_HIP(cfv::launch_div_diag(c->grid->g.ncells, diag, vj, r, s));
+        vj = r;
+      }
       if (cfv_status st = apply_operator(c, U, diag, transpose, vj, w, s)) return st;
       // modified Gram-Schmidt, coefficients on the device: h_0 = <w, V_0>, then
       // each update w -= h_i V_i is fused with the next projection
@@ -596,7 +602,12 @@ cfv_status cfv_solve(cfv_ctx* c, const double* U, const double* diag, const doub
     }
     CFV_HIP(hipMemcpyAsync(yd, y.data(), size_t(kdone) * sizeof(double), hipMemcpyHostToDevice, s));
     CFV_HIP(cfv::launch_lincomb(n, kdone, yd, V, w, s));
-    CFV_HIP(cfv::launch_axpby(n, 1.0, w, 1.0, x, s));
+    if (c->precond == 1) {  // x += D^-1 V y
+      CFV_HIP(cfv::launch_div_diag(c->grid->g.ncells, diag, w, r, s));
+      CFV_HIP(cfv::launch_axpby(n, 1.0, r, 1.0, x, s));
+    } else {
+      CFV_HIP(cfv::launch_axpby(n, 1.0, w, 1.0, x, s));
+    }
     CFV_HIP(hipStreamSynchronize(s));
     if (stop) break;
   }
@@ -1340,6 +1351,13 @@ cfv_status cfv_timing_enable(cfv_ctx* c, int32_t on) {
 cfv_status cfv_timing_read(cfv_ctx* c, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n) {
   if (cfv_status st = check_ctx(c)) return st;
   return timing_read(c->timer, max, names, total_ms, count, n);
+}
+
+cfv_status cfv_set_preconditioner(cfv_ctx* c, int32_t kind) {
+  if (cfv_status st = check_ctx(c)) return st;
+  if (kind != 0 && kind != 1) return fail(CFV_ERR_ARG, "preconditioner: 0 (none) or 1 (Jacobi)");
+  c->precond = kind;
+  return CFV_OK;
 }
 
 cfv_status cfv_set_chunk_layers(cfv_ctx* c, int32_t kc) {

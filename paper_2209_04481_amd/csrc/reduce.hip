@@ -216,6 +216,14 @@ __global__ __launch_bounds__(kRBlock) void add_diag_kernel(int64_t nc, const dou
     w[e] += diag[e % nc] * x[e];
 }
 
+// y[v*nc + c] = x[v*nc + c] / diag[c] (the Jacobi preconditioner's inverse)
+__global__ __launch_bounds__(kRBlock) void div_diag_kernel(int64_t nc, const double* __restrict__ diag,
+                                                           const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t n = 9 * nc;
+  for (int64_t e = int64_t(blockIdx.x) * kRBlock + threadIdx.x; e < n; e += int64_t(gridDim.x) * kRBlock)
+    y[e] = x[e] / diag[e % nc];
+}
+
 // x = sum_i y[i] V_i over k vectors of length n (coefficients on the device)
 __global__ __launch_bounds__(kRBlock) void lincomb_kernel(int64_t n, int k, const double* __restrict__ y,
                                                           const double* __restrict__ V, double* __restrict__ x) {
@@ -240,6 +248,11 @@ hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double*
 
 hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s) {
   hipLaunchKernelGGL(add_diag_kernel, dim3(stream_blocks(9 * nc)), dim3(kRBlock), 0, s, nc, diag, x, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_diag(int64_t nc, const double* diag, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(div_diag_kernel, dim3(stream_blocks(9 * nc)), dim3(kRBlock), 0, s, nc, diag, x, y);
   return hipGetLastError();
 }
 

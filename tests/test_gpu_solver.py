@@ -45,6 +45,50 @@ def test_be_step_gmres30_matches_oracle_tiny():
     assert float(rel_err_per_var((Un - U).cpu(), Uo - torch.from_numpy(inst.U)).max()) <= 1e-8
 
 
+@pytest.mark.parametrize("cfl", [1e3, 10.0])
+def test_be_step_jacobi_preconditioned_matches_oracle_tiny(cfl):
+    """GMRES(30) right-preconditioned by the step's diagonal V/dt: history and
+    new state agree with the oracle's preconditioned step."""
+    print(f"case: BE step tiny, Jacobi, CFL {cfl}", flush=True)
+    inst = ci.workload("tiny")
+    ctx = context(inst)
+    ctx.set_preconditioner(1)
+    U = torch.from_numpy(inst.U).cuda()
+    Un, hist = ctx.be_step(U, cfl=cfl, m=30)
+    og = OGrid(inst.N, inst.Nr, inst.r_nodes)
+    Uo, hist_o, _ = solve.be_step(og, torch.from_numpy(inst.U), torch.from_numpy(inst.br), mhd.Params(), cfl, 30,
+                                  jacobi=True)
+    h, ho = np.asarray(hist), np.asarray(hist_o)
+    print("history", h[[0, 9, len(h) - 1]], "oracle", ho[[0, 9, len(ho) - 1]])
+    assert len(h) == len(ho)
+    assert np.all(np.abs(h - ho) <= 1e-9 * ho + 1e-13)
+    assert float(rel_err_per_var((Un - U).cpu(), Uo - torch.from_numpy(inst.U)).max()) <= 1e-8
+    with pytest.raises(Exception):
+        ctx.set_preconditioner(2)
+
+
+def test_be_step_medium_jacobi_converges_further_and_reports_the_true_residual():
+    """Medium grid, CFL 1e3, GMRES(30): the Jacobi-preconditioned step ends
+    below the unpreconditioned one, and its last history entry is the true
+    relative residual |(D + J) x + R| / |R|."""
+    print("case: BE step medium, Jacobi", flush=True)
+    inst = ci.workload("medium")
+    ctx = context(inst)
+    U = torch.from_numpy(inst.U).cuda()
+    _, hist0 = ctx.be_step(U, cfl=1e3, m=30)
+    ctx.set_preconditioner(1)
+    Un, hist = ctx.be_step(U, cfl=1e3, m=30)
+    torch.cuda.synchronize()
+    print("plain", hist0[[9, 29]], "jacobi", hist[[9, 29]])
+    assert hist[-1] < hist0[-1]
+    x = Un - U
+    R = ctx.residual(U)
+    D = ctx.local_dt(U, 1e3)
+    Ax = ctx.jvp(U, x.contiguous()) + D[None, :] * x
+    true_rel = float((Ax + R).norm() / R.norm())
+    assert abs(true_rel - hist[-1]) <= 1e-6 * hist[-1]
+
+
 def test_transpose_solve_is_tight_and_consistent():
     print("case: transpose solve", flush=True)
     inst = ci.make_instance(6, 10, "log", lmax=4, seed=8)

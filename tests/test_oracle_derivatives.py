@@ -98,6 +98,30 @@ def test_gmres_minimises_over_krylov_space_and_solves_exactly():
     assert all(hist[i + 1] <= hist[i] + 1e-15 for i in range(len(hist) - 1))
 
 
+def test_right_preconditioned_gmres_minimises_over_the_preconditioned_space():
+    """GMRES on A M^-1 with x = M^-1 y: exact at m = n, its history the
+    minimum of |b - A x| over x in M^-1 K_j(A M^-1, b) (explicit lstsq),
+    and one iteration when M = A is diagonal."""
+    rng = np.random.default_rng(2)
+    n = 12
+    A = torch.tensor(rng.standard_normal((n, n)) + 4 * np.eye(n))
+    d = torch.tensor(rng.uniform(0.5, 20.0, n))
+    b = torch.tensor(rng.standard_normal(n))
+    Minv = lambda v: v / d
+    x, hist = solve.gmres(lambda y: A @ y, b, m=n, precond=Minv)
+    assert torch.allclose(x, torch.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
+    AM = A / d[None, :]
+    K = [b]
+    for j in range(1, 6):
+        Q, _ = torch.linalg.qr(torch.stack(K, 1))
+        y = torch.linalg.lstsq(AM @ Q, b).solution
+        assert abs(float((b - A @ (Minv(Q @ y))).norm() / b.norm()) - hist[j - 1]) < 1e-12
+        K.append(AM @ K[-1])
+    D = torch.diag(d)
+    x1, h1 = solve.gmres(lambda y: D @ y, b, m=5, precond=Minv)
+    assert h1[0] < 1e-14 and torch.allclose(x1, b / d, rtol=1e-14)
+
+
 def test_eq2_monitor():
     a = torch.tensor([[1.0, 2.0, 3.0], [0.0, 0.0, 1.0]], dtype=DT)
     b = torch.tensor([[1.0, 2.0, 2.0], [3.0, 4.0, 1.0]], dtype=DT)
