@@ -144,8 +144,8 @@ struct GState {
   bool act;
   T Pm[9], P0[9], Pp[9];
   int64_t rc0;  // ring threads: the ring slot's cell at layer 0 (-1: no slot)
-  // tangent pass: the column's geometry per item (centroid sum, radial face
-  // centroid per unit radius, angular face-centroid offsets per unit rs_k)
+  // the column's geometry per item (centroid sum, radial face centroid per
+  // unit radius, angular face-centroid offsets per unit rs_k)
   V3 cc, xr, fe[4];
 };
 
@@ -172,10 +172,6 @@ __host__ __device__ __forceinline__ bool ring_slot(const MarchArgs& a, const Til
 template <class T>
 struct GradWG {
   static constexpr int kTw = int(sizeof(T) / sizeof(double));
-  // The tangent pass (one wavefront per SIMD, registers to spare) keeps its
-  // column's geometry in registers for the whole item; the plain pass (two
-  // per SIMD) reloads it every layer.
-  static constexpr bool kGeo = kTw > 1;
   // primitives plane (9 T per position), then the column centroid sums (3)
   static constexpr int kLds = 9 * kPlane * kTw + 3 * kPlane;
 
@@ -216,11 +212,9 @@ struct GradWG {
       cs[pos] = cn.x; cs[kPlane + pos] = cn.y; cs[2 * kPlane + pos] = cn.z;
     }
     for (int v = 0; v < 9; ++v) st.Pm[v] = st.P0[v] = st.Pp[v] = T(0.0);
-    if constexpr (kGeo) {
-      st.cc = c0;
-      st.xr = cg3(G, CG_XR, st.col);
-      for (int q = 0; q < 4; ++q) st.fe[q] = 2.0 * cg3(G, CG_ANG + 6 * q + 3, st.col) - c0;
-    }
+    st.cc = c0;
+    st.xr = cg3(G, CG_XR, st.col);
+    for (int q = 0; q < 4; ++q) st.fe[q] = 2.0 * cg3(G, CG_ANG + 6 * q + 3, st.col) - c0;
   }
 
   // First layer of the march of a chunk [k0, k1): the layers k0 - 1 and k0
@@ -292,11 +286,11 @@ struct GradWG {
     const int ti = t % kTI, tj = t / kTI;
     const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
     const double rs = 0.125 * (r0 + r1);
-    const V3 xc = rs * (kGeo ? st.cc : cg3(G, CG_CSUM, st.col));
+    const V3 xc = rs * st.cc;
     // geometry: neighbour offsets and face-centroid offsets
     V3 dx[6], dxf[6];
     int pos[4];
-    if constexpr (kGeo) {
+    {
       // a layer's centroid is rs_k cc, an angular face's centroid 2 rs_k b_q,
       // a radial face's r xr: offsets from the item's constants
       const V3 xf0 = r0 * st.xr, xf1 = r1 * st.xr;
@@ -323,25 +317,6 @@ struct GradWG {
         dxf[lf] = rs * st.fe[lf - 2];
         dx[lf] = rs * (mk(cs[q], cs[kPlane + q], cs[2 * kPlane + q]) - st.cc);
       }
-    } else {
-#pragma unroll
-    for (int lf = 0; lf < 6; ++lf) {
-      V3 S, xf;
-      bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, lf, Nbr{}, 0, S, xf, own);
-      dxf[lf] = xf - xc;
-      if (lf == 0) {
-        dx[0] = (k > 0 ? cell_centre(G, g, st.p, k - 1, st.j, st.i) : ghost_centre(xc, S, xf)) - xc;
-      } else if (lf == 1) {
-        dx[1] = (k + 1 < g.Nr ? cell_centre(G, g, st.p, k + 1, st.j, st.i) : ghost_centre(xc, S, xf)) - xc;
-      } else {
-        int ddx, ddy;
-        dir_offset(lf - 2, ddx, ddy);
-        pos[lf - 2] = plane_pos(ti + ddx, tj + ddy);
-        const int q = pos[lf - 2];
-        dx[lf] = rs * mk(cs[q], cs[kPlane + q], cs[2 * kPlane + q]) - xc;
-      }
-    }
     }
     const LsqWeights W(dx);
     // ghost states on the boundary layers
