@@ -339,6 +339,10 @@ void cfv_ensemble_destroy(cfv_ensemble* e);
 /* Change the schedule (drops a captured graph; a new chunk length rebuilds
  * the item lists, synchronously). */
 cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t);
+/* GMRES preconditioner of the batched backward-Euler step, as
+ * cfv_set_preconditioner (0 none, 1 Jacobi by V/dt); it takes effect at the
+ * next cfv_ensemble_bind_be_step (a bound step must be bound again). */
+cfv_status cfv_ensemble_set_preconditioner(cfv_ensemble* e, int32_t kind);
 /* Number of work items and the workgroups a launch uses (host outputs). */
 cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks);
 /* Bind the per-instance device buffers (host arrays of n device pointers,
@@ -433,8 +437,8 @@ cfv_status cfv_set_chunk_layers(cfv_ctx* ctx, int32_t kc);
  * to the diagonal of V/dt plus the first-order flux Jacobian).  The history
  * still reports |rhs - (diag + J) x| / |rhs|.  With kind 1 every diag entry
  * must be positive (a zero gives non-finite iterates, which the solve
- * reports as CFV_ERR_NONPHYSICAL).  The batched ensemble step is not
- * preconditioned. */
+ * reports as CFV_ERR_NONPHYSICAL).  The batched ensemble step takes its own
+ * setting (cfv_ensemble_set_preconditioner). */
 cfv_status cfv_set_preconditioner(cfv_ctx* ctx, int32_t kind);
 cfv_status cfv_timing_read(cfv_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* count, int32_t* n);
 

@@ -108,6 +108,7 @@ def lib():
         "cfv_timing_enable": ([P, c_int32], c_int32),
         "cfv_set_chunk_layers": ([P, c_int32], c_int32),
         "cfv_set_preconditioner": ([P, c_int32], c_int32),
+        "cfv_ensemble_set_preconditioner": ([P, c_int32], c_int32),
         "cfv_timing_read": ([P, c_int32, P, P, P, P], c_int32),
     }
     for name, (args, res) in sig.items():
@@ -465,6 +466,11 @@ class Ensemble:
         if h is not None and _lib is not None:
             _lib.cfv_ensemble_destroy(h)
             self._h = None
+
+    def set_preconditioner(self, kind: int):
+        """GMRES preconditioner of the batched step (0 none, 1 Jacobi); takes
+        effect at the next bind_be_step."""
+        check(lib().cfv_ensemble_set_preconditioner(self._h, int(kind)))
 
     def set_tuning(self, tuning: Tuning):
         t = tuning.c()

@@ -881,6 +881,7 @@ struct cfv_ensemble {
   cfv::StepLaunch step;
   double* mon = nullptr;                 // 9 n device scalars: monitors of the batched march
   unsigned* dflags = nullptr;            // n non-physical state words, one per instance
+  int precond = 0;                       // the step's GMRES preconditioner (at the next step binding)
   // the fused residual march's items (its own tiles, chunks of kc layers)
   int kc = cfv::kKC;                     // layers per item of both marches
   std::vector<int64_t> foff;             // n + 1 prefix sums of fused items
@@ -1079,6 +1080,17 @@ cfv_status cfv_ensemble_set_tuning(cfv_ensemble* e, const cfv_tuning* t) {
   return build_items(e);
 }
 
+cfv_status cfv_ensemble_set_preconditioner(cfv_ensemble* e, int32_t kind) {
+  if (!e) return fail(CFV_ERR_ARG, "null ensemble");
+  if (kind != 0 && kind != 1) return fail(CFV_ERR_ARG, "preconditioner: 0 (none) or 1 (Jacobi)");
+  e->precond = kind;
+  if (e->mode == 1) {  // a bound step keeps its tables: bind it again
+    drop_graph(e);
+    e->bound = false;
+  }
+  return CFV_OK;
+}
+
 cfv_status cfv_ensemble_items(const cfv_ensemble* e, int64_t* total, int32_t* blocks) {
   if (!e) return fail(CFV_ERR_ARG, "null ensemble");
   if (total) *total = e->total;
@@ -1126,7 +1138,7 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
   size_t need = 0;
   for (size_t q = 0; q < n; ++q) {
     const size_t nc = size_t(e->ctx[q]->grid->g.ncells);
-    need += size_t(m + 2) * 9 * nc + nc + size_t(Y.size);
+    need += size_t(m + 3) * 9 * nc + nc + size_t(Y.size);
   }
   drop_graph(e);
   cfv_status st;
@@ -1154,6 +1166,7 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
   L.m = m;
   L.blocks = kStepBlocks;
   L.cfl = cfl;
+  L.precond = e->precond;
   L.sv = e->step_sv;
   L.part = e->step_part;
   L.hist = hist;
@@ -1173,6 +1186,8 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
     p += size_t(m + 1) * n9;
     v.w = p;
     p += n9;
+    v.z = p;
+    p += n9;
     double* diag = p;
     p += nc;
     v.diag = diag;
@@ -1184,7 +1199,8 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
     d.flag = e->dflags + q;
     args[q] = cfv::MarchArgs{d, U[q], nullptr, nullptr, c->W, nullptr, U_new[q], nullptr};
     for (int j = 0; j < m; ++j)
-      args[size_t(1 + j) * n + q] = cfv::MarchArgs{d, U[q], v.V + size_t(j) * n9, nullptr, c->W, c->Wd, nullptr, v.w};
+      args[size_t(1 + j) * n + q] =
+          cfv::MarchArgs{d, U[q], e->precond ? v.z : v.V + size_t(j) * n9, nullptr, c->W, c->Wd, nullptr, v.w};
     L.dev.push_back(d);
     L.Uh.push_back(U[q]);
     L.diagh.push_back(diag);

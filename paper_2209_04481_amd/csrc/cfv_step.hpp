@@ -14,6 +14,7 @@ struct StepVec {
   double* Unew;        // output; holds -R during the solve
   double* V;           // (m + 1) Krylov vectors of 9 nc
   double* w;           // work vector, 9 nc
+  double* z;           // preconditioned Krylov vector D^-1 V_j (Jacobi), 9 nc
   const double* diag;  // V/dt, nc
   double* sm;          // small per-instance scalars (StepLayout)
   int64_t nc;
@@ -39,12 +40,13 @@ struct StepLayout {
 
 struct StepLaunch {
   int n, m, blocks;                  // instances, Krylov size, vector blocks per instance
+  int precond = 0;                   // 1: GMRES right-preconditioned by the diagonal (Jacobi)
   double cfl;
   const StepVec* sv;                 // device, n
   double* part;                      // device, n x blocks
   double* hist;                      // device, n x m, nullable
   EnsembleLaunch res;                // residual descriptors (output in Unew)
-  std::vector<EnsembleLaunch> jvp;   // m JVP descriptor tables (v = V_j, Jv = w)
+  std::vector<EnsembleLaunch> jvp;   // m JVP descriptor tables (v = V_j, or z with precond; Jv = w)
   std::vector<DevGrid> dev;          // host copies for the per-instance V/dt launches
   std::vector<const double*> Uh;
   std::vector<double*> diagh, Wh;

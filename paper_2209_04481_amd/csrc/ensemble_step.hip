@@ -118,11 +118,21 @@ __global__ __launch_bounds__(kSB) void step_scale_kernel(const StepVec* __restri
   for (; e < n9; e += S) gst(dst, e, den != 0.0 ? gld(src, e) / den : 0.0);
 }
 
-// w += diag o V_j (the V/dt part of the operator)
-__global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __restrict__ sv, int j) {
+// z = V_j / diag (the Jacobi-preconditioned vector the JVP then reads)
+__global__ __launch_bounds__(kSB) void step_precond_kernel(const StepVec* __restrict__ sv, int j) {
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const double* x = v.V + int64_t(j) * n9;
+  const int64_t S = int64_t(gridDim.x) * kSB;
+  for (int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x; e < n9; e += S)
+    gst(v.z, e, gld(x, e) / gld(v.diag, e % v.nc));
+}
+
+// w += diag o x with x = V_j, or z (the V/dt part of the operator)
+__global__ __launch_bounds__(kSB) void step_add_diag_kernel(const StepVec* __restrict__ sv, int j, int use_z) {
+  const StepVec& v = sv[blockIdx.y];
+  const int64_t n9 = 9 * v.nc;
+  const double* x = use_z ? v.z : v.V + int64_t(j) * n9;
   const int64_t S = int64_t(gridDim.x) * kSB;
   int64_t e = int64_t(blockIdx.x) * kSB + threadIdx.x;
   for (; e + 3 * S < n9; e += 4 * S) {  // four entries per pass, loads before stores
@@ -229,8 +239,8 @@ __global__ void step_backsub_kernel(const StepVec* __restrict__ sv, int n, int m
   }
 }
 
-// Unew = U + sum_i y_i V_i
-__global__ __launch_bounds__(kSB) void step_update_kernel(const StepVec* __restrict__ sv, int m) {
+// Unew = U + sum_i y_i V_i (divided by diag with the Jacobi preconditioner)
+__global__ __launch_bounds__(kSB) void step_update_kernel(const StepVec* __restrict__ sv, int m, int precond) {
   const StepVec& v = sv[blockIdx.y];
   const int64_t n9 = 9 * v.nc;
   const StepLayout L(m);
@@ -238,6 +248,7 @@ __global__ __launch_bounds__(kSB) void step_update_kernel(const StepVec* __restr
   STEP_LOOP(n9) {
     double s = 0.0;
     for (int i = 0; i < k; ++i) s += gld(v.sm, L.y + i) * gld(v.V, int64_t(i) * n9 + e);
+    if (precond) s = s / gld(v.diag, e % v.nc);
     gst(v.Unew, e, gld(v.U, e) + s);
   }
 }
@@ -260,12 +271,13 @@ hipError_t launch_ensemble_step(const StepLaunch& L, hipStream_t s, KernelTimer*
   hipLaunchKernelGGL(step_init_kernel, dim3(tgrid), dim3(64), 0, s, L.sv, L.n, L.m);
   hipLaunchKernelGGL(step_scale_kernel, vgrid, dim3(kSB), 0, s, L.sv, -1, Y.beta);
   for (int j = 0; j < L.m; ++j) {
+    if (L.precond) hipLaunchKernelGGL(step_precond_kernel, vgrid, dim3(kSB), 0, s, L.sv, j);
     {
       TimedScope ts(t, "step_jvp", s);
       if (hipError_t e = launch_march_ensemble(L.jvp[j], true, s, nullptr)) return e;
     }
     TimedScope ts(t, "step_krylov", s);
-    hipLaunchKernelGGL(step_add_diag_kernel, vgrid, dim3(kSB), 0, s, L.sv, j);
+    hipLaunchKernelGGL(step_add_diag_kernel, vgrid, dim3(kSB), 0, s, L.sv, j, L.precond);
     // modified Gram-Schmidt: h_0 = <w, V_0>, then each update fused with the
     // next projection (for i = j: the norm of w)
     hipLaunchKernelGGL(step_dot_kernel, vgrid, dim3(kSB), 0, s, L.sv, 0, L.part);
@@ -282,7 +294,7 @@ hipError_t launch_ensemble_step(const StepLaunch& L, hipStream_t s, KernelTimer*
     hipLaunchKernelGGL(step_givens_kernel, dim3(tgrid), dim3(64), 0, s, L.sv, L.n, L.m, j, L.hist);
   }
   hipLaunchKernelGGL(step_backsub_kernel, dim3(tgrid), dim3(64), 0, s, L.sv, L.n, L.m);
-  hipLaunchKernelGGL(step_update_kernel, vgrid, dim3(kSB), 0, s, L.sv, L.m);
+  hipLaunchKernelGGL(step_update_kernel, vgrid, dim3(kSB), 0, s, L.sv, L.m, L.precond);
   return hipGetLastError();
 }
 

@@ -175,6 +175,36 @@ def test_ensemble_64_instances_sampled(setup):
         assert _same(R[q], r) and _same(J[q], j), f"instance {q} ({insts[q].N}, {insts[q].Nr})"
 
 
+def test_ensemble_jacobi_be_step_matches_single_instance_steps(setup):
+    """The lockstep step with the Jacobi preconditioner (CFL 10, GMRES(12))
+    equals each instance's preconditioned cfv_be_step; a step bound before
+    the preconditioner changes must be bound again."""
+    from paper_2209_04481_amd import CfvError, Ensemble, Tuning
+    ctxs, U, v, dbr, R1, J1, R0 = setup
+    print("case: ensemble backward-Euler step, Jacobi", flush=True)
+    ens = Ensemble(ctxs, Tuning(1, 2, 1))
+    ens.set_preconditioner(1)
+    Un, hist = ens.be_step(U, cfl=10.0, m=12)
+    torch.cuda.synchronize()
+    try:
+        for q in range(len(U)):
+            ctxs[q].set_preconditioner(1)
+            Us, hs = ctxs[q].be_step(U[q], cfl=10.0, m=12)
+            hb = hist[q].cpu().numpy()
+            k = len(hs)
+            assert np.all(np.abs(hb[:k] - hs) <= 1e-9 * np.abs(hs) + 1e-300), f"history of instance {q} {SHAPES[q]}"
+            dx, dxs = (Un[q] - U[q]).cpu(), (Us - U[q]).cpu()
+            assert float(rel_err_per_var(dx, dxs).max()) <= 1e-8, f"step of instance {q} {SHAPES[q]}"
+    finally:
+        for c in ctxs:
+            c.set_preconditioner(0)
+    ens.set_preconditioner(0)
+    with pytest.raises(CfvError):
+        ens.run()  # the bound step was dropped
+    with pytest.raises(CfvError):
+        ens.set_preconditioner(3)
+
+
 def test_ensemble_be_step_matches_single_instance_steps(setup):
     """One backward-Euler step (CFL 1e3, GMRES(12)) of every instance in
     lockstep on the device equals cfv_be_step of each instance: the same
