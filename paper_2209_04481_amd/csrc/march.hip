@@ -1,4 +1,6 @@
-// Tiled radial-march kernels for the residual and its forward derivative.
+// Tiled two-pass radial-march kernels: the forward derivative (JVP, T =
+// Dual) and the VJP's forward pass (T = double, face states written); the
+// residual itself runs as one fused pass (fused.hip).
 //
 // A workgroup owns a 16 x 16 tile of columns (i, j) of one panel and a chunk
 // of radial layers, and marches upward in k:
@@ -17,7 +19,9 @@
 //             with the sign of the side (canonical owner orientation).
 //
 // Both passes are written as barrier-separated phase functions over a
-// per-thread state, so the same code also runs under a host emulation.
+// per-thread state, so the same code also runs under a host emulation.  A
+// chunk enters and leaves through warm-up and cool-down iterations of the
+// same phases, so the outputs do not depend on the chunk length.
 #include "cfv_kernels.hpp"
 #include "cfv_march.hpp"
 
