@@ -434,6 +434,9 @@ struct FusedWG {
   // ---------------------------------------------------------- accumulate
   // Inner lanes: the fluxes from the west and south neighbours; the layer's
   // residual then waits for its top face (next layer), except the outermost.
+  // Runs after the next layer's first barrier (the flux buffers are written
+  // again only after its second), or after a barrier of its own when no layer
+  // follows.
   __host__ __device__ static void accumulate(const MarchArgs& a, const FTile& tm, FuState<T>& st, int t, int k,
                                              double* lds) {
     if (st.role != 1) return;

@@ -172,8 +172,11 @@ __host__ __device__ __forceinline__ bool ring_slot(const MarchArgs& a, const Til
 template <class T>
 struct GradWG {
   static constexpr int kTw = int(sizeof(T) / sizeof(double));
-  // primitives plane (9 T per position), then the column centroid sums (3)
-  static constexpr int kLds = 9 * kPlane * kTw + 3 * kPlane;
+  // two primitives planes (9 T per position; layer k in plane k mod 2), then
+  // the column centroid sums (3)
+  static constexpr int kCs = 2 * 9 * kPlane * kTw;
+  static constexpr int kLds = kCs + 3 * kPlane;
+  __host__ __device__ static int plane(int k) { return (k & 1) * 9 * kPlane; }
 
   __host__ __device__ static bool in_tile_active(const Shape& g, const TileMap& tm, int ti, int tj) {
     return ti >= 0 && ti < kTI && tj >= 0 && tj < kTJ && tm.i0 + ti < g.N && tm.j0 + tj < g.N;
@@ -199,7 +202,7 @@ struct GradWG {
     }
     if (!st.act) return;
     st.col = column_of(g, st.p, st.j, st.i);
-    double* cs = lds + 9 * kPlane * kTw;
+    double* cs = lds + kCs;
     const V3 c0 = cg3(G, CG_CSUM, st.col);
     const int me = plane_pos(ti, tj);
     cs[me] = c0.x; cs[kPlane + me] = c0.y; cs[2 * kPlane + me] = c0.z;
@@ -239,7 +242,7 @@ struct GradWG {
       }
       return;
     }
-    T* L = lds_as<T>(lds);
+    T* L = lds_as<T>(lds) + plane(k);
     const int me = plane_pos(ti, tj);
     for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
     if (a.P) {
@@ -267,7 +270,7 @@ struct GradWG {
     dir_offset(q, dx, dy);
     T qn[9];
     load_prims(a, st.rc0 + int64_t(k) * g.N * g.N, qn);
-    T* L = lds_as<T>(lds);
+    T* L = lds_as<T>(lds) + plane(k);
     const int pos = plane_pos(ti + dx, tj + dy);
     for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
   }
@@ -281,8 +284,8 @@ struct GradWG {
     if (!st.act) return;
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
-    const T* L = lds_as<T>(lds);
-    const double* cs = lds + 9 * kPlane * kTw;
+    const T* L = lds_as<T>(lds) + plane(k);
+    const double* cs = lds + kCs;
     const int ti = t % kTI, tj = t / kTI;
     const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
     const double rs = 0.125 * (r0 + r1);

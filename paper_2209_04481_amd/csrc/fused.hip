@@ -4,8 +4,9 @@
 // flux of the tile once and the residual.  HBM sees U read (plus the ring and
 // chunk-boundary layers, mostly from L2) and R written.
 //
-// Per layer, three barriers: after the primitives are published, after the
-// gradients and the exchanged face states, and after the face fluxes.  A
+// Per layer, two barriers: after the primitives are published, and after the
+// gradients and the exchanged face states; the face fluxes a layer exchanges
+// are summed after the next layer's first barrier.  A
 // chunk of layers [k0, k1) also evaluates the gradient of the layer below it
 // (for the state on its bottom face) and of the layer above it (for its top
 // face); those layers take no fluxes.  One workgroup per CU: the block keeps
@@ -27,13 +28,16 @@ __device__ __forceinline__ void fused_march_tile(const MarchArgs& a, const FTile
     const int mode = k < tm.k0 ? 1 : k >= tm.k1 ? 2 : 0;
     FusedWG<T>::publish(a, tm, st, t, k, lds);
     __syncthreads();
+    // the previous layer's fluxes from the west and south neighbours: the
+    // barrier above also orders them, so the flux phase needs none of its own
+    if (k - 1 >= tm.k0 && k - 1 < tm.k1) FusedWG<T>::accumulate(a, tm, st, t, k - 1, lds);
     FusedWG<T>::gradient(a, tm, st, t, k, mode, lds);
     __syncthreads();
-    if (mode == 0) {
-      FusedWG<T>::flux(a, tm, st, t, k, lds);
-      __syncthreads();
-      FusedWG<T>::accumulate(a, tm, st, t, k, lds);
-    }
+    if (mode == 0) FusedWG<T>::flux(a, tm, st, t, k, lds);
+  }
+  if (ke < tm.k1) {  // the chunk's last layer is the shell's outermost: no layer follows
+    __syncthreads();
+    FusedWG<T>::accumulate(a, tm, st, t, ke, lds);
   }
   record_nonphysical(a.d, st.role == 1 && st.bad);
 }

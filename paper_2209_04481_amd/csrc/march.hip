@@ -6,7 +6,8 @@
 // of radial layers, and marches upward in k:
 //
 //  grad pass  per layer: each thread converts its cell to primitives once and
-//             publishes them in LDS; the least-squares gradient and the
+//             publishes them in LDS (two planes, alternating by layer, so
+//             one barrier per layer); the least-squares gradient and the
 //             Barth-Jespersen factor then read in-tile neighbours from LDS,
 //             radial neighbours from registers (the march keeps layers k-1,
 //             k, k+1), and only tile-edge neighbours from global memory.
@@ -35,13 +36,14 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   const int t = threadIdx.x;
   GState<T> st;
   GradWG<T>::init(a, tm, st, t, lds);
+  // one barrier per layer: layers alternate between two LDS planes, so the
+  // next layer's plane fills while this one's is still being read
   for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
     if (k < tm.k0) continue;  // warm-up: registers only
     if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
-    __syncthreads();
   }
 }
 
@@ -59,8 +61,9 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
     __syncthreads();
     FluxWG<T>::faces(a, tm, st, t, k, lds);
     __syncthreads();
+    // no barrier after it: the next layer's states and ring slots overwrite
+    // buffers that only the face phase (before the barrier above) reads
     FluxWG<T>::accumulate(a, tm, st, t, k, lds);
-    __syncthreads();
   }
   FluxWG<T>::finish(a, tm, st, t);
 }

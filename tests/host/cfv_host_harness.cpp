@@ -63,7 +63,19 @@ struct HostShell {
   }
 };
 
-// the fused residual march, one work item (tile, chunk) after the other
+// Lanes of one workgroup between two barriers: the device runs them in any
+// interleaving, the emulation one lane after the other, first to last or (the
+// tests run both) last to first.  A phase that reads what another lane writes
+// before the next barrier gives different results in the two orders.
+bool g_reverse = false;
+
+template <class F>
+void lanes(int n, F&& f) {
+  for (int q = 0; q < n; ++q) f(g_reverse ? n - 1 - q : q);
+}
+
+// the fused residual march, one work item (tile, chunk) after the other, with
+// the kernel's barriers (fused.hip) between the lane loops
 void fused_residual(const MarchArgs& a, int kc) {
   using WG = FusedWG<double>;
   const Shape& g = a.d.g;
@@ -76,23 +88,28 @@ void fused_residual(const MarchArgs& a, int kc) {
     std::fill(lds.begin(), lds.end(), kPoison);
     const int kb = tm.k0 > 0 ? tm.k0 - 1 : 0;
     const int ke = tm.k1 < g.Nr ? tm.k1 : tm.k1 - 1;
-    for (int t = 0; t < kFL; ++t) WG::init(a, tm, st[t], t, kb, lds.data());
-    for (int k = WG::first_publish(kb); k < kb; ++k)
-      for (int t = 0; t < kFL; ++t) WG::publish_block(a, st[t], t, k, lds.data());
+    lanes(kFL, [&](int t) {
+      WG::init(a, tm, st[t], t, kb, lds.data());
+      for (int k = WG::first_publish(kb); k < kb; ++k) WG::publish_block(a, st[t], t, k, lds.data());
+      WG::publish(a, tm, st[t], t, kb, lds.data());
+    });
     for (int k = kb; k <= ke; ++k) {
       const int mode = k < tm.k0 ? 1 : k >= tm.k1 ? 2 : 0;
-      for (int t = 0; t < kFL; ++t) WG::publish(a, tm, st[t], t, k, lds.data());
-      for (int t = 0; t < kFL; ++t) WG::gradient(a, tm, st[t], t, k, mode, lds.data());
-      if (mode == 0) {
-        for (int t = 0; t < kFL; ++t) WG::flux(a, tm, st[t], t, k, lds.data());
-        for (int t = 0; t < kFL; ++t) WG::accumulate(a, tm, st[t], t, k, lds.data());
-      }
+      lanes(kFL, [&](int t) {
+        if (k - 1 >= tm.k0 && k - 1 < tm.k1) WG::accumulate(a, tm, st[t], t, k - 1, lds.data());
+        WG::gradient(a, tm, st[t], t, k, mode, lds.data());
+      });
+      lanes(kFL, [&](int t) {
+        if (mode == 0) WG::flux(a, tm, st[t], t, k, lds.data());
+        if (k + 1 <= ke) WG::publish(a, tm, st[t], t, k + 1, lds.data());
+      });
     }
+    if (ke < tm.k1) lanes(kFL, [&](int t) { WG::accumulate(a, tm, st[t], t, ke, lds.data()); });
     for (int t = 0; t < kFL; ++t) record_nonphysical(a.d, st[t].role == 1 && st[t].bad);
   }
 }
 
-// the two-pass march (gradient pass, then flux pass), as march.hip runs it
+// the two-pass march (gradient pass, then flux pass), with march.hip's barriers
 template <class T, bool Faces = false>
 void grad_march(const MarchArgs& a, int kc) {
   const Shape& g = a.d.g;
@@ -102,17 +119,21 @@ void grad_march(const MarchArgs& a, int kc) {
     TileMap tm;
     tile_of_logical(g, l, tm, kc);
     std::fill(lds.begin(), lds.end(), kPoison);
-    for (int t = 0; t < kNT; ++t) GradWG<T>::init(a, tm, st[t], t, lds.data());
-    for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
-      if (k < tm.k0) {
-        for (int t = 0; t < kNT; ++t) GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
-        continue;
-      }
-      for (int t = 0; t < kNT; ++t) {
-        GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
-        if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
-      }
-      for (int t = 0; t < kNT; ++t) GradWG<T>::template compute<Faces>(a, tm, st[t], t, k, lds.data());
+    // one barrier per layer, after the publish and ring steps: a segment is
+    // the previous layer's compute, then this layer's publish and ring
+    for (int k = tm.k0; k <= tm.k1; ++k) {
+      lanes(kNT, [&](int t) {
+        if (k == tm.k0) {  // the item's start and its warm-up layers
+          GradWG<T>::init(a, tm, st[t], t, lds.data());
+          for (int kw = GradWG<T>::first_layer(tm); kw < tm.k0; ++kw)
+            GradWG<T>::publish(a, tm, st[t], t, kw, lds.data());
+        }
+        if (k > tm.k0) GradWG<T>::template compute<Faces>(a, tm, st[t], t, k - 1, lds.data());
+        if (k < tm.k1) {
+          GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
+          if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+        }
+      });
     }
   }
 }
@@ -126,26 +147,34 @@ void flux_march(const MarchArgs& a, int kc) {
     TileMap tm;
     tile_of_logical(g, l, tm, kc);
     std::fill(lds.begin(), lds.end(), kPoison);
-    for (int t = 0; t < kNT; ++t) FluxWG<T>::init(a, tm, st[t], t);
-    for (int k = FluxWG<T>::first_layer(tm); k <= FluxWG<T>::last_layer(g, tm); ++k) {
-      if (k < tm.k0 || k >= tm.k1) {
-        for (int t = 0; t < kNT; ++t) FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
-        continue;
-      }
-      for (int t = 0; t < kNT; ++t) {
-        FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
-        if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
-      }
-      for (int t = 0; t < kNT; ++t) FluxWG<T>::faces(a, tm, st[t], t, k, lds.data());
-      for (int t = 0; t < kNT; ++t) FluxWG<T>::accumulate(a, tm, st[t], t, k, lds.data());
+    const int kf = FluxWG<T>::first_layer(tm), kl = FluxWG<T>::last_layer(g, tm);
+    // two barriers per layer (after the states and ring slots, after the
+    // faces): a segment is the faces, or the previous layer's accumulation,
+    // the warm-up or cool-down states and this layer's states and ring slots
+    for (int k = tm.k0; k <= tm.k1; ++k) {
+      lanes(kNT, [&](int t) {
+        if (k == tm.k0) {  // the item's start and its warm-up layer
+          FluxWG<T>::init(a, tm, st[t], t);
+          for (int kw = kf; kw < tm.k0; ++kw) FluxWG<T>::states(a, tm, st[t], t, kw, lds.data());
+        }
+        if (k > tm.k0) FluxWG<T>::accumulate(a, tm, st[t], t, k - 1, lds.data());
+        if (k <= kl) FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
+        if (k < tm.k1 && t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing)
+          FluxWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+        if (k == tm.k1) FluxWG<T>::finish(a, tm, st[t], t);
+      });
+      if (k < tm.k1) lanes(kNT, [&](int t) { FluxWG<T>::faces(a, tm, st[t], t, k, lds.data()); });
     }
-    for (int t = 0; t < kNT; ++t) FluxWG<T>::finish(a, tm, st[t], t);
   }
 }
 
 }  // namespace
 
 extern "C" {
+
+// Lane order of the emulated workgroups from now on: 0 first to last, 1 last
+// to first.
+void host_set_lane_order(int reverse) { g_reverse = reverse != 0; }
 
 // R = R(U, B_r) by the fused march with chunks of kc layers; flag (nullable)
 // receives the non-physical state word.  Returns 0, or 1 on bad arguments.

@@ -3,7 +3,8 @@ UndefinedBehaviorSanitizer (tests/host/cfv_host_harness.cpp), against the
 oracle.
 
 The harness emulates each workgroup (its lanes' states and its LDS, a barrier
-being the end of a loop over the lanes), so the residual of the fused march,
+being the end of a loop over the lanes, the lanes between two barriers run
+first to last or last to first), so the residual of the fused march,
 the JVP of the two-pass dual march and the VJP's four passes run exactly the
 index arithmetic of the GPU kernels.  An access outside any array stops the
 run with a sanitizer report; LDS is filled with NaN at the start of every
@@ -91,6 +92,7 @@ R = np.full_like(U, np.nan); Rj = np.full_like(U, np.nan); Jv = np.full_like(U, 
 gU = np.full_like(U, np.nan); gbr = np.full_like(br, np.nan)
 flag = ctypes.c_uint(0)
 bt = ptr(bth) if prm["inner_mode"] == 1 else None
+L.host_set_lane_order(int(d["order"]) if "order" in d.files else 0)
 assert L.host_residual(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(R), ctypes.byref(flag)) == 0
 assert L.host_jvp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(v), ptr(dbr), ptr(Jv), ptr(Rj)) == 0
 assert L.host_vjp(N, Nr, ptr(r), ctypes.byref(cp), ptr(U), ptr(br), bt, kc, ptr(w), ptr(gU), ptr(gbr)) == 0
@@ -177,3 +179,40 @@ def test_host_emulation_outputs_do_not_depend_on_the_chunk_length(harness, tmp_p
     for kc in (1, 2, 5, 40):
         for name in ("R", "Rj", "Jv", "gU", "gbr"):
             assert np.array_equal(res[kc][name], res[16][name]), f"{name} with chunk {kc}"
+
+
+def test_host_emulation_outputs_do_not_depend_on_the_lane_order(harness, tmp_path):
+    """Between two barriers the GPU runs a workgroup's lanes in any
+    interleaving.  The emulation runs the code between two of the kernels'
+    barriers lane after lane, first to last and then last to first: a phase
+    reading an LDS value another lane writes before the next barrier (a
+    missing barrier) would give different results in the two orders.  Partial
+    tiles, ring lanes across panel edges, several chunks and both boundary
+    layers; residual, JVP and VJP bitwise equal."""
+    lib, pre = harness
+    N, Nr, kc = 17, 5, 2
+    inst = ci.make_instance(N, Nr, "log", lmax=3, seed=91)
+    op = mhd.Params()
+    v = ci.scaled_direction(inst.U, 5)
+    dbr = ci.br_direction(6 * N * N, 5)
+    w = np.random.default_rng(9).standard_normal(inst.U.shape)
+    prm = tmp_path / "prm.json"
+    import json
+    prm.write_text(json.dumps({"gamma": op.gamma, "c_h": op.c_h, "G": op.G, "vr_star": op.vr_star, "rho_b": op.rho_b,
+                               "T_b": op.T_b, "limiter": int(op.limiter), "inner_mode": 0,
+                               "outer_exp": [float(x) for x in op.outer_exp], "outer_vr_mass": int(op.outer_vr_mass),
+                               "outer_psi_zero": int(op.outer_psi_zero)}))
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    res = {}
+    for order in (0, 1):
+        inp, out, script = tmp_path / f"in{order}.npz", tmp_path / f"out{order}.npz", tmp_path / f"run{order}.py"
+        np.savez(inp, N=N, Nr=Nr, kc=kc, order=order, r=inst.r_nodes, U=inst.U, br=inst.br,
+                 bth=np.zeros(6 * N * N), v=v, dbr=dbr, w=w)
+        script.write_text(RUNNER.format(root=ROOT, lib=lib, inp=str(inp), prm=str(prm), out=str(out)))
+        r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
+        assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-6000:])
+        res[order] = np.load(out)
+    for name in ("R", "Rj", "Jv", "gU", "gbr"):
+        assert np.all(np.isfinite(res[0][name])), name
+        assert np.array_equal(res[0][name], res[1][name]), f"{name} depends on the lane order"
