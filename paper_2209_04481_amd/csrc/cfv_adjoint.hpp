@@ -20,18 +20,21 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
   const double bn = bx * n.x + by * n.y + bz * n.z;
   const double B2 = bx * bx + by * by + bz * bz;
   const double v2 = vx * vx + vy * vy + vz * vz;
+  const double igm1 = 1.0 / (gamma - 1.0);  // the same expression for every face: computed once
   const double pT = p + 0.5 * B2;
-  const double E = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
+  const double E = p * igm1 + 0.5 * rho * v2 + 0.5 * B2;
   const double rvn = rho * vn;
   const double vb = vx * bx + vy * by + vz * bz;
-  const double irho = 1.0 / rho;
+  const double irho = recip(rho);  // as side_speed
   const double a2 = gamma * p * irho;
   const double b2 = B2 * irho;
   const double bn2 = bn * bn * irho;
   const double s = a2 + b2;
   const double disc = s * s - 4.0 * a2 * bn2;
-  const double sd = disc > 0.0 ? sqrt_nonneg(disc) : 0.0;
-  const double cf = sqrt_nonneg(0.5 * (s + sd));
+  // the roots with 1/(2 root) from the same sequence (hsd only where disc > 0)
+  double hsd = 0.0, hcf;
+  const double sd = disc > 0.0 ? sqrt_nonneg(disc, &hsd) : 0.0;
+  const double cf = sqrt_nonneg(0.5 * (s + sd), &hcf);
 
   // adjoints of the intermediates from the flux components
   double rvnb = Fb[0] + Fb[1] * vx + Fb[2] * vy + Fb[3] * vz;
@@ -51,9 +54,9 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
 
   // lambda = |v_n| + c_f
   vnb += (vn < 0.0 ? -lamb : lamb);
-  const double hb = lamb / (2.0 * cf);
+  const double hb = lamb * hcf;
   double sb = 0.5 * hb;
-  const double discb = disc > 0.0 ? (0.5 * hb) / (2.0 * sd) : 0.0;
+  const double discb = disc > 0.0 ? (0.5 * hb) * hsd : 0.0;
   sb += 2.0 * s * discb;
   double a2b = -4.0 * bn2 * discb + sb;
   const double bn2b = -4.0 * a2 * discb;
@@ -65,7 +68,7 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
   double rhob = -irho * irho * irhob;
 
   // E and p_T
-  pb += Eb / (gamma - 1.0) + pTb;
+  pb += Eb * igm1 + pTb;
   rhob += 0.5 * v2 * Eb;
   const double v2b = 0.5 * rho * Eb;
   B2b += 0.5 * Eb + 0.5 * pTb;
@@ -102,8 +105,8 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
 __host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], const double qR[9], V3 S, const double wb[9],
                                                 double qLb[9], double qRb[9], const Params& pr,
                                                 bool want_L = true, bool want_R = true) {
-  const double area = norm3(S);
-  const double ia = 1.0 / area;
+  double ia;
+  const double area = area_and_inverse(S, ia);  // as rusanov()
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
   double UL[9], UR[9];
   const double lamL = side_speed(qL, n, pr.gamma);
@@ -136,8 +139,8 @@ __host__ __device__ __forceinline__ void rusanov_adjoint(const double qL[9], con
 __host__ __device__ __forceinline__ void rusanov_adjoint_side(const double qa[9], const double qb[9], V3 S,
                                                      const double wb[9], double qab[9], const Params& pr,
                                                      bool a_is_L) {
-  const double area = norm3(S);
-  const double ia = 1.0 / area;
+  double ia;
+  const double area = area_and_inverse(S, ia);
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
   const double lamA = side_speed(qa, n, pr.gamma);
   const double lamB = side_speed(qb, n, pr.gamma);
@@ -164,7 +167,7 @@ __host__ __device__ __forceinline__ void rusanov_adjoint_side(const double qa[9]
 // (dP/dU)^T Pb for P = prim(U): returns Ub.
 __host__ __device__ __forceinline__ void prim_adjoint(const double u[9], const double Pb[9], double Ub[9], double gamma) {
   const double rho = u[0];
-  const double ir = 1.0 / rho;
+  const double ir = recip(rho);  // as cons_to_prim
   const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
   const double g1 = gamma - 1.0;
   const double pb = Pb[7];

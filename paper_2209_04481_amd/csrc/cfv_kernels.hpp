@@ -110,7 +110,7 @@ struct LsqWeights {
     }
     const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
     const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
-    const double idet = 1.0 / (m00 * c00 + m01 * c01 + m02 * c02);
+    const double idet = recip_refined(m00 * c00 + m01 * c01 + m02 * c02);
     const double i00 = c00 * idet, i01 = c01 * idet, i02 = c02 * idet;
     const double i11 = c11 * idet, i12 = c12 * idet, i22 = c22 * idet;
 #pragma unroll
@@ -136,7 +136,7 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
   if (!limiter) return;
   // Barth-Jespersen: the smallest ratio (q_ext - q_c) / (g . (x_f - x_c))
   // below 1, found by comparing magnitudes cross-multiplied (ties keep the
-  // earlier candidate: 1 first, then faces in local order); one division.
+  // earlier candidate: 1 first, then faces in local order); one reciprocal.
   double bn = 1.0, bd = 1.0;
   T nb = T(1.0), db = T(1.0);
   bool act = false;
@@ -157,7 +157,7 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
     }
   }
   if (!act) return;
-  const T phi = nb / db;
+  const T phi = nb * recip(db);  // the plain-value version's bits: |nb| recip(|db|)
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 
@@ -191,7 +191,7 @@ __host__ __device__ __forceinline__ void limited_grad<double>(const LsqWeights& 
       bd = ad;
     }
   }
-  const double phi = bn / bd;
+  const double phi = bn * recip(bd);
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 

@@ -30,12 +30,13 @@ __host__ __device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual
 __host__ __device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
 __host__ __device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
 __host__ __device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
-// 1/b for tangents: on the GPU the hardware reciprocal refined by two Newton
-// steps (e = 1 - b r, r += r e; each squares the relative error), within an
-// ulp or so of the IEEE quotient for normal b, at about half a division's
-// instructions.  Values keep IEEE division, so a derivative pass takes the
-// same branches as the value-only pass.
-__host__ __device__ __forceinline__ double tangent_recip(double b) {
+// 1/b: on the GPU the hardware reciprocal refined by two Newton steps
+// (e = 1 - b r, r += r e; each squares the relative error), within an ulp or
+// so of the IEEE quotient for normal b, at about half a division's
+// instructions.  For tangents, and for reciprocals that every pass takes
+// through recip() below, so that the passes agree with each other bit for
+// bit.  recip_refined(-b) = -recip_refined(b) exactly.  On the host, 1 / b.
+__host__ __device__ __forceinline__ double recip_refined(double b) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double r = __builtin_amdgcn_rcp(b);
   double e = __builtin_fma(-b, r, 1.0);
@@ -46,6 +47,7 @@ __host__ __device__ __forceinline__ double tangent_recip(double b) {
   return 1.0 / b;
 #endif
 }
+__host__ __device__ __forceinline__ double tangent_recip(double b) { return recip_refined(b); }
 __host__ __device__ __forceinline__ Dual operator/(Dual a, Dual b) {
   double q = a.v / b.v;
   return Dual(q, (a.d - q * b.d) * tangent_recip(b.v));
@@ -100,6 +102,13 @@ __host__ __device__ __forceinline__ Dual sqrt(Dual a) {
   double h;
   const double s = sqrt_nonneg(a.v, &h);
   return Dual(s, a.d * h);
+}
+
+// 1/b with the value of recip_refined for plain values and Dual values alike
+__host__ __device__ __forceinline__ double recip(double b) { return recip_refined(b); }
+__host__ __device__ __forceinline__ Dual recip(Dual b) {
+  const double r = recip_refined(b.v);
+  return Dual(r, -(b.d * r) * r);
 }
 
 __host__ __device__ __forceinline__ double val(double a) { return a; }
@@ -168,7 +177,7 @@ struct Params {
 template <class T>
 __host__ __device__ __forceinline__ void cons_to_prim(const T u[9], T q[9], double gamma) {
   T rho = u[0];
-  T irho = 1.0 / rho;
+  T irho = recip(rho);
   T vx = u[1] * irho, vy = u[2] * irho, vz = u[3] * irho;
   T v2 = vx * vx + vy * vy + vz * vz;
   T B2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
@@ -185,7 +194,7 @@ __host__ __device__ __forceinline__ void prim_to_cons(const T q[9], T u[9], doub
   u[0] = q[0];
   u[1] = q[0] * q[1]; u[2] = q[0] * q[2]; u[3] = q[0] * q[3];
   u[4] = q[4]; u[5] = q[5]; u[6] = q[6];
-  u[7] = q[7] / (gamma - 1.0) + 0.5 * q[0] * v2 + 0.5 * B2;
+  u[7] = q[7] * (1.0 / (gamma - 1.0)) + 0.5 * q[0] * v2 + 0.5 * B2;
   u[8] = q[8];
 }
 
@@ -196,7 +205,7 @@ __host__ __device__ __forceinline__ T side_speed(const T q[9], V3 n, double gamm
   T vn = q[1] * n.x + q[2] * n.y + q[3] * n.z;
   T bn = bx * n.x + by * n.y + bz * n.z;
   T B2 = bx * bx + by * by + bz * bz;
-  T irho = 1.0 / rho;
+  T irho = recip(rho);
   T a2 = gamma * p * irho;
   T b2 = B2 * irho;
   T bn2 = bn * bn * irho;
@@ -242,10 +251,18 @@ __host__ __device__ __forceinline__ T phys_flux(const T q[9], V3 n, T F[9], doub
 
 // Rusanov flux through the face of vector area S (L -> R); returns s.
 //   F = (F_L + F_R)/2 |S| - s/2 (U_R - U_L) |S|,  s = max(lam_L, lam_R, c_h)
+// |S| and 1/|S| from one square-root sequence
+__host__ __device__ __forceinline__ double area_and_inverse(V3 S, double& ia) {
+  double h;
+  const double area = sqrt_nonneg(dot3(S, S), &h);
+  ia = 2.0 * h;
+  return area;
+}
+
 template <class T>
 __host__ __device__ __forceinline__ T rusanov(const T qL[9], const T qR[9], V3 S, T F[9], const Params& pr) {
-  const double area = norm3(S);
-  const double ia = 1.0 / area;
+  double ia;
+  const double area = area_and_inverse(S, ia);
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
   T s = pick_max(side_speed(qL, n, pr.gamma), side_speed(qR, n, pr.gamma));
   s = pick_max(s, T(pr.c_h));

@@ -216,12 +216,14 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
           }
         }
       }
-      const double phi = act >= 0 ? num / den : 1.0;
+      // phi as limited_grad takes it (num and den share their sign)
+      const double rd = recip(den);
+      const double phi = act >= 0 ? num * rd : 1.0;
       const double phib = gbx * gx + gby * gy + gbz * gz;
       gbx *= phi; gby *= phi; gbz *= phi;
       if (act >= 0) {
-        const double numb = phib / den;
-        const double denb = -phib * phi / den;
+        const double numb = phib * rd;
+        const double denb = -phib * phi * rd;
         gbx += denb * dact.x; gby += denb * dact.y; gbz += denb * dact.z;
         const int ext = den > 0.0 ? amax : amin;
         pb -= numb;
