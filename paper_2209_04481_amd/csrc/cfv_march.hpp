@@ -172,11 +172,9 @@ __host__ __device__ __forceinline__ bool ring_slot(const MarchArgs& a, const Til
 template <class T>
 struct GradWG {
   static constexpr int kTw = int(sizeof(T) / sizeof(double));
-  // two primitives planes (9 T per position; layer k in plane k mod 2), then
-  // the column centroid sums (3)
-  static constexpr int kCs = 2 * 9 * kPlane * kTw;
+  // primitives plane (9 T per position), then the column centroid sums (3)
+  static constexpr int kCs = 9 * kPlane * kTw;
   static constexpr int kLds = kCs + 3 * kPlane;
-  __host__ __device__ static int plane(int k) { return (k & 1) * 9 * kPlane; }
 
   __host__ __device__ static bool in_tile_active(const Shape& g, const TileMap& tm, int ti, int tj) {
     return ti >= 0 && ti < kTI && tj >= 0 && tj < kTJ && tm.i0 + ti < g.N && tm.j0 + tj < g.N;
@@ -242,7 +240,7 @@ struct GradWG {
       }
       return;
     }
-    T* L = lds_as<T>(lds) + plane(k);
+    T* L = lds_as<T>(lds);
     const int me = plane_pos(ti, tj);
     for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
     if (a.P) {
@@ -270,7 +268,7 @@ struct GradWG {
     dir_offset(q, dx, dy);
     T qn[9];
     load_prims(a, st.rc0 + int64_t(k) * g.N * g.N, qn);
-    T* L = lds_as<T>(lds) + plane(k);
+    T* L = lds_as<T>(lds);
     const int pos = plane_pos(ti + dx, tj + dy);
     for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
   }
@@ -284,7 +282,7 @@ struct GradWG {
     if (!st.act) return;
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
-    const T* L = lds_as<T>(lds) + plane(k);
+    const T* L = lds_as<T>(lds);
     const double* cs = lds + kCs;
     const int ti = t % kTI, tj = t / kTI;
     const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);

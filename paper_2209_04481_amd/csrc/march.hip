@@ -6,8 +6,7 @@
 // of radial layers, and marches upward in k:
 //
 //  grad pass  per layer: each thread converts its cell to primitives once and
-//             publishes them in LDS (two planes, alternating by layer, so
-//             one barrier per layer); the least-squares gradient and the
+//             publishes them in LDS; the least-squares gradient and the
 //             Barth-Jespersen factor then read in-tile neighbours from LDS,
 //             radial neighbours from registers (the march keeps layers k-1,
 //             k, k+1), and only tile-edge neighbours from global memory.
@@ -36,14 +35,15 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   const int t = threadIdx.x;
   GState<T> st;
   GradWG<T>::init(a, tm, st, t, lds);
-  // one barrier per layer: layers alternate between two LDS planes, so the
-  // next layer's plane fills while this one's is still being read
   for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
     GradWG<T>::publish(a, tm, st, t, k, lds);
     if (k < tm.k0) continue;  // warm-up: registers only
     if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
+    // the plane is written again by the next layer (a second plane to drop
+    // this barrier made both gradient passes slower: more LDS per workgroup)
+    __syncthreads();
   }
 }
 
