@@ -195,6 +195,45 @@ __host__ __device__ __forceinline__ void limited_grad<double>(const LsqWeights& 
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 
+// The factor alone, for a pass that needs no derivative of the choice (the
+// fused residual march): the numerator is qmax - qc on faces with d2 > 0 and
+// qc - qmin on faces with d2 < 0, so the smallest ratio is (qmax - qc) over
+// the largest d2 or (qc - qmin) over the largest -d2: two candidates instead
+// of six, the same value (up to which of two equal ratios is kept).
+__host__ __device__ __forceinline__ void limited_grad_value(const LsqWeights& L, const V3 dxf[6], int limiter,
+                                                            double qc, const double qn[6], double& gx, double& gy,
+                                                            double& gz) {
+  gx = 0.0; gy = 0.0; gz = 0.0;
+  double qmax = qc, qmin = qc;
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const double dq = qn[n] - qc;
+    gx += L.W[n].x * dq; gy += L.W[n].y * dq; gz += L.W[n].z * dq;
+    qmax = ::fmax(qmax, qn[n]);
+    qmin = ::fmin(qmin, qn[n]);
+  }
+  if (!limiter) return;
+  double dmax = 0.0, dmin = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const double d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
+    dmax = ::fmax(dmax, d2);
+    dmin = ::fmin(dmin, d2);
+  }
+  const double up = qmax - qc, down = qc - qmin, ad = -dmin;
+  double bn = 1.0, bd = 1.0;
+  if (up * bd < bn * dmax) {
+    bn = up;
+    bd = dmax;
+  }
+  if (down * bd < bn * ad) {
+    bn = down;
+    bd = ad;
+  }
+  const double phi = bn * recip(bd);
+  gx = phi * gx; gy = phi * gy; gz = phi * gz;
+}
+
 // launchers (residual.hip)
 hipError_t launch_geometry(const DevGrid& d, double* xc, double* vol, double* xf, double* S, hipStream_t s);
 hipError_t launch_local_dt(const DevGrid& d, const double* U, double cfl, double* diag, double* W, hipStream_t s,
