@@ -135,29 +135,32 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
   }
   if (!limiter) return;
   // Barth-Jespersen: the smallest ratio (q_ext - q_c) / (g . (x_f - x_c))
-  // below 1, found by comparing magnitudes cross-multiplied (ties keep the
-  // earlier candidate: 1 first, then faces in local order); one reciprocal.
-  double bn = 1.0, bd = 1.0;
-  T nb = T(1.0), db = T(1.0);
-  bool act = false;
+  // below 1, ties keeping the earlier candidate (1 first, then faces in
+  // local order).  The numerator is qmax - qc where the projection d2 is
+  // positive and qmin - qc where it is negative, so the candidates are the
+  // face with the largest d2 and the face with the smallest (the first of
+  // equal ones); their magnitudes are compared cross-multiplied, and an
+  // exact tie between the two goes to the earlier face.  One reciprocal.
+  T dhi = T(0.0), dlo = T(0.0);
+  int fhi = 6, flo = 6;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const T d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
-    const double d2v = val(d2);
-    if (d2v != 0.0) {
-      const T num = d2v > 0.0 ? qmax - qc : qmin - qc;
-      const double an = ::fabs(val(num)), ad = ::fabs(d2v);
-      if (an * bd < bn * ad) {
-        bn = an;
-        bd = ad;
-        nb = num;
-        db = d2;
-        act = true;
-      }
-    }
+    if (val(d2) > val(dhi)) { dhi = d2; fhi = f; }
+    if (val(d2) < val(dlo)) { dlo = d2; flo = f; }
   }
-  if (!act) return;
-  const T phi = nb * recip(db);  // the plain-value version's bits: |nb| recip(|db|)
+  const double up = val(qmax) - val(qc), down = val(qc) - val(qmin), adhi = val(dhi), adlo = -val(dlo);
+  double bn = 1.0, bd = 1.0;
+  int pick = 0;
+  if (up * bd < bn * adhi) {
+    bn = up;
+    bd = adhi;
+    pick = 1;
+  }
+  const double lhs = down * bd, rhs = bn * adlo;
+  if (lhs < rhs || (lhs == rhs && pick == 1 && flo < fhi)) pick = 2;
+  if (pick == 0) return;
+  const T phi = pick == 1 ? (qmax - qc) * recip(dhi) : (qmin - qc) * recip(dlo);
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 
