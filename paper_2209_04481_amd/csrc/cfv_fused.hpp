@@ -305,7 +305,7 @@ struct FusedWG {
 #pragma unroll
       for (int q = 0; q < 4; ++q) qn[2 + q] = at(L, st.nb[q], v, k);
       T gx, gy, gz;
-      limited_grad_value(W, dxf, a.d.pr.limiter, P0[v], qn, gx, gy, gz);
+      limited_grad(W, dxf, a.d.pr.limiter, P0[v], qn, gx, gy, gz);
       const T p0 = P0[v];
       // every mode computes and publishes the same states (the warm-up and
       // cool-down layers' are overwritten before any flux phase reads them):

@@ -165,47 +165,15 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
 }
 
 // The same for plain values, with fewer selects: no derivative follows the
-// extremes (max / min give the same values as the tie rule), and the chosen
-// ratio is kept by its magnitudes alone (the numerator has the sign of the
-// denominator, so num / den = |num| / |den|); a face with a zero denominator
-// never wins the comparison, and with no face below 1 the factor is 1 / 1.
+// choice, so the extremes are taken by max/min, the candidates are the
+// largest and the smallest projection (max/min), and which of two equal
+// ratios is kept does not matter (the numerator has the sign of the
+// denominator, so num / den = |num| / |den|); with no ratio below 1 the
+// factor is 1.
 template <>
 __host__ __device__ __forceinline__ void limited_grad<double>(const LsqWeights& L, const V3 dxf[6], int limiter,
                                                               double qc, const double qn[6], double& gx,
                                                               double& gy, double& gz) {
-  gx = 0.0; gy = 0.0; gz = 0.0;
-  double qmax = qc, qmin = qc;
-#pragma unroll
-  for (int n = 0; n < 6; ++n) {
-    const double dq = qn[n] - qc;
-    gx += L.W[n].x * dq; gy += L.W[n].y * dq; gz += L.W[n].z * dq;
-    qmax = ::fmax(qmax, qn[n]);
-    qmin = ::fmin(qmin, qn[n]);
-  }
-  if (!limiter) return;
-  const double up = qmax - qc, down = qc - qmin;
-  double bn = 1.0, bd = 1.0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const double d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
-    const double an = d2 > 0.0 ? up : down, ad = ::fabs(d2);
-    if (an * bd < bn * ad) {
-      bn = an;
-      bd = ad;
-    }
-  }
-  const double phi = bn * recip(bd);
-  gx = phi * gx; gy = phi * gy; gz = phi * gz;
-}
-
-// The factor alone, for a pass that needs no derivative of the choice (the
-// fused residual march): the numerator is qmax - qc on faces with d2 > 0 and
-// qc - qmin on faces with d2 < 0, so the smallest ratio is (qmax - qc) over
-// the largest d2 or (qc - qmin) over the largest -d2: two candidates instead
-// of six, the same value (up to which of two equal ratios is kept).
-__host__ __device__ __forceinline__ void limited_grad_value(const LsqWeights& L, const V3 dxf[6], int limiter,
-                                                            double qc, const double qn[6], double& gx, double& gy,
-                                                            double& gz) {
   gx = 0.0; gy = 0.0; gz = 0.0;
   double qmax = qc, qmin = qc;
 #pragma unroll

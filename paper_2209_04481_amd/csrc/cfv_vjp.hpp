@@ -196,26 +196,30 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
     for (int lf = 0; lf < 6; ++lf) o[lf] = 0.0;
     double pb = Pb[v];
     if (d.pr.limiter) {
-      // the same choice as the forward limiter (limited_grad)
-      double bn = 1.0, bd = 1.0, num = 0.0, den = 1.0;
-      int act = -1;
-      V3 dact = mk(0.0, 0.0, 0.0);
+      // the choice of the dual limiter (limited_grad): the face with the
+      // largest positive projection or the one with the most negative (the
+      // first of equal ones), an exact tie between them to the earlier face
+      double dhi = 0.0, dlo = 0.0;
+      int fhi = 6, flo = 6;
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         const double d2 = gx * dxf[f].x + gy * dxf[f].y + gz * dxf[f].z;
-        if (d2 != 0.0) {
-          const double nm = d2 > 0.0 ? qmax - qc : qmin - qc;
-          const double an = ::fabs(nm), ad = ::fabs(d2);
-          if (an * bd < bn * ad) {
-            bn = an;
-            bd = ad;
-            num = nm;
-            den = d2;
-            act = f;
-            dact = dxf[f];
-          }
-        }
+        if (d2 > dhi) { dhi = d2; fhi = f; }
+        if (d2 < dlo) { dlo = d2; flo = f; }
       }
+      const double up = qmax - qc, down = qc - qmin;
+      double bn = 1.0, bd = 1.0;
+      int pick = 0;
+      if (up * bd < bn * dhi) {
+        bn = up;
+        bd = dhi;
+        pick = 1;
+      }
+      const double lhs = down * bd, rhs = bn * -dlo;
+      if (lhs < rhs || (lhs == rhs && pick == 1 && flo < fhi)) pick = 2;
+      const int act = pick == 1 ? fhi : pick == 2 ? flo : -1;
+      const double num = pick == 1 ? qmax - qc : qmin - qc;
+      const double den = pick == 1 ? dhi : pick == 2 ? dlo : 1.0;
       // phi as limited_grad takes it (num and den share their sign)
       const double rd = recip(den);
       const double phi = act >= 0 ? num * rd : 1.0;
@@ -224,7 +228,13 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       if (act >= 0) {
         const double numb = phib * rd;
         const double denb = -phib * phi * rd;
-        gbx += denb * dact.x; gby += denb * dact.y; gbz += denb * dact.z;
+        // den = g . dxf[act] (a masked sum, not dxf[act]: a run-time index
+        // would put the array in scratch)
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const double wf = f == act ? denb : 0.0;
+          gbx += wf * dxf[f].x; gby += wf * dxf[f].y; gbz += wf * dxf[f].z;
+        }
         const int ext = den > 0.0 ? amax : amin;
         pb -= numb;
         if (ext < 0) pb += numb;
