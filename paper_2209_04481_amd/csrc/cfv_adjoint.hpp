@@ -144,10 +144,10 @@ __host__ __device__ __forceinline__ void rusanov_adjoint_side(const double qa[9]
   const V3 n = mk(S.x * ia, S.y * ia, S.z * ia);
   const double lamA = side_speed(qa, n, pr.gamma);
   const double lamB = side_speed(qb, n, pr.gamma);
-  const double lamL = a_is_L ? lamA : lamB, lamR = a_is_L ? lamB : lamA;
-  const bool left_wins = lamL >= lamR;  // the left speed wins ties
-  const double s1 = left_wins ? lamL : lamR;
-  const double s = s1 >= pr.c_h ? s1 : pr.c_h;
+  // the larger speed (the same value whichever side has it); on a tie the
+  // left side wins
+  const double s1 = ::fmax(lamA, lamB);
+  const double s = ::fmax(s1, pr.c_h);
   double UA[9], UB[9];
   prim_to_cons(qa, UA, pr.gamma);
   prim_to_cons(qb, UB, pr.gamma);
@@ -159,7 +159,7 @@ __host__ __device__ __forceinline__ void rusanov_adjoint_side(const double qa[9]
     UAb[v] = sg * (0.5 * s * area * wb[v]);
     sb -= 0.5 * area * wb[v] * (sg * (UB[v] - UA[v]));
   }
-  const bool a_wins = a_is_L == left_wins;
+  const bool a_wins = lamA > lamB || (lamA == lamB && a_is_L);
   const double lamAb = s1 >= pr.c_h && a_wins ? sb : 0.0;
   flux_side_adjoint(qa, n, Fb, UAb, lamAb, qab, pr.gamma, pr.c_h);
 }

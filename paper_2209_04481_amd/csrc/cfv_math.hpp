@@ -119,6 +119,12 @@ template <class T> __host__ __device__ __forceinline__ T tabs(T a) { return val(
 // min/max that keep the first argument on ties; the pick follows the values
 template <class T> __host__ __device__ __forceinline__ T pick_min(T a, T b) { return val(a) <= val(b) ? a : b; }
 template <class T> __host__ __device__ __forceinline__ T pick_max(T a, T b) { return val(a) >= val(b) ? a : b; }
+// plain values carry nothing that depends on which argument wins: the
+// hardware's abs modifier and min/max instructions (the same values; only a
+// NaN argument, which makes the flux NaN anyway, is passed over)
+__host__ __device__ __forceinline__ double tabs(double a) { return ::fabs(a); }
+__host__ __device__ __forceinline__ double pick_min(double a, double b) { return ::fmin(a, b); }
+__host__ __device__ __forceinline__ double pick_max(double a, double b) { return ::fmax(a, b); }
 __host__ __device__ __forceinline__ Dual powd(Dual a, double e) {
   double p = ::pow(a.v, e);
   return Dual(p, e == 0.0 ? 0.0 : e * ::pow(a.v, e - 1.0) * a.d);

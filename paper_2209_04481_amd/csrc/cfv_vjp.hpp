@@ -135,12 +135,15 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       }
     } else {
       const int64_t o = nb.id;
+      // w_L - w_R: (wc - wn) signed by the orientation (a product, the same
+      // bits as the other difference, instead of two differences and a select)
+      const double sg = own ? 1.0 : -1.0;
       // the neighbour's state on this face, as the forward pass reconstructed it
 #pragma unroll
       for (int v = 0; v < 9; ++v) {
         qo[v] = lf < 2 ? gld(Q, (9 * nb.back + v) * nc + o) : Qr(nb.back, v, o);
         const double wn = lf < 2 ? gld(w, v * nc + o) : wr(v, o);
-        wb[v] = own ? wc[v] - wn : wn - wc[v];  // w_L - w_R
+        wb[v] = (wc[v] - wn) * sg;
       }
     }
     double qLb[9], qRb[9];
