@@ -230,7 +230,6 @@ struct GradWG {
                                           double* lds) {
     if (!st.act) return;
     const Shape& g = a.d.g;
-    const GeomRef& G = a.d.G;
     const int ti = t % kTI, tj = t / kTI;
     if (k + 1 >= 0 && k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
     if (k < tm.k0) {
@@ -600,7 +599,8 @@ struct FluxWG {
           for (int v = 0; v < 9; ++v) qo[v] = src[v * stride];
         }
         face_flux(own, qs, qo, S, F, a.d.pr);
-        for (int v = 0; v < 9; ++v) st.acc[v] += own ? F[v] : -F[v];
+        const double sg = own ? 1.0 : -1.0;  // a product by +-1: the same bits as the select
+        for (int v = 0; v < 9; ++v) st.acc[v] += F[v] * sg;
         for (int v = 0; v < 9; ++v) Fb[(9 * h + v) * kNT + t] = F[v];
       }
     }
@@ -633,14 +633,14 @@ struct FluxWG {
     const T* Eb = lds_as<T>(lds) + kEdgeOff;
     const int ti = t % kTI, tj = t / kTI;
     if (ti > 0) {
-      const bool own = (gld(G.cn, 4 * G.ncol + st.col) >> 8) != 0;
-      for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[v * kNT + t - 1] : -Fb[v * kNT + t - 1];
+      const double sg = (gld(G.cn, 4 * G.ncol + st.col) >> 8) != 0 ? 1.0 : -1.0;  // the west face's orientation
+      for (int v = 0; v < 9; ++v) st.acc[v] += Fb[v * kNT + t - 1] * sg;
     } else {
       for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + 16 + tj];
     }
     if (tj > 0) {
-      const bool own = (gld(G.cn, 6 * G.ncol + st.col) >> 8) != 0;
-      for (int v = 0; v < 9; ++v) st.acc[v] += own ? Fb[(9 + v) * kNT + t - kTI] : -Fb[(9 + v) * kNT + t - kTI];
+      const double sg = (gld(G.cn, 6 * G.ncol + st.col) >> 8) != 0 ? 1.0 : -1.0;  // the south face's
+      for (int v = 0; v < 9; ++v) st.acc[v] += Fb[(9 + v) * kNT + t - kTI] * sg;
     } else {
       for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + ti];
     }
