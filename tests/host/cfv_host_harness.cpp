@@ -175,6 +175,28 @@ extern "C" {
 // to first.
 void host_set_lane_order(int reverse) { g_reverse = reverse != 0; }
 
+// The dual Barth-Jespersen limited gradient of one variable (limited_grad
+// with T = Dual) for given least-squares weights W (6 x 3, so that the
+// unlimited gradient is sum_n W_n (q_n - q_c)), face offsets dxf (6 x 3),
+// the cell's and neighbours' values and tangents; out: gx, gy, gz values,
+// then their tangents.
+void host_limited_grad_dual(const double* W, const double* dxf, double qc_v, double qc_d, const double* qn_v,
+                            const double* qn_d, int limiter, double* out) {
+  V3 dx[6], df[6];
+  for (int n = 0; n < 6; ++n) {
+    dx[n] = mk(1.0, 0.0, 0.0);
+    df[n] = mk(dxf[3 * n], dxf[3 * n + 1], dxf[3 * n + 2]);
+  }
+  LsqWeights L(dx);
+  for (int n = 0; n < 6; ++n) L.W[n] = mk(W[3 * n], W[3 * n + 1], W[3 * n + 2]);
+  Dual qn[6];
+  for (int n = 0; n < 6; ++n) qn[n] = Dual(qn_v[n], qn_d[n]);
+  Dual gx, gy, gz;
+  limited_grad(L, df, limiter, Dual(qc_v, qc_d), qn, gx, gy, gz);
+  out[0] = gx.v; out[1] = gy.v; out[2] = gz.v;
+  out[3] = gx.d; out[4] = gy.d; out[5] = gz.d;
+}
+
 // R = R(U, B_r) by the fused march with chunks of kc layers; flag (nullable)
 // receives the non-physical state word.  Returns 0, or 1 on bad arguments.
 int host_residual(int N, int Nr, const double* r, const cfv_params* p, const double* U, const double* br,

@@ -216,3 +216,80 @@ def test_host_emulation_outputs_do_not_depend_on_the_lane_order(harness, tmp_pat
     for name in ("R", "Rj", "Jv", "gU", "gbr"):
         assert np.all(np.isfinite(res[0][name])), name
         assert np.array_equal(res[0][name], res[1][name]), f"{name} depends on the lane order"
+
+
+LIMITER_RUNNER = r'''
+import ctypes, sys
+import numpy as np
+L = ctypes.CDLL({lib!r})
+d = np.load({inp!r})
+P = ctypes.c_void_p
+ptr = lambda a: np.ascontiguousarray(a).ctypes.data_as(P)
+out = np.zeros((len(d["qc"]), 6))
+for c in range(len(d["qc"])):
+    o = np.zeros(6)
+    L.host_limited_grad_dual(ptr(d["W"][c]), ptr(d["dxf"][c]), ctypes.c_double(d["qc"][c]), ctypes.c_double(d["qcd"][c]),
+                             ptr(d["qn"][c]), ptr(d["qnd"][c]), 1, ptr(o))
+    out[c] = o
+np.save({out!r}, out)
+'''
+
+
+def _limiter_cases():
+    """Stencils for the dual limiter: given weights W (so g = sum W_n (q_n -
+    q_c) exactly), face offsets and values; exact ties built with powers of
+    two, then random ones."""
+    cases = []
+    e = np.zeros((6, 3))
+    W = e.copy(); W[0] = (1.0, 0.0, 0.0)          # g = (q_0 - q_c, 0, 0)
+    qn = np.array([1.0, 0.0, 0.0, 0.0, -1.0, 0.0])  # up = down = 1
+    for plus, minus in ((2, 3), (3, 2), (5, 1), (1, 5)):
+        # projections +4 on face `plus`, -4 on face `minus`: ratios 1/4 and
+        # 1/4, an exact tie across signs (the earlier face wins)
+        dxf = e.copy(); dxf[plus] = (4.0, 0.0, 0.0); dxf[minus] = (-4.0, 0.0, 0.0)
+        cases.append((W, dxf, 0.0, qn))
+    # two equal positive projections (same-sign tie), and a ratio of exactly 1
+    dxf = e.copy(); dxf[3] = (4.0, 0.0, 0.0); dxf[1] = (4.0, 0.0, 0.0); dxf[2] = (-2.0, 0.0, 0.0)
+    cases.append((W, dxf, 0.0, qn))
+    dxf = e.copy(); dxf[4] = (1.0, 0.0, 0.0); dxf[0] = (-0.5, 0.0, 0.0)
+    cases.append((W, dxf, 0.0, qn))
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        cases.append((rng.standard_normal((6, 3)) * 0.3, rng.standard_normal((6, 3)), rng.standard_normal(),
+                      rng.standard_normal(6)))
+    return cases
+
+
+def test_dual_limiter_choice_matches_the_oracle_scan(harness, tmp_path):
+    """The kernels' dual Barth-Jespersen choice (two candidate faces, an
+    exact tie between them to the earlier face) against the oracle's scan
+    over faces in local order (R7: 1 wins ties, then the first face), value
+    and tangent (torch.func.jvp of the oracle), on exact same-sign and
+    cross-sign ties in both face orders and on random stencils."""
+    lib, pre = harness
+    from torch.func import jvp
+    cases = _limiter_cases()
+    rng = np.random.default_rng(12)
+    W = np.stack([c[0] for c in cases]); dxf = np.stack([c[1] for c in cases])
+    qc = np.array([c[2] for c in cases]); qn = np.stack([c[3] for c in cases])
+    qcd = rng.standard_normal(len(cases)); qnd = rng.standard_normal((len(cases), 6))
+    inp, out, script = tmp_path / "lim.npz", tmp_path / "lim.npy", tmp_path / "lim.py"
+    np.savez(inp, W=W.reshape(len(cases), 18), dxf=dxf.reshape(len(cases), 18), qc=qc, qcd=qcd, qn=qn, qnd=qnd)
+    script.write_text(LIMITER_RUNNER.format(lib=lib, inp=str(inp), out=str(out)))
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    got = np.load(out)
+    Wt, dxt = torch.tensor(W), torch.tensor(dxf)
+
+    def glim(qc_, qn_):
+        g = torch.einsum("nfa,nf->na", Wt, qn_ - qc_[:, None])
+        # one variable: the oracle's shapes carry a variable axis of length 1
+        phi = mhd.barth_jespersen(qc_[:, None], qn_[:, :, None], g[:, None, :], dxt)[:, 0]
+        return g * phi[:, None]
+
+    val, tan = jvp(glim, (torch.tensor(qc), torch.tensor(qn)), (torch.tensor(qcd), torch.tensor(qnd)))
+    assert np.abs(got[:, :3] - val.numpy()).max() <= 1e-14 * max(1.0, float(np.abs(val.numpy()).max()))
+    err_t = np.abs(got[:, 3:] - tan.numpy()) / np.maximum(np.abs(tan.numpy()).max(1, keepdims=True), 1e-300)
+    assert err_t.max() <= 1e-13, f"tangent differs: {err_t.max():.2e} in case {int(err_t.max(1).argmax())}"
