@@ -145,12 +145,14 @@ __host__ __device__ __forceinline__ void load_cons(const MarchArgs& a, int64_t c
 template <class T>
 struct FusedWG {
   // LDS in units of T: block primitives of three layers (rotating by k mod 3,
-  // 3 x 9 x 256), outer slots of layer k (9 x 64), the exchanged face states
+  // 3 x 9 x 256), outer slots of layer k (9 rows of 64 at the planes' row
+  // stride of 256, so that a neighbour's nine values sit at one base plus
+  // fixed offsets whether it is a block lane or an outer slot), the exchanged face states
   // (west: inner lanes' west state, ring lanes' state on the shared face;
   // south: inner lanes' south state; 9 x 256 each), and the face fluxes
   // signed from lane t toward its east (t + 1) and north (t + 16) neighbour
   // (9 x 256 each)
-  static constexpr int kPL = 0, kPO = kPL + 3 * 9 * kFL, kSW = kPO + 9 * kOuterSlots, kSS = kSW + 9 * kFL,
+  static constexpr int kPL = 0, kPO = kPL + 3 * 9 * kFL, kSW = kPO + 9 * kFL, kSS = kSW + 9 * kFL,
                        kFE = kSS + 9 * kFL, kFN = kFE + 9 * kFL, kTot = kFN + 9 * kFL;
   static constexpr int kLds = kTot * int(sizeof(T) / sizeof(double));
 
@@ -252,7 +254,7 @@ struct FusedWG {
     if (st.obase >= 0) {
       T q[9];
       cons_to_prim(st.On, q, a.d.pr.gamma);
-      for (int v = 0; v < 9; ++v) L[kPO + v * kOuterSlots + t] = q[v];
+      for (int v = 0; v < 9; ++v) L[kPO + v * kFL + t] = q[v];
       if (k + 1 < g.Nr) load_cons(a, st.obase + int64_t(k + 1) * g.N * g.N, st.On);
     }
     (void)tm;
@@ -260,7 +262,7 @@ struct FusedWG {
 
   // value of variable v of layer k at block position pos (or outer slot)
   __host__ __device__ static T at(const T* L, int pos, int v, int k) {
-    return pos < kFL ? L[plane(k) + v * kFL + pos] : L[kPO + v * kOuterSlots + (pos - kFL)];
+    return L[(pos < kFL ? plane(k) + pos : kPO + (pos - kFL)) + v * kFL];
   }
 
   // -------------------------------------------------------------- gradient
@@ -408,8 +410,9 @@ struct FusedWG {
       // an inner lane's flux leaves it eastward; a ring lane's leaves the
       // inner cell through its west / south face, toward the ring lane
       const bool neg = inner ? !own : own;
+      const double sg = neg ? -1.0 : 1.0;  // a product by +-1: the same bits as the negation
       for (int v = 0; v < 9; ++v) {
-        const T f = neg ? -F[v] : F[v];
+        const T f = F[v] * sg;
         if (inner) st.acc[v] += f;
         L[(inner || west ? kFE : kFN) + v * kFL + t] = f;
       }
@@ -423,8 +426,9 @@ struct FusedWG {
       T qo[9], F[9];
       for (int v = 0; v < 9; ++v) qo[v] = L[(ring_n ? kSW : kSS) + v * kFL + t + kFB];
       face_flux(own, st.qN, qo, S, F, a.d.pr);
+      const double sg = own ? 1.0 : -1.0;
       for (int v = 0; v < 9; ++v) {
-        const T f = own ? F[v] : -F[v];
+        const T f = F[v] * sg;
         st.acc[v] += f;
         L[kFN + v * kFL + t] = f;
       }

@@ -10,7 +10,7 @@
 // chunk of layers [k0, k1) also evaluates the gradient of the layer below it
 // (for the state on its bottom face) and of the layer above it (for its top
 // face); those layers take no fluxes.  One workgroup per CU: the block keeps
-// three layers of primitives and the exchange buffers in LDS (134 KB).
+// three layers of primitives and the exchange buffers in LDS (148 KB).
 #include "cfv_fused.hpp"
 
 namespace cfv {
