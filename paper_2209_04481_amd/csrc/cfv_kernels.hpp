@@ -160,7 +160,7 @@ __host__ __device__ __forceinline__ void limited_grad(const LsqWeights& L, const
   const double lhs = down * bd, rhs = bn * adlo;
   if (lhs < rhs || (lhs == rhs && pick == 1 && flo < fhi)) pick = 2;
   if (pick == 0) return;
-  const T phi = pick == 1 ? (qmax - qc) * recip(dhi) : (qmin - qc) * recip(dlo);
+  const T phi = pick == 1 ? ratio_refined(qmax - qc, dhi) : ratio_refined(qmin - qc, dlo);
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 
@@ -201,7 +201,7 @@ __host__ __device__ __forceinline__ void limited_grad<double>(const LsqWeights& 
     bn = down;
     bd = ad;
   }
-  const double phi = bn * recip(bd);
+  const double phi = ratio_refined(bn, bd);
   gx = phi * gx; gy = phi * gy; gz = phi * gz;
 }
 

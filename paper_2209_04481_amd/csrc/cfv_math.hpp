@@ -111,6 +111,18 @@ __host__ __device__ __forceinline__ Dual recip(Dual b) {
   return Dual(r, -(b.d * r) * r);
 }
 
+// n / d for |n| <= |d| (a limiter ratio) by the refined reciprocal.  A
+// subnormal d's reciprocal overflows, so d below 2^-1000 is first scaled,
+// with n, by 2^64 (exact); for every other d the bits are n * recip(d).
+__host__ __device__ __forceinline__ double ratio_refined(double n, double d) {
+  const double s = ::fabs(d) < 0x1p-1000 ? 0x1p+64 : 1.0;
+  return (n * s) * recip_refined(d * s);
+}
+__host__ __device__ __forceinline__ Dual ratio_refined(Dual n, Dual d) {
+  const double s = ::fabs(d.v) < 0x1p-1000 ? 0x1p+64 : 1.0;
+  return (n * s) * recip(d * s);
+}
+
 __host__ __device__ __forceinline__ double val(double a) { return a; }
 __host__ __device__ __forceinline__ double val(Dual a) { return a.v; }
 __host__ __device__ __forceinline__ double dsqrt(double a) { return sqrt_nonneg(a); }

@@ -225,7 +225,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
       const double den = pick == 1 ? dhi : pick == 2 ? dlo : 1.0;
       // phi as limited_grad takes it (num and den share their sign)
       const double rd = recip(den);
-      const double phi = act >= 0 ? num * rd : 1.0;
+      const double phi = act >= 0 ? ratio_refined(num, den) : 1.0;
       const double phib = gbx * gx + gby * gy + gbz * gz;
       gbx *= phi; gby *= phi; gbz *= phi;
       if (act >= 0) {

@@ -109,6 +109,32 @@ def test_vjp_parity_tiny(tiny):
     assert float(e1.max()) <= TOL and float(e2.max()) <= TOL
 
 
+def test_parity_with_subnormal_limiter_ratios():
+    """psi as noise at the 1e-310 scale: its gradient projections on the faces
+    are subnormal and its local maxima have a zero limiter numerator, so the
+    limiter's ratio has a subnormal denominator (whose reciprocal alone would
+    overflow).  R (fused march, and the value part of the dual march) stays
+    finite and matches the oracle, and so does Jv along a direction scaled
+    like U (along a raw N(0,1) direction, and for the VJP, the exact
+    derivative of the ratio, about 1/d, overflows in the oracle too)."""
+    print("case: subnormal psi 6x5x5x6", flush=True)
+    inst = ci.make_instance(5, 6, "log", lmax=3, seed=41)
+    inst.U[8] = 1e-310 * np.random.default_rng(41).standard_normal(inst.ncells)
+    c = Case(inst)
+    R = c.ctx.residual(c.Ud).cpu()
+    Ro = mhd.residual(c.og, c.U, c.br, c.op)
+    v = torch.tensor(ci.scaled_direction(inst.U, 41))
+    Rj = torch.empty_like(c.Ud)
+    Jv = c.ctx.jvp(c.Ud, v.cuda(), R=Rj).cpu()
+    Jo, _ = solve.jvp(c.og, c.U, c.br, c.op, v)
+    for name, a, b in (("R", R, Ro), ("R (dual march)", Rj.cpu(), Ro), ("Jv", Jv, Jo)):
+        assert bool(torch.isfinite(b).all()), f"oracle {name} not finite"
+        assert bool(torch.isfinite(a).all()), f"{name} not finite"
+        err = float(rel_err_per_var(a, b).max())
+        print(f"  {name} rel err {err:.2e}")
+        assert err <= TOL, name
+
+
 def test_dot_product_identity_tiny(tiny):
     gen = torch.Generator().manual_seed(2)
     v = torch.randn(9, tiny.inst.ncells, dtype=torch.float64, generator=gen).cuda()
