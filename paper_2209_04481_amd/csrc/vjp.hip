@@ -34,10 +34,19 @@ __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double*
   const int64_t nc = d.g.ncells;
   const int64_t c0 = int64_t(blockIdx.x) * kVBlock, c = c0 + threadIdx.x;
   if (c < nc) {
-    for (int r = 0; r < 9; ++r) lW[r * kVBlock + threadIdx.x] = W[r * nc + c];
-    for (int r = 0; r < 54; ++r) lW[(9 + r) * kVBlock + threadIdx.x] = Q[r * nc + c];
+    // every load of the window issued before the first LDS store (one memory
+    // latency for the 72 rows, not one per batch of rows)
+    double t[72];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = w[r * nc + c];
+    for (int r = 0; r < 9; ++r) t[r] = gld(W, r * nc + c);
+#pragma unroll
+    for (int r = 0; r < 54; ++r) t[9 + r] = gld(Q, r * nc + c);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) t[63 + r] = gld(w, r * nc + c);
+#pragma unroll
+    for (int r = 0; r < 63; ++r) lW[r * kVBlock + threadIdx.x] = t[r];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = t[63 + r];
   }
   __syncthreads();
   if (c < nc) adjoint_cell(d, w, W, Q, A, Gg, c, lW, lw, c0);
