@@ -34,7 +34,7 @@ __host__ __device__ __forceinline__ void flux_side_adjoint(const double q[9], V3
   // the roots with 1/(2 root) from the same sequence (hsd only where disc > 0)
   double hsd = 0.0, hcf;
   const double sd = disc > 0.0 ? sqrt_nonneg(disc, &hsd) : 0.0;
-  const double cf = sqrt_nonneg(0.5 * (s + sd), &hcf);
+  (void)sqrt_nonneg(0.5 * (s + sd), &hcf);  // c_f itself is not needed, only 1/(2 c_f)
 
   // adjoints of the intermediates from the flux components
   double rvnb = Fb[0] + Fb[1] * vx + Fb[2] * vy + Fb[3] * vz;
