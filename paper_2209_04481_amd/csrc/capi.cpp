@@ -104,6 +104,7 @@ struct cfv_ctx {
   double* dbth = nullptr;  // inner B_theta map (large-E law), zero until set
   double* W = nullptr;     // 36 ncells: primitives + limited gradients
   double* Wd = nullptr;    // 36 ncells: their tangents
+  double* E = nullptr;     // dual march: tile-edge face states (edge_buffer_doubles)
   double* A = nullptr;     // adjoint workspace
   double* part = nullptr;  // reduction partials
   int part_vectors = 0;
@@ -307,7 +308,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
       (st = dmalloc(&c->dr, g->r.size())) ||
       (st = dmalloc(&c->dbr, size_t(g->g.nb))) || (st = dmalloc(&c->dbth, size_t(g->g.nb))) ||
       (st = dmalloc(&c->W, size_t(36) * nc)) ||
-      (st = dmalloc(&c->Wd, size_t(36) * nc)) ||
+      (st = dmalloc(&c->Wd, size_t(36) * nc)) || (st = dmalloc(&c->E, size_t(cfv::edge_buffer_doubles(g->g)))) ||
       (st = dmalloc(&c->A, size_t(cfv::vjp_workspace_doubles(g->g)))) ||
       (st = dmalloc(&c->part, size_t(c->part_vectors) * cfv::reduce_partials_per_vector())) ||
       (st = dmalloc(&c->slot, 1)) || (st = dmalloc(&c->dflag, 1)) || (st = dmalloc(&c->dftab, g->ftab.size()))) {
@@ -332,7 +333,7 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
 
 void cfv_ctx_destroy(cfv_ctx* c) {
   if (!c) return;
-  double* bufs[] = {c->dcg, c->dr, c->dbr, c->dbth, c->W, c->Wd, c->A, c->part};
+  double* bufs[] = {c->dcg, c->dr, c->dbr, c->dbth, c->W, c->Wd, c->E, c->A, c->part};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->dcn) (void)hipFree(c->dcn);
@@ -382,6 +383,7 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !v || !Jv) return fail(CFV_ERR_ARG, "null state, direction or output");
   cfv::MarchArgs a{c->dev(), U, v, dbr, c->W, c->Wd, R, Jv};
+  a.E = c->E;
   CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   return CFV_OK;
 }
@@ -495,6 +497,7 @@ static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag
     CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
+    a.E = c->E;
     CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   CFV_HIP(cfv::launch_add_diag(c->grid->g.ncells, diag, x, w, s));
@@ -801,12 +804,14 @@ cfv_status cfv_jvp_dir(cfv_ctx* c, const double* U, const double* v, const doubl
   CFV_HIP(cfv::launch_axpby(n, h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dp, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, Jv2};
+    a.E = c->E;
     CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, dU, 1.0, c->dir_u, s));
   {
     cfv::MarchArgs a{dm, c->dir_u, v, nullptr, c->W, c->Wd, nullptr, c->dir_g};
+    a.E = c->E;
     CFV_HIP(cfv::launch_march(a, c->slot, true, c->march_chunk(true), s, c->tm()));
   }
   const double ih = 0.5 / h;
@@ -1113,6 +1118,7 @@ cfv_status cfv_ensemble_bind(cfv_ensemble* e, const double* const* U, const doub
       return fail(CFV_ERR_ARG, "null pointer for instance " + std::to_string(q));
     h[q] = cfv::MarchArgs{c->dev(), U[q], dual ? v[q] : nullptr, dbr ? dbr[q] : nullptr, c->W,
                           dual ? c->Wd : nullptr, R ? R[q] : nullptr, dual ? Jv[q] : nullptr};
+    h[q].E = dual ? c->E : nullptr;
     h[q].d.flag = e->dflags + q;
   }
   CFV_HIP(hipMemcpy(e->dargs, h.data(), n * sizeof(cfv::MarchArgs), hipMemcpyHostToDevice));
@@ -1198,9 +1204,11 @@ cfv_status cfv_ensemble_bind_be_step(cfv_ensemble* e, const double* const* U, do
     cfv::DevGrid d = c->dev();
     d.flag = e->dflags + q;
     args[q] = cfv::MarchArgs{d, U[q], nullptr, nullptr, c->W, nullptr, U_new[q], nullptr};
-    for (int j = 0; j < m; ++j)
+    for (int j = 0; j < m; ++j) {
       args[size_t(1 + j) * n + q] =
           cfv::MarchArgs{d, U[q], e->precond ? v.z : v.V + size_t(j) * n9, nullptr, c->W, c->Wd, nullptr, v.w};
+      args[size_t(1 + j) * n + q].E = c->E;
+    }
     L.dev.push_back(d);
     L.Uh.push_back(U[q]);
     L.diagh.push_back(diag);

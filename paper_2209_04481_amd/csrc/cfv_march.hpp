@@ -20,11 +20,33 @@ struct MarchArgs {
   double* Rd;         // tangent of the residual (Dual only)
   double* P = nullptr;  // primitives [9][ncells] written by the gradient pass (nullable)
   double* Q = nullptr;  // face states [6 x 9][ncells] (row 9 lf + v) written by the face-state gradient pass
+  double* E = nullptr;  // dual march: tile-edge face states (edge_buffer_doubles), written by the gradient
+                        // pass, read by the flux pass's ring
 };
 
 struct TileMap {
   int p, j0, i0, k0, k1;
 };
+
+// Tile-edge face states of the dual march: for every tile, layer and edge
+// slot (64 slots: 16 east faces of the last column by row, 16 north faces of
+// the last row by column, 16 west faces of the first column by row, 16 south
+// faces of the first row by column), the edge cell's state on that face (9
+// values, then their 9 tangents), at [tile][layer][18][64].  The gradient
+// pass writes them (its edge cells have their limited gradients at hand);
+// the flux pass's ring reads a neighbour tile's 18 contiguous rows instead of
+// that cell's primitives and gradients (72 values, strided by N along the
+// tile's east and west edges).
+constexpr int kEdgeSlots = 64, kEdgeLayer = 18 * kEdgeSlots;
+__host__ __device__ __forceinline__ int march_tiles_1d(int N) { return (N + 15) / 16; }
+__host__ __device__ __forceinline__ int64_t edge_buffer_doubles(const Shape& g) {
+  const int64_t nt = march_tiles_1d(g.N);
+  return 6 * nt * nt * int64_t(g.Nr) * kEdgeLayer;
+}
+__host__ __device__ __forceinline__ int64_t march_tile_index(const Shape& g, int p, int j0, int i0) {
+  const int64_t nt = march_tiles_1d(g.N);
+  return (int64_t(p) * nt + j0 / 16) * nt + i0 / 16;
+}
 
 // work items (tile, chunk of kc layers) of one instance
 __host__ __device__ __forceinline__ int64_t march_logical_blocks(const Shape& g, int kc) {
@@ -144,6 +166,7 @@ struct GState {
   bool act;
   T Pm[9], P0[9], Pp[9];
   int64_t rc0;  // ring threads: the ring slot's cell at layer 0 (-1: no slot)
+  unsigned emask;  // dual pass: the tile edges the cell lies on (bit = edge slot kind 0..3)
   // the column's geometry per item (centroid sum, radial face centroid per
   // unit radius, angular face-centroid offsets per unit rs_k)
   V3 cc, xr, fe[4];
@@ -189,6 +212,12 @@ struct GradWG {
     st.i = tm.i0 + ti;
     st.act = st.j < g.N && st.i < g.N;
     st.rc0 = -1;
+    {
+      // east (kind 0), north (1), west (2), south (3) tile edges of the cell
+      const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
+      const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
+      st.emask = unsigned(ti == tiL) | unsigned(tj == tjL) << 1 | unsigned(ti == 0) << 2 | unsigned(tj == 0) << 3;
+    }
     if (t >= kNT / 4 && t < kNT / 2) {  // the ring slot's neighbour cell, decoded once per item
       int ti2, tj2, q;
       int64_t ncol;
@@ -276,7 +305,7 @@ struct GradWG {
   // gradients to a.G (the VJP's forward pass; a separate instantiation so
   // that the residual's pass does not carry the stores' registers)
   template <bool Faces = false>
-  __host__ __device__ static void compute(const MarchArgs& a, const TileMap&, GState<T>& st, int t, int k,
+  __host__ __device__ static void compute(const MarchArgs& a, const TileMap& tm, GState<T>& st, int t, int k,
                                           double* lds) {
     if (!st.act) return;
     const Shape& g = a.d.g;
@@ -348,6 +377,22 @@ struct GradWG {
         stT(a.G, a.Gd, (3 * v) * g.ncells + c, gx);
         stT(a.G, a.Gd, (3 * v + 1) * g.ncells + c, gy);
         stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
+        if constexpr (sizeof(T) > sizeof(double)) {
+          // the states on the cell's tile-edge faces (the same expression as
+          // the flux pass's reconstruction) for the neighbour tiles' rings
+          if (a.E && st.emask) {
+            const int64_t eb = (march_tile_index(g, tm.p, tm.j0, tm.i0) * g.Nr + k) * kEdgeLayer;
+#pragma unroll
+            for (int kind = 0; kind < 4; ++kind) {
+              if (!((st.emask >> kind) & 1u)) continue;
+              const int lf = kind == 0 ? 3 : kind == 1 ? 5 : kind == 2 ? 2 : 4;  // E, N, W, S
+              const T qf = st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z);
+              const int slot = kind * 16 + ((kind & 1) ? ti : tj);
+              gst(a.E, eb + v * kEdgeSlots + slot, qf.v);
+              gst(a.E, eb + (9 + v) * kEdgeSlots + slot, qf.d);
+            }
+          }
+        }
       } else {  // instead of the gradient, the reconstructed state at each face centroid
 #pragma unroll
         for (int lf = 0; lf < 6; ++lf) {
@@ -376,8 +421,7 @@ struct FState {
   T acc[9];   // residual of layer k so far
   T q3[9], q5[9];
   bool bad;   // a face state of this column met a non-positive density or pressure
-  int64_t rc0;   // ring threads: the ring slot's neighbour cell at layer 0 (-1: no slot)
-  int32_t rcol;  // and its column
+  int64_t ebase;  // ring threads: the slot's state in the edge buffer at layer 0 (-1: no slot)
 };
 
 template <class T>
@@ -415,37 +459,16 @@ struct FluxWG {
     return (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
   }
 
-  // state of cell c (column col, layer k) reconstructed at the face centroid xf
-  __host__ __device__ static void remote_state_at(const MarchArgs& a, int64_t c, int32_t col, int k, V3 xf, T q[9]) {
-    const GeomRef& G = a.d.G;
-    T P[9], Gr[27];
-    load_prims(a, c, P);
-    load_grad(a, c, Gr);
-    recon(P, Gr, xf - (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * cg3(G, CG_CSUM, col), q);
-  }
-
   // ring slot r of layer k: the state of the out-of-tile neighbour across
-  // one edge face of the tile, on that face (one wavefront loads all 64)
+  // one edge face of the tile, on that face, as the neighbour tile's
+  // gradient pass left it in the edge buffer (one wavefront loads all 64)
   __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, const FState<T>& st, int r, int k,
                                        double* lds) {
-    const Shape& g = a.d.g;
-    if (st.rc0 < 0) return;
-    const int kind = r >> 4, idx = r & 15;
-    const int tiL = last_ti(g, tm), tjL = last_tj(g, tm);
-    // kind 0: east face of row idx's last cell; 1: north face of column idx's
-    // last cell; 2: west face of row idx's first cell; 3: south face of
-    // column idx's first cell
-    const int ti = kind == 0 ? tiL : kind == 2 ? 0 : idx;
-    const int tj = kind == 1 ? tjL : kind == 3 ? 0 : idx;
-    const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
-    const int j = tm.j0 + tj, i = tm.i0 + ti;
-    V3 S, xf;
-    bool own;
-    canon_face(a.d.G, g, tm.p, k, j, i, 2 + q, Nbr{}, 0, S, xf, own);
-    T qo[9];
-    remote_state_at(a, st.rc0 + int64_t(k) * g.N * g.N, st.rcol, k, xf, qo);
+    if (st.ebase < 0) return;
+    const int64_t e = st.ebase + int64_t(k) * kEdgeLayer;
     T* Rg = lds_as<T>(lds) + kRingOff;
-    for (int v = 0; v < 9; ++v) Rg[v * kRing + r] = qo[v];
+    for (int v = 0; v < 9; ++v) ldT(a.E, a.E + 9 * kEdgeSlots, e + v * kEdgeSlots, Rg[v * kRing + r]);
+    (void)tm;
   }
 
   __host__ __device__ static void init(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t) {
@@ -456,16 +479,20 @@ struct FluxWG {
     st.act = st.j < g.N && st.i < g.N;
     st.bad = false;
     for (int v = 0; v < 9; ++v) st.qtop[v] = T(0.0);
-    st.rc0 = -1;
-    st.rcol = 0;
-    if (t >= kNT / 4 && t < kNT / 4 + kRing) {  // the ring's neighbour cell, decoded once per item
+    st.ebase = -1;
+    if (t >= kNT / 4 && t < kNT / 4 + kRing) {  // the ring slot's source in the edge buffer, once per item
       int ti, tj, q;
       int64_t ncol;
       if (ring_slot(a, tm, t - kNT / 4, ti, tj, q, ncol)) {
+        // the neighbour cell, its tile and the edge slot of its face back
+        // toward this tile (local faces 2..5: W, E, S, N)
         int np, nj, ni;
         column_pji(g, ncol, np, nj, ni);
-        st.rc0 = cell_index(g, np, 0, nj, ni);
-        st.rcol = int32_t(ncol);
+        const int back = (gld(a.d.G.cn, (4 + q) * a.d.G.ncol + column_of(g, tm.p, tm.j0 + tj, tm.i0 + ti)) & 0xff) - 2;
+        const int kind = back == 1 ? 0 : back == 3 ? 1 : back == 0 ? 2 : 3;
+        const int slot = kind * 16 + ((kind & 1) ? ni % 16 : nj % 16);
+        const int64_t tile = march_tile_index(g, np, nj - nj % 16, ni - ni % 16);
+        st.ebase = tile * g.Nr * kEdgeLayer + slot;
       }
     }
   }

@@ -172,6 +172,7 @@ hipError_t launch_march_ensemble(const EnsembleLaunch& e, bool dual, hipStream_t
 // persistent kernels run with one workgroup per item (no queue, no table).
 hipError_t launch_march(const MarchArgs& a, MarchArgs* slot, bool dual, int kc, hipStream_t s, KernelTimer* t) {
   if (!dual) return launch_fused(a, slot, kc, s, t);  // the residual: one fused pass (fused.hip)
+  if (!a.E) return hipErrorInvalidValue;  // the flux pass's ring reads the tile-edge states
   hipLaunchKernelGGL(put_args_kernel, dim3(1), dim3(64), 0, s, a, slot);
   const int64_t total = march_logical_blocks(a.d.g, kc);
   EnsembleLaunch e{slot, nullptr, nullptr, nullptr, 1, total, 0, unsigned(march_blocks(a.d.g, kc)), kc};

@@ -219,7 +219,9 @@ int host_jvp(int N, int Nr, const double* r, const cfv_params* p, const double* 
   if (!s.ok) return 1;
   const int64_t nc = s.t.g.ncells;
   std::vector<double> G(size_t(27) * nc, kPoison), Gd(size_t(27) * nc, kPoison);
+  std::vector<double> E(size_t(edge_buffer_doubles(s.t.g)), kPoison);
   MarchArgs a{s.d, U, v, dbr, G.data(), Gd.data(), R, Jv};
+  a.E = E.data();
   grad_march<Dual>(a, kc);
   flux_march<Dual>(a, kc);
   return 0;
