@@ -167,6 +167,9 @@ struct GState {
   T Pm[9], P0[9], Pp[9];
   int64_t rc0;  // ring threads: the ring slot's cell at layer 0 (-1: no slot)
   unsigned emask;  // dual pass: the tile edges the cell lies on (bit = edge slot kind 0..3)
+  int es0, es1;    // dual pass: the edge slots of the first two of them (-1: none)
+  unsigned erest;  // and the others (one-cell-wide tiles only)
+  V3 fe0, fe1;     // their face-centroid offsets per unit rs_k
   // the column's geometry per item (centroid sum, radial face centroid per
   // unit radius, angular face-centroid offsets per unit rs_k)
   V3 cc, xr, fe[4];
@@ -197,7 +200,10 @@ struct GradWG {
   static constexpr int kTw = int(sizeof(T) / sizeof(double));
   // primitives plane (9 T per position), then the column centroid sums (3)
   static constexpr int kCs = 9 * kPlane * kTw;
-  static constexpr int kLds = kCs + 3 * kPlane;
+  // dual pass: a layer's tile-edge face states, staged for one coalesced
+  // write ([18][64] doubles, the edge buffer's layout)
+  static constexpr int kEs = kCs + 3 * kPlane;
+  static constexpr int kLds = kEs + (sizeof(T) > sizeof(double) ? kEdgeLayer : 0);
 
   __host__ __device__ static bool in_tile_active(const Shape& g, const TileMap& tm, int ti, int tj) {
     return ti >= 0 && ti < kTI && tj >= 0 && tj < kTJ && tm.i0 + ti < g.N && tm.j0 + tj < g.N;
@@ -217,6 +223,8 @@ struct GradWG {
       const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
       const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
       st.emask = unsigned(ti == tiL) | unsigned(tj == tjL) << 1 | unsigned(ti == 0) << 2 | unsigned(tj == 0) << 3;
+      st.es0 = st.es1 = -1;
+      st.erest = 0;
     }
     if (t >= kNT / 4 && t < kNT / 2) {  // the ring slot's neighbour cell, decoded once per item
       int ti2, tj2, q;
@@ -245,6 +253,18 @@ struct GradWG {
     st.cc = c0;
     st.xr = cg3(G, CG_XR, st.col);
     for (int q = 0; q < 4; ++q) st.fe[q] = 2.0 * cg3(G, CG_ANG + 6 * q + 3, st.col) - c0;
+    // the first two tile edges of the cell as slots and face offsets (kind
+    // 0..3: east, north, west, south faces, q = 1, 3, 0, 2)
+    st.fe0 = st.fe1 = mk(0.0, 0.0, 0.0);
+    for (int kind = 0; kind < 4; ++kind) {
+      if (!((st.emask >> kind) & 1u)) continue;
+      const int q = kind == 0 ? 1 : kind == 1 ? 3 : kind == 2 ? 0 : 2;
+      const int slot = kind * 16 + ((kind & 1) ? ti : tj);
+      const V3 f = q == 0 ? st.fe[0] : q == 1 ? st.fe[1] : q == 2 ? st.fe[2] : st.fe[3];
+      if (st.es0 < 0) { st.es0 = slot; st.fe0 = f; }
+      else if (st.es1 < 0) { st.es1 = slot; st.fe1 = f; }
+      else st.erest |= 1u << kind;
+    }
   }
 
   // First layer of the march of a chunk [k0, k1): the layers k0 - 1 and k0
@@ -379,17 +399,30 @@ struct GradWG {
         stT(a.G, a.Gd, (3 * v + 2) * g.ncells + c, gz);
         if constexpr (sizeof(T) > sizeof(double)) {
           // the states on the cell's tile-edge faces (the same expression as
-          // the flux pass's reconstruction) for the neighbour tiles' rings
-          if (a.E && st.emask) {
-            const int64_t eb = (march_tile_index(g, tm.p, tm.j0, tm.i0) * g.Nr + k) * kEdgeLayer;
+          // the flux pass's reconstruction) for the neighbour tiles' rings,
+          // staged in LDS (flush_edges writes the layer's block)
+          double* Es = lds + kEs;
+          if (st.es0 >= 0) {  // rs_k fe is dxf of that face: the same products
+            const V3 d0 = rs * st.fe0;
+            const T qf = st.P0[v] + (gx * d0.x + gy * d0.y + gz * d0.z);
+            Es[v * kEdgeSlots + st.es0] = qf.v;
+            Es[(9 + v) * kEdgeSlots + st.es0] = qf.d;
+          }
+          if (st.es1 >= 0) {
+            const V3 d1 = rs * st.fe1;
+            const T qf = st.P0[v] + (gx * d1.x + gy * d1.y + gz * d1.z);
+            Es[v * kEdgeSlots + st.es1] = qf.v;
+            Es[(9 + v) * kEdgeSlots + st.es1] = qf.d;
+          }
+          if (st.erest) {
 #pragma unroll
             for (int kind = 0; kind < 4; ++kind) {
-              if (!((st.emask >> kind) & 1u)) continue;
+              if (!((st.erest >> kind) & 1u)) continue;
               const int lf = kind == 0 ? 3 : kind == 1 ? 5 : kind == 2 ? 2 : 4;  // E, N, W, S
               const T qf = st.P0[v] + (gx * dxf[lf].x + gy * dxf[lf].y + gz * dxf[lf].z);
               const int slot = kind * 16 + ((kind & 1) ? ti : tj);
-              gst(a.E, eb + v * kEdgeSlots + slot, qf.v);
-              gst(a.E, eb + (9 + v) * kEdgeSlots + slot, qf.d);
+              Es[v * kEdgeSlots + slot] = qf.v;
+              Es[(9 + v) * kEdgeSlots + slot] = qf.d;
             }
           }
         }
@@ -406,6 +439,25 @@ struct GradWG {
     for (int v = 0; v < 9; ++v) {
       st.Pm[v] = st.P0[v];
       st.P0[v] = st.Pp[v];
+    }
+    (void)tm;
+  }
+
+  // dual pass, after the barrier that ends layer k's compute step: lanes
+  // 128..191 write the layer's staged tile-edge states (slots of edge cells
+  // beyond a partial tile hold stale values that no ring reads)
+  __host__ __device__ static void flush_edges(const MarchArgs& a, const TileMap& tm, int t, int k,
+                                              const double* lds) {
+    if constexpr (sizeof(T) > sizeof(double)) {
+      if (!a.E || t < 2 * kEdgeSlots || t >= 3 * kEdgeSlots) return;
+      const Shape& g = a.d.g;
+      const int r = t - 2 * kEdgeSlots;
+      const int64_t eb = (march_tile_index(g, tm.p, tm.j0, tm.i0) * g.Nr + k) * kEdgeLayer + r;
+      const double* Es = lds + kEs;
+#pragma unroll
+      for (int row = 0; row < 18; ++row) gst(a.E, eb + row * kEdgeSlots, Es[row * kEdgeSlots + r]);
+    } else {
+      (void)a; (void)tm; (void)t; (void)k; (void)lds;
     }
   }
 };

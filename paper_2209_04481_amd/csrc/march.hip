@@ -44,6 +44,9 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
     // the plane is written again by the next layer (a second plane to drop
     // this barrier made both gradient passes slower: more LDS per workgroup)
     __syncthreads();
+    // the dual pass's staged tile-edge states, written again only after the
+    // next layer's first barrier
+    GradWG<T>::flush_edges(a, tm, t, k, lds);
   }
 }
 

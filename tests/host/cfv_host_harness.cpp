@@ -120,19 +120,22 @@ void grad_march(const MarchArgs& a, int kc) {
     tile_of_logical(g, l, tm, kc);
     std::fill(lds.begin(), lds.end(), kPoison);
     // two barriers per layer (after the publish and ring steps, after the
-    // compute): a segment is the warm-up and this layer's publish and ring,
-    // or its compute
-    for (int k = tm.k0; k < tm.k1; ++k) {
+    // compute): a segment is the previous layer's edge flush, the warm-up
+    // and this layer's publish and ring, or its compute
+    for (int k = tm.k0; k <= tm.k1; ++k) {
       lanes(kNT, [&](int t) {
         if (k == tm.k0) {  // the item's start and its warm-up layers
           GradWG<T>::init(a, tm, st[t], t, lds.data());
           for (int kw = GradWG<T>::first_layer(tm); kw < tm.k0; ++kw)
             GradWG<T>::publish(a, tm, st[t], t, kw, lds.data());
         }
-        GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
-        if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+        if (k > tm.k0) GradWG<T>::flush_edges(a, tm, t, k - 1, lds.data());
+        if (k < tm.k1) {
+          GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
+          if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+        }
       });
-      lanes(kNT, [&](int t) { GradWG<T>::template compute<Faces>(a, tm, st[t], t, k, lds.data()); });
+      if (k < tm.k1) lanes(kNT, [&](int t) { GradWG<T>::template compute<Faces>(a, tm, st[t], t, k, lds.data()); });
     }
   }
 }
