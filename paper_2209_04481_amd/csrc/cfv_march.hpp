@@ -274,38 +274,59 @@ struct GradWG {
   __host__ __device__ static int first_layer(const TileMap& tm) { return tm.k0 >= 1 ? tm.k0 - 2 : -1; }
 
   // layer k: load the primitives of layer k + 1; publish layer k's in LDS
-  // (a warm-up iteration only shifts the registers instead)
+  // (a warm-up iteration only shifts the registers instead).  In the dual
+  // pass (one wavefront per SIMD) a ring lane (second wavefront) also fills
+  // its ring position of layer k here, its loads issued before the cell's
+  // own so that both wait for memory once; the plain pass (two wavefronts
+  // per SIMD, the other hides the wait) fills it after publishing
+  // (ring_late), which spills less.
+  static constexpr bool kEarlyRing = sizeof(T) > sizeof(double);
   __host__ __device__ static void publish(const MarchArgs& a, const TileMap& tm, GState<T>& st, int t, int k,
                                           double* lds) {
-    if (!st.act) return;
     const Shape& g = a.d.g;
-    const int ti = t % kTI, tj = t / kTI;
-    if (k + 1 >= 0 && k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
-    if (k < tm.k0) {
-      for (int v = 0; v < 9; ++v) {
-        st.Pm[v] = st.P0[v];
-        st.P0[v] = st.Pp[v];
+    const int64_t nc = g.ncells;
+    const bool rl = kEarlyRing && k >= tm.k0 && st.rc0 >= 0;  // rc0 >= 0: a ring lane with a neighbour
+    T ur[9];
+    if (rl)
+      for (int v = 0; v < 9; ++v) ldT(a.U, a.Ud, v * nc + st.rc0 + int64_t(k) * g.N * g.N, ur[v]);
+    if (st.act) {
+      const int ti = t % kTI, tj = t / kTI;
+      if (k + 1 >= 0 && k + 1 < g.Nr) load_prims(a, cell_index(g, st.p, k + 1, st.j, st.i), st.Pp);
+      if (k < tm.k0) {
+        for (int v = 0; v < 9; ++v) {
+          st.Pm[v] = st.P0[v];
+          st.P0[v] = st.Pp[v];
+        }
+      } else {
+        T* L = lds_as<T>(lds);
+        const int me = plane_pos(ti, tj);
+        for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
+        if (a.P) {
+          const int64_t c = cell_index(g, st.p, k, st.j, st.i);
+          for (int v = 0; v < 9; ++v) gst(a.P, v * g.ncells + c, val(st.P0[v]));
+        }
       }
-      return;
     }
-    T* L = lds_as<T>(lds);
-    const int me = plane_pos(ti, tj);
-    for (int v = 0; v < 9; ++v) L[v * kPlane + me] = st.P0[v];
-    if (a.P) {
-      const int64_t c = cell_index(g, st.p, k, st.j, st.i);
-      for (int v = 0; v < 9; ++v) gst(a.P, v * g.ncells + c, val(st.P0[v]));
-    }
+    if (rl) ring(a, tm, t - kNT / 4, ur, lds);
   }
 
-  // Ring position r of layer k (the plane's out-of-tile neighbours, loaded
-  // by one wavefront in one pass instead of a divergent pass per direction
-  // in every wavefront): kind 0 east of row idx's last cell, 1 north of
+  // the plain pass's ring position r of layer k (the lanes r + kNT / 4)
+  __host__ __device__ static void ring_late(const MarchArgs& a, const TileMap& tm, const GState<T>& st, int r,
+                                            int k, double* lds) {
+    if (kEarlyRing || st.rc0 < 0) return;
+    const Shape& g = a.d.g;
+    T u[9];
+    for (int v = 0; v < 9; ++v) ldT(a.U, a.Ud, v * g.ncells + st.rc0 + int64_t(k) * g.N * g.N, u[v]);
+    ring(a, tm, r, u, lds);
+  }
+
+  // Ring position r of layer k from the neighbour's state u (the plane's
+  // out-of-tile neighbours, filled by one wavefront in one pass instead of a
+  // divergent pass per direction in every wavefront): kind 0 east of row idx's last cell, 1 north of
   // column idx's last cell, 2 west of row idx's first cell, 3 south of
   // column idx's first cell.
-  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, const GState<T>& st, int r, int k,
-                                       double* lds) {
+  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, int r, const T u[9], double* lds) {
     const Shape& g = a.d.g;
-    if (st.rc0 < 0) return;
     const int kind = r >> 4, idx = r & 15;
     const int tiL = (g.N - tm.i0 < kTI ? g.N - tm.i0 : kTI) - 1;
     const int tjL = (g.N - tm.j0 < kTJ ? g.N - tm.j0 : kTJ) - 1;
@@ -315,7 +336,7 @@ struct GradWG {
     int dx, dy;
     dir_offset(q, dx, dy);
     T qn[9];
-    load_prims(a, st.rc0 + int64_t(k) * g.N * g.N, qn);
+    cons_to_prim(u, qn, a.d.pr.gamma);
     T* L = lds_as<T>(lds);
     const int pos = plane_pos(ti + dx, tj + dy);
     for (int v = 0; v < 9; ++v) L[v * kPlane + pos] = qn[v];
@@ -513,14 +534,15 @@ struct FluxWG {
 
   // ring slot r of layer k: the state of the out-of-tile neighbour across
   // one edge face of the tile, on that face, as the neighbour tile's
-  // gradient pass left it in the edge buffer (one wavefront loads all 64)
-  __host__ __device__ static void ring(const MarchArgs& a, const TileMap& tm, const FState<T>& st, int r, int k,
-                                       double* lds) {
-    if (st.ebase < 0) return;
+  // gradient pass left it in the edge buffer (one wavefront loads all 64,
+  // in the states phase)
+  __host__ __device__ static void ring_load(const MarchArgs& a, const FState<T>& st, int k, T q[9]) {
     const int64_t e = st.ebase + int64_t(k) * kEdgeLayer;
+    for (int v = 0; v < 9; ++v) ldT(a.E, a.E + 9 * kEdgeSlots, e + v * kEdgeSlots, q[v]);
+  }
+  __host__ __device__ static void ring_store(int r, const T q[9], double* lds) {
     T* Rg = lds_as<T>(lds) + kRingOff;
-    for (int v = 0; v < 9; ++v) ldT(a.E, a.E + 9 * kEdgeSlots, e + v * kEdgeSlots, Rg[v * kRing + r]);
-    (void)tm;
+    for (int v = 0; v < 9; ++v) Rg[v * kRing + r] = q[v];
   }
 
   __host__ __device__ static void init(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t) {
@@ -563,9 +585,17 @@ struct FluxWG {
   // residual of layer k - 1.  A warm-up layer (k < k0) runs this phase alone
   // for its top-face state, a cool-down layer (k = k1) for the flux through
   // the chunk's top face; what else they compute is overwritten or unused.
+  // A ring lane (second wavefront) of a marched layer also fills its ring
+  // slot, the loads issued with the cell's own (one wait for both).
   __host__ __device__ static void states(const MarchArgs& a, const TileMap& tm, FState<T>& st, int t, int k,
                                          double* lds) {
-    if (!st.act) return;
+    const bool rl = k >= tm.k0 && k < tm.k1 && st.ebase >= 0;  // ebase >= 0: a ring lane with a slot
+    T rq[9];
+    if (rl) ring_load(a, st, k, rq);
+    if (!st.act) {
+      if (rl) ring_store(t - kNT / 4, rq, lds);
+      return;
+    }
     const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     st.col = column_of(g, st.p, st.j, st.i);
@@ -573,6 +603,7 @@ struct FluxWG {
     T u[9], P[9], Gr[27];
     for (int v = 0; v < 9; ++v) ldT(a.U, a.Ud, v * g.ncells + c, u[v]);
     cons_to_prim(u, P, a.d.pr.gamma);
+    if (rl) ring_store(t - kNT / 4, rq, lds);
     load_grad(a, c, Gr);
     const V3 xc = cell_centre(G, g, st.p, k, st.j, st.i);
 

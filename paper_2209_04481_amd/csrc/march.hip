@@ -36,9 +36,11 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
   GState<T> st;
   GradWG<T>::init(a, tm, st, t, lds);
   for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
+    // (the second wavefront also fills the plane's ring of out-of-tile
+    // neighbours: in the dual pass inside publish)
     GradWG<T>::publish(a, tm, st, t, k, lds);
     if (k < tm.k0) continue;  // warm-up: registers only
-    if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
+    if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring_late(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     GradWG<T>::template compute<Faces>(a, tm, st, t, k, lds);
     // the plane is written again by the next layer (a second plane to drop
@@ -57,10 +59,10 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
   FluxWG<T>::init(a, tm, st, t);
   const int kl = FluxWG<T>::last_layer(a.d.g, tm);
   for (int k = FluxWG<T>::first_layer(tm); k <= kl; ++k) {
+    // (the second wavefront also loads the ring of out-of-tile neighbour
+    // states)
     FluxWG<T>::states(a, tm, st, t, k, lds);
     if (k < tm.k0 || k >= tm.k1) continue;  // warm-up or cool-down: registers only
-    // the second wavefront also loads the ring of out-of-tile neighbour states
-    if (t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing) FluxWG<T>::ring(a, tm, st, t - kNT / 4, k, lds);
     __syncthreads();
     FluxWG<T>::faces(a, tm, st, t, k, lds);
     __syncthreads();

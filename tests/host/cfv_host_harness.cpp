@@ -131,8 +131,8 @@ void grad_march(const MarchArgs& a, int kc) {
         }
         if (k > tm.k0) GradWG<T>::flush_edges(a, tm, t, k - 1, lds.data());
         if (k < tm.k1) {
-          GradWG<T>::publish(a, tm, st[t], t, k, lds.data());
-          if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+          GradWG<T>::publish(a, tm, st[t], t, k, lds.data());  // and the dual pass's ring
+          if (t >= kNT / 4 && t < kNT / 2) GradWG<T>::ring_late(a, tm, st[t], t - kNT / 4, k, lds.data());
         }
       });
       if (k < tm.k1) lanes(kNT, [&](int t) { GradWG<T>::template compute<Faces>(a, tm, st[t], t, k, lds.data()); });
@@ -160,9 +160,7 @@ void flux_march(const MarchArgs& a, int kc) {
           for (int kw = kf; kw < tm.k0; ++kw) FluxWG<T>::states(a, tm, st[t], t, kw, lds.data());
         }
         if (k > tm.k0) FluxWG<T>::accumulate(a, tm, st[t], t, k - 1, lds.data());
-        if (k <= kl) FluxWG<T>::states(a, tm, st[t], t, k, lds.data());
-        if (k < tm.k1 && t >= kNT / 4 && t < kNT / 4 + FluxWG<T>::kRing)
-          FluxWG<T>::ring(a, tm, st[t], t - kNT / 4, k, lds.data());
+        if (k <= kl) FluxWG<T>::states(a, tm, st[t], t, k, lds.data());  // and the ring slots
         if (k == tm.k1) FluxWG<T>::finish(a, tm, st[t], t);
       });
       if (k < tm.k1) lanes(kNT, [&](int t) { FluxWG<T>::faces(a, tm, st[t], t, k, lds.data()); });
