@@ -173,16 +173,30 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const LsqWeights Lw(dx);
 
   // ---- per variable: recompute the gradient and limiter choice, then their
-  // adjoint; contributions to the six neighbours are stored at once
+  // adjoint; contributions to the six neighbours are stored at once.  The
+  // neighbours' values of variable v + 2 are loaded before variable v's
+  // arithmetic, so the loads of later variables are in flight while earlier
+  // ones compute (one wait per variable had left them exposed).
+  auto neighbour_values = [&](int v, double q[6]) {
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) {
+      if (lf == 0 && bin) q[lf] = qGin[v];
+      else if (lf == 1 && bout) q[lf] = qGout[v];
+      else q[lf] = lf < 2 ? gld(W, v * nc + nid[lf]) : Wr(v, nid[lf]);
+    }
+  };
+  double qn1[6], qn2[6];  // variables v + 1 and v + 2
+  neighbour_values(0, qn1);
+  neighbour_values(1, qn2);
 #pragma unroll
   for (int v = 0; v < 9; ++v) {
     double qn[6];
 #pragma unroll
     for (int lf = 0; lf < 6; ++lf) {
-      if (lf == 0 && bin) qn[lf] = qGin[v];
-      else if (lf == 1 && bout) qn[lf] = qGout[v];
-      else qn[lf] = lf < 2 ? gld(W, v * nc + nid[lf]) : Wr(v, nid[lf]);
+      qn[lf] = qn1[lf];
+      qn1[lf] = qn2[lf];
     }
+    if (v + 2 < 9) neighbour_values(v + 2, qn2);
     const double qc = Pc[v];
     double gx = 0.0, gy = 0.0, gz = 0.0, qmax = qc, qmin = qc;
     int amax = -1, amin = -1;
