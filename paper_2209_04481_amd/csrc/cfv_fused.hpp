@@ -114,7 +114,7 @@ struct FuState {
 __host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, const Shape& g, int k, V3 cc, V3 sr,
                                                           V3 xr, const V3 dn[4], const V3 fe[4], V3& xc, V3 dx[6],
                                                           V3 dxf[6]) {
-  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+  const double r0 = radius_uniform(G, k), r1 = radius_uniform(G, k + 1);
   const double rs = 0.125 * (r0 + r1);
   xc = rs * cc;
 #pragma unroll
@@ -126,12 +126,12 @@ __host__ __device__ __forceinline__ void stencil_geometry(const GeomRef& G, cons
   dxf[0] = xf0 - xc;
   dxf[1] = xf1 - xc;
   if (k > 0) {
-    dx[0] = (0.125 * (gld(G.r, k - 1) + r0) - rs) * cc;
+    dx[0] = (0.125 * (radius_uniform(G, k - 1) + r0) - rs) * cc;
   } else {
     dx[0] = ghost_centre(xc, (r0 * r0) * sr, xf0) - xc;
   }
   if (k + 1 < g.Nr) {
-    dx[1] = (0.125 * (r1 + gld(G.r, k + 2)) - rs) * cc;
+    dx[1] = (0.125 * (r1 + radius_uniform(G, k + 2)) - rs) * cc;
   } else {
     dx[1] = ghost_centre(xc, (r1 * r1) * sr, xf1) - xc;
   }
@@ -297,7 +297,7 @@ struct FusedWG {
     // the west face of an inner lane, the shared face of a ring lane: its
     // centroid offset, rs_k times the item's constant (indexing dxf by a
     // run-time face would put the array in scratch memory)
-    const V3 dw = (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * st.fw;
+    const V3 dw = (0.125 * (radius_uniform(G, k) + radius_uniform(G, k + 1))) * st.fw;
     T qB[9], qT[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
@@ -331,7 +331,7 @@ struct FusedWG {
     st.bad = st.bad || !physical(qB);
     // the bottom face closes layer k - 1 (stored when the chunk owns it)
     {
-      const double r0 = gld(G.r, k);
+      const double r0 = radius_uniform(G, k);
       V3 S = (r0 * r0) * st.sr;
       if (k == 0) S = mk(-S.x, -S.y, -S.z);  // the inner boundary face, outward
       T F[9];
@@ -363,7 +363,7 @@ struct FusedWG {
       u[0] = P0[0];
       for (int d = 1; d < 4; ++d) u[d] = P0[0] * P0[d];
       for (int v = 4; v < 9; ++v) u[v] = T(0.0);
-      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      const double r0 = radius_uniform(G, k), r1 = radius_uniform(G, k + 1);
       gravity_source(u, xc, (r1 * r1 * r1 - r0 * r0 * r0) * st.om * (1.0 / 3.0), a.d.pr.G, src);
       for (int v = 0; v < 9; ++v) st.acc[v] -= src[v];
     }
@@ -386,7 +386,6 @@ struct FusedWG {
   // flux is stored signed from this lane toward its east or north neighbour.
   __host__ __device__ static void flux(const MarchArgs& a, const FTile& tm, FuState<T>& st, int t, int k,
                                        double* lds) {
-    const Shape& g = a.d.g;
     const GeomRef& G = a.d.G;
     T* L = lds_as<T>(lds);
     const int bi = st.bi, bj = st.bj;
@@ -398,7 +397,7 @@ struct FusedWG {
     if (inner || (st.role == 2 && (bi == 0 || bj == 0))) {
       const bool west = bi == 0;
       const int tn = inner ? t + 1 : west ? t + 1 : t + kFB;  // the other side's lane
-      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      const double r0 = radius_uniform(G, k), r1 = radius_uniform(G, k + 1);
       const V3 S = (0.5 * (r1 * r1 - r0 * r0)) * st.fa;
       const bool own = st.fown;
       T qs[9], qo[9], F[9];
@@ -419,7 +418,7 @@ struct FusedWG {
     }
     // second face: an inner lane's north face
     if (inner) {
-      const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+      const double r0 = radius_uniform(G, k), r1 = radius_uniform(G, k + 1);
       const V3 S = (0.5 * (r1 * r1 - r0 * r0)) * st.na;
       const bool own = st.nown;
       const bool ring_n = bj == tm.wj;  // the north neighbour is a ring cell: its shared-face state

@@ -101,6 +101,20 @@ __host__ __device__ __forceinline__ T* lds_as(double* lds) {
   return reinterpret_cast<T*>(lds);
 }
 
+// A launch's descriptor (no kernel writes it while one runs) read through
+// the constant address space: at a uniform address its fields become scalar
+// loads, which the vector memory counter does not track, so reading one does
+// not wait for the loads and stores in flight (a vector load of the field
+// would: the compiler cannot prove that the kernel's own stores leave the
+// descriptor alone).
+__host__ __device__ __forceinline__ const MarchArgs& constant_args(const MarchArgs* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const MarchArgs*)reinterpret_cast<const __attribute__((address_space(4))) MarchArgs*>(uniform_address(p));
+#else
+  return *p;
+#endif
+}
+
 template <class T>
 __host__ __device__ __forceinline__ void load_prims(const MarchArgs& a, int64_t c, T P[9]) {
   const int64_t nc = a.d.g.ncells;
@@ -354,7 +368,7 @@ struct GradWG {
     const T* L = lds_as<T>(lds);
     const double* cs = lds + kCs;
     const int ti = t % kTI, tj = t / kTI;
-    const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+    const double r0 = radius_uniform(G, k), r1 = radius_uniform(G, k + 1);
     const double rs = 0.125 * (r0 + r1);
     const V3 xc = rs * st.cc;
     // geometry: neighbour offsets and face-centroid offsets
@@ -367,13 +381,13 @@ struct GradWG {
       dxf[0] = xf0 - xc;
       dxf[1] = xf1 - xc;
       if (k > 0) {
-        dx[0] = (0.125 * (gld(G.r, k - 1) + r0) - rs) * st.cc;
+        dx[0] = (0.125 * (radius_uniform(G, k - 1) + r0) - rs) * st.cc;
       } else {
         const V3 S = (r0 * r0) * cg3(G, CG_SR, st.col);
         dx[0] = ghost_centre(xc, S, xf0) - xc;
       }
       if (k + 1 < g.Nr) {
-        dx[1] = (0.125 * (r1 + gld(G.r, k + 2)) - rs) * st.cc;
+        dx[1] = (0.125 * (r1 + radius_uniform(G, k + 2)) - rs) * st.cc;
       } else {
         const V3 S = (r1 * r1) * cg3(G, CG_SR, st.col);
         dx[1] = ghost_centre(xc, S, xf1) - xc;

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kFL, 1) void fused_march_kernel(EnsembleLaunch e) {
     if (q >= e.total) break;
     const int64_t w = e.perm ? fused_uniform(e.perm[q]) : q;
     const int inst = e.n > 1 ? int(fused_uniform(fused_find_instance(e.item_off, e.n, w))) : 0;
-    const MarchArgs& a = e.args[inst];
+    const MarchArgs& a = constant_args(e.args + inst);
     FTile tm;
     fused_tile_of(a.d.g, e.kc, e.n > 1 ? w - e.item_off[inst] : w, tm);
     __syncthreads();  // the previous item's LDS reads are done

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kNT, (MarchOccupancy<T, Flux>::value)) void march_e
     if (q >= e.total) break;
     const int64_t w = e.perm ? uniform(e.perm[q]) : q;
     const int inst = e.n > 1 ? int(uniform(find_instance(e.item_off, e.n, w))) : 0;
-    const MarchArgs& a = e.args[inst];
+    const MarchArgs& a = constant_args(e.args + inst);
     TileMap tm;
     tile_of_logical(a.d.g, e.n > 1 ? w - e.item_off[inst] : w, tm, e.kc);
     __syncthreads();  // the previous item's LDS reads are done

@@ -176,6 +176,10 @@ extern "C" {
 // to first.
 void host_set_lane_order(int reverse) { g_reverse = reverse != 0; }
 
+// The join of the two address halves behind the kernels' uniform (scalar)
+// loads, as readfirstlane returns them.
+uint64_t host_join_address(int hi, int lo) { return join_address(hi, lo); }
+
 // The dual Barth-Jespersen limited gradient of one variable (limited_grad
 // with T = Dual) for given least-squares weights W (6 x 3, so that the
 // unlimited gradient is sum_n W_n (q_n - q_c)), face offsets dxf (6 x 3),

@@ -293,3 +293,32 @@ def test_dual_limiter_choice_matches_the_oracle_scan(harness, tmp_path):
     assert np.abs(got[:, :3] - val.numpy()).max() <= 1e-14 * max(1.0, float(np.abs(val.numpy()).max()))
     err_t = np.abs(got[:, 3:] - tan.numpy()) / np.maximum(np.abs(tan.numpy()).max(1, keepdims=True), 1e-300)
     assert err_t.max() <= 1e-13, f"tangent differs: {err_t.max():.2e} in case {int(err_t.max(1).argmax())}"
+
+
+JOIN_RUNNER = r'''
+import ctypes
+L = ctypes.CDLL({lib!r})
+L.host_join_address.restype = ctypes.c_uint64
+L.host_join_address.argtypes = [ctypes.c_int, ctypes.c_int]
+for hi, lo in {pairs!r}:
+    print(L.host_join_address(hi, lo))
+'''
+
+
+def test_uniform_address_halves_join_as_unsigned(harness, tmp_path):
+    """The kernels read a launch descriptor and the layer radii with scalar
+    loads at an address rebuilt from two readfirstlane halves, which are
+    signed 32-bit ints.  Joined as signed, a low half with bit 31 set turned
+    the high half into 0xffffffff, an address outside every allocation (a
+    GPU memory fault that came and went with the allocation's address)."""
+    lib, pre = harness
+    pairs = [(0x7F, -0x7FFFE000), (0x7FFF, -1), (0x1234, 0x7FFFFFFF), (0, -0x80000000), (0x7F, 0x1000)]
+    script = tmp_path / "join.py"
+    script.write_text(JOIN_RUNNER.format(lib=lib, pairs=pairs))
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stderr[-4000:]
+    got = [int(x) for x in r.stdout.split()]
+    want = [((hi & 0xFFFFFFFF) << 32) | (lo & 0xFFFFFFFF) for hi, lo in pairs]
+    assert got == want
+    assert all(g >> 32 == hi & 0xFFFFFFFF for g, (hi, _) in zip(got, pairs))
