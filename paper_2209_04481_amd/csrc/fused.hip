@@ -15,8 +15,18 @@
 
 namespace cfv {
 
+// the same descriptor, but a value the compiler cannot follow: reads through
+// it are not hoisted out of the layer loop (the descriptor's fields would
+// otherwise stay in scalar registers across the whole item and spill)
+__device__ __forceinline__ const MarchArgs& per_layer(const MarchArgs& a) {
+  const MarchArgs* p = &a;
+  asm volatile("" : "+s"(p));
+  return constant_args(p);
+}
+
 template <class T>
-__device__ __forceinline__ void fused_march_tile(const MarchArgs& a, const FTile& tm, double* lds) {
+__device__ __forceinline__ void fused_march_tile(const MarchArgs& a0, const FTile& tm, double* lds) {
+  const MarchArgs& a = a0;
   const int t = threadIdx.x;
   const Shape& g = a.d.g;
   const int kb = tm.k0 > 0 ? tm.k0 - 1 : 0;
@@ -25,6 +35,7 @@ __device__ __forceinline__ void fused_march_tile(const MarchArgs& a, const FTile
   FusedWG<T>::init(a, tm, st, t, kb, lds);
   for (int k = FusedWG<T>::first_publish(kb); k < kb; ++k) FusedWG<T>::publish_block(a, st, t, k, lds);
   for (int k = kb; k <= ke; ++k) {
+    const MarchArgs& a = per_layer(a0);
     const int mode = k < tm.k0 ? 1 : k >= tm.k1 ? 2 : 0;
     FusedWG<T>::publish(a, tm, st, t, k, lds);
     __syncthreads();

@@ -28,14 +28,24 @@
 namespace cfv {
 
 // --------------------------------------------------------------- device glue
+// the same descriptor, but a value the compiler cannot follow: reads through
+// it are not hoisted out of the layer loop (the descriptor's fields would
+// otherwise stay in scalar registers across the whole item and spill)
+__device__ __forceinline__ const MarchArgs& per_layer(const MarchArgs& a) {
+  const MarchArgs* p = &a;
+  asm volatile("" : "+s"(p));
+  return constant_args(p);
+}
+
 // One (tile, chunk) of each pass; the single-instance kernels run one per
 // workgroup, the ensemble kernels (ensemble.hip) loop over a queue of them.
 template <class T, bool Faces = false>
-__device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMap& tm, double* lds) {
+__device__ __forceinline__ void grad_march_tile(const MarchArgs& a0, const TileMap& tm, double* lds) {
   const int t = threadIdx.x;
   GState<T> st;
-  GradWG<T>::init(a, tm, st, t, lds);
+  GradWG<T>::init(a0, tm, st, t, lds);
   for (int k = GradWG<T>::first_layer(tm); k < tm.k1; ++k) {
+    const MarchArgs& a = per_layer(a0);
     // (the second wavefront also fills the plane's ring of out-of-tile
     // neighbours: in the dual pass inside publish)
     GradWG<T>::publish(a, tm, st, t, k, lds);
@@ -53,12 +63,13 @@ __device__ __forceinline__ void grad_march_tile(const MarchArgs& a, const TileMa
 }
 
 template <class T>
-__device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMap& tm, double* lds) {
+__device__ __forceinline__ void flux_march_tile(const MarchArgs& a0, const TileMap& tm, double* lds) {
   const int t = threadIdx.x;
   FState<T> st;
-  FluxWG<T>::init(a, tm, st, t);
-  const int kl = FluxWG<T>::last_layer(a.d.g, tm);
+  FluxWG<T>::init(a0, tm, st, t);
+  const int kl = FluxWG<T>::last_layer(a0.d.g, tm);
   for (int k = FluxWG<T>::first_layer(tm); k <= kl; ++k) {
+    const MarchArgs& a = per_layer(a0);
     // (the second wavefront also loads the ring of out-of-tile neighbour
     // states)
     FluxWG<T>::states(a, tm, st, t, k, lds);
@@ -70,7 +81,7 @@ __device__ __forceinline__ void flux_march_tile(const MarchArgs& a, const TileMa
     // buffers that only the face phase (before the barrier above) reads
     FluxWG<T>::accumulate(a, tm, st, t, k, lds);
   }
-  FluxWG<T>::finish(a, tm, st, t);
+  FluxWG<T>::finish(a0, tm, st, t);
 }
 
 // ----------------------------------------------------------------- ensemble
