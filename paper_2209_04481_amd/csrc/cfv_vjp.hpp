@@ -62,10 +62,6 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
   // rows of cells in the workgroup's window [c0, c0 + kVBlock) come from LDS
   // (one flat load serves either memory: the select stays a single load)
-  auto Wr = [&](int row, int64_t id) -> double {
-    const int64_t l = id - c0;
-    return (l >= 0 && l < kVBlock) ? lW[row * kVBlock + l] : W[row * nc + id];
-  };
   auto wr = [&](int row, int64_t id) -> double {
     const int64_t l = id - c0;
     return (l >= 0 && l < kVBlock) ? lw[row * kVBlock + l] : w[row * nc + id];
@@ -78,7 +74,8 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   // the LDS window holds copies of global rows, so any row may also be read
   // from global memory: the cell itself always from LDS, radial neighbours
   // (never in the window once a layer has 256 cells) always from global
-  // memory, angular ones from wherever they are
+  // memory, angular ones from wherever they are in the face loop and from
+  // global memory in the variable loop (below)
   const int lc = int(c - c0);
   double Pc[9], wc[9];
 #pragma unroll
@@ -176,13 +173,16 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   // adjoint; contributions to the six neighbours are stored at once.  The
   // neighbours' values of variable v + 2 are loaded before variable v's
   // arithmetic, so the loads of later variables are in flight while earlier
-  // ones compute (one wait per variable had left them exposed).
+  // ones compute (one wait per variable had left them exposed).  They are
+  // global loads even inside the window (cache hits there): a value from a
+  // flat load can only be waited for together with every memory access in
+  // flight, the prefetched ones included.
   auto neighbour_values = [&](int v, double q[6]) {
 #pragma unroll
     for (int lf = 0; lf < 6; ++lf) {
       if (lf == 0 && bin) q[lf] = qGin[v];
       else if (lf == 1 && bout) q[lf] = qGout[v];
-      else q[lf] = lf < 2 ? gld(W, v * nc + nid[lf]) : Wr(v, nid[lf]);
+      else q[lf] = gld(W, v * nc + nid[lf]);
     }
   };
   double qn1[6], qn2[6];  // variables v + 1 and v + 2
