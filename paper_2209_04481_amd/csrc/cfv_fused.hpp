@@ -372,7 +372,7 @@ struct FusedWG {
       st.bad = st.bad || !physical(gout);
       V3 S, xf;
       bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
+      canon_face<true>(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
       T F[9];
       rusanov(qT, gout, S, F, a.d.pr);
       for (int v = 0; v < 9; ++v) st.acc[v] += F[v];

@@ -619,13 +619,13 @@ struct FluxWG {
     cons_to_prim(u, P, a.d.pr.gamma);
     if (rl) ring_store(t - kNT / 4, rq, lds);
     load_grad(a, c, Gr);
-    const V3 xc = cell_centre(G, g, st.p, k, st.j, st.i);
+    const V3 xc = cell_centre<true>(G, g, st.p, k, st.j, st.i);
 
     // radial face below: k - 1/2 (owner k-1), or the inner boundary face
     {
       V3 S, xf;
       bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
+      canon_face<true>(G, g, st.p, k, st.j, st.i, 0, Nbr{}, 0, S, xf, own);
       T qb[9], F[9];
       recon(P, Gr, xf - xc, qb);
       st.bad = st.bad || !physical(qb);
@@ -648,14 +648,14 @@ struct FluxWG {
     // gravity source
     {
       T src[9];
-      gravity_source(u, xc, cell_volume(G, g, st.p, k, st.j, st.i), a.d.pr.G, src);
+      gravity_source(u, xc, cell_volume<true>(G, g, st.p, k, st.j, st.i), a.d.pr.G, src);
       for (int v = 0; v < 9; ++v) st.acc[v] -= src[v];
     }
     // top face state (and the outer boundary face)
     {
       V3 S, xf;
       bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
+      canon_face<true>(G, g, st.p, k, st.j, st.i, 1, Nbr{}, 0, S, xf, own);
       recon(P, Gr, xf - xc, st.qtop);
       st.bad = st.bad || !physical(st.qtop);
       if (k == g.Nr - 1) {
@@ -672,7 +672,7 @@ struct FluxWG {
     for (int q = 0; q < 4; ++q) {
       V3 S, xf;
       bool own;
-      canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
+      canon_face<true>(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
       T s[9];
       recon(P, Gr, xf - xc, s);
       st.bad = st.bad || !physical(s);
@@ -705,7 +705,7 @@ struct FluxWG {
         const int q = h == 0 ? 1 : 3;
         V3 S, xf;
         bool own;
-        canon_face(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
+        canon_face<true>(G, g, st.p, k, st.j, st.i, 2 + q, Nbr{}, 0, S, xf, own);
         T qs[9], qo[9], F[9];
         if (h == 0) {
           for (int v = 0; v < 9; ++v) qs[v] = st.q3[v];
@@ -736,7 +736,7 @@ struct FluxWG {
         const int tc = etj * kTI + eti;
         V3 S, xf;
         bool own;
-        canon_face(G, g, tm.p, k, tm.j0 + etj, tm.i0 + eti, 2 + q, Nbr{}, 0, S, xf, own);
+        canon_face<true>(G, g, tm.p, k, tm.j0 + etj, tm.i0 + eti, 2 + q, Nbr{}, 0, S, xf, own);
         T qs[9], qo[9], F[9];
         for (int v = 0; v < 9; ++v) {
           qs[v] = Sb[((south ? 9 : 0) + v) * kNT + tc];

@@ -179,12 +179,20 @@ __host__ __device__ __forceinline__ V3 cg3(const GeomRef& G, int comp, int64_t c
   return mk(gld(G.cg, comp * G.ncol + col), gld(G.cg, (comp + 1) * G.ncol + col), gld(G.cg, (comp + 2) * G.ncol + col));
 }
 
-__host__ __device__ __forceinline__ V3 cell_centre(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  return (0.125 * (gld(G.r, k) + gld(G.r, k + 1))) * cg3(G, CG_CSUM, column_of(g, p, j, i));
+// r_k; kUniformK: k is the same in every lane (radius_uniform)
+template <bool kUniformK = false>
+__host__ __device__ __forceinline__ double radius(const GeomRef& G, int k) {
+  return kUniformK ? radius_uniform(G, k) : gld(G.r, k);
 }
 
+template <bool kUniformK = false>
+__host__ __device__ __forceinline__ V3 cell_centre(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
+  return (0.125 * (radius<kUniformK>(G, k) + radius<kUniformK>(G, k + 1))) * cg3(G, CG_CSUM, column_of(g, p, j, i));
+}
+
+template <bool kUniformK = false>
 __host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const Shape& g, int p, int k, int j, int i) {
-  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+  const double r0 = radius<kUniformK>(G, k), r1 = radius<kUniformK>(G, k + 1);
   return (r1 * r1 * r1 - r0 * r0 * r0) * gld(G.cg, CG_OMEGA * G.ncol + column_of(g, p, j, i)) * (1.0 / 3.0);
 }
 
@@ -192,10 +200,11 @@ __host__ __device__ __forceinline__ double cell_volume(const GeomRef& G, const S
 // owner's vector area (pointing from the owner to the other side), the
 // owner's centroid, and whether (p,k,j,i) is the owner.  The owner of a face
 // is the cell with the lower index, or the interior cell on the boundary.
+template <bool kUniformK = false>
 __host__ __device__ __forceinline__ void canon_face_col(const GeomRef& G, int64_t col, int k, int lf, V3& S, V3& xf,
                                                         bool& owner) {
   if (lf < 2) {
-    const double r = gld(G.r, k + lf);
+    const double r = radius<kUniformK>(G, k + lf);
     const V3 sr = cg3(G, CG_SR, col);
     S = (r * r) * sr;
     xf = r * cg3(G, CG_XR, col);
@@ -204,15 +213,16 @@ __host__ __device__ __forceinline__ void canon_face_col(const GeomRef& G, int64_
     return;
   }
   const int q = lf - 2;
-  const double r0 = gld(G.r, k), r1 = gld(G.r, k + 1);
+  const double r0 = radius<kUniformK>(G, k), r1 = radius<kUniformK>(G, k + 1);
   S = (0.5 * (r1 * r1 - r0 * r0)) * cg3(G, CG_ANG + 6 * q, col);
   xf = (0.25 * (r0 + r1)) * cg3(G, CG_ANG + 6 * q + 3, col);
   owner = (gld(G.cn, (4 + q) * G.ncol + col) >> 8) != 0;
 }
 
+template <bool kUniformK = false>
 __host__ __device__ __forceinline__ void canon_face(const GeomRef& G, const Shape& g, int p, int k, int j, int i, int lf,
                                            const Nbr&, int64_t, V3& S, V3& xf, bool& owner) {
-  canon_face_col(G, column_of(g, p, j, i), k, lf, S, xf, owner);
+  canon_face_col<kUniformK>(G, column_of(g, p, j, i), k, lf, S, xf, owner);
 }
 
 // vector area pointing out of cell (p,k,j,i) and centroid of its face lf
