@@ -509,6 +509,7 @@ struct FState {
   T q3[9], q5[9];
   bool bad;   // a face state of this column met a non-positive density or pressure
   int64_t ebase;  // ring threads: the slot's state in the edge buffer at layer 0 (-1: no slot)
+  int own_ws;  // bit 0 (1): the cell owns its west (south) face
 };
 
 template <class T>
@@ -568,6 +569,12 @@ struct FluxWG {
     st.bad = false;
     for (int v = 0; v < 9; ++v) st.qtop[v] = T(0.0);
     st.ebase = -1;
+    st.own_ws = 0;
+    if (st.act) {  // the west and south faces' orientations, once per item
+      const int64_t col = column_of(g, st.p, st.j, st.i);
+      st.own_ws = int((gld(a.d.G.cn, 4 * a.d.G.ncol + col) >> 8) != 0) |
+                  int((gld(a.d.G.cn, 6 * a.d.G.ncol + col) >> 8) != 0) << 1;
+    }
     if (t >= kNT / 4 && t < kNT / 4 + kRing) {  // the ring slot's source in the edge buffer, once per item
       int ti, tj, q;
       int64_t ncol;
@@ -752,18 +759,17 @@ struct FluxWG {
                                              double* lds) {
     if (!st.act) return;
     const Shape& g = a.d.g;
-    const GeomRef& G = a.d.G;
     const T* Fb = lds_as<T>(lds) + 18 * kNT;
     const T* Eb = lds_as<T>(lds) + kEdgeOff;
     const int ti = t % kTI, tj = t / kTI;
     if (ti > 0) {
-      const double sg = (gld(G.cn, 4 * G.ncol + st.col) >> 8) != 0 ? 1.0 : -1.0;  // the west face's orientation
+      const double sg = (st.own_ws & 1) ? 1.0 : -1.0;  // the west face's orientation
       for (int v = 0; v < 9; ++v) st.acc[v] += Fb[v * kNT + t - 1] * sg;
     } else {
       for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + 16 + tj];
     }
     if (tj > 0) {
-      const double sg = (gld(G.cn, 6 * G.ncol + st.col) >> 8) != 0 ? 1.0 : -1.0;  // the south face's
+      const double sg = (st.own_ws & 2) ? 1.0 : -1.0;  // the south face's
       for (int v = 0; v < 9; ++v) st.acc[v] += Fb[(9 + v) * kNT + t - kTI] * sg;
     } else {
       for (int v = 0; v < 9; ++v) st.acc[v] += Eb[v * kEdge + ti];
