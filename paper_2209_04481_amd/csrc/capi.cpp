@@ -35,8 +35,10 @@ int dots_noalloc_max_vectors();
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_fused_ensemble(const EnsembleLaunch& e, hipStream_t s, KernelTimer* t);
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t);
+                      double* A, MarchArgs* slot, int kc, const int64_t* bw, int64_t nbw, hipStream_t s,
+                      KernelTimer* t);
 int64_t vjp_workspace_doubles(const Shape& g);
+int64_t adjoint_boundary_windows(const Shape& g, int64_t* out);
 hipError_t launch_div_dev(int64_t n, const double* den, const double* x, double* y, hipStream_t s);
 hipError_t launch_add_diag(int64_t nc, const double* diag, const double* x, double* w, hipStream_t s);
 hipError_t launch_div_diag(int64_t nc, const double* diag, const double* x, double* y, hipStream_t s);
@@ -106,6 +108,8 @@ struct cfv_ctx {
   double* Wd = nullptr;    // 36 ncells: their tangents
   double* E = nullptr;     // dual march: tile-edge face states (edge_buffer_doubles)
   double* A = nullptr;     // adjoint workspace
+  int64_t* dbwin = nullptr;  // the adjoint windows holding boundary-layer cells
+  int64_t nbwin = 0;
   double* part = nullptr;  // reduction partials
   int part_vectors = 0;
   cfv::MarchArgs* slot = nullptr;  // descriptor of the current march launch
@@ -315,6 +319,12 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
     cfv_ctx_destroy(c);
     return st;
   }
+  std::vector<int64_t> bwin(size_t(cfv::adjoint_boundary_windows(g->g, nullptr)));
+  c->nbwin = cfv::adjoint_boundary_windows(g->g, bwin.data());
+  if ((st = dmalloc(&c->dbwin, bwin.size() > 0 ? bwin.size() : 1))) {
+    cfv_ctx_destroy(c);
+    return st;
+  }
   hipError_t e = hipMemcpy(c->dcg, g->cg.data(), g->cg.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dcn, g->cn.data(), g->cn.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->dr, g->r.data(), g->r.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -323,6 +333,8 @@ cfv_status cfv_ctx_create(const cfv_grid* g, const cfv_params* prm, cfv_ctx** ou
   if (e == hipSuccess) e = hipMemset(c->dflag, 0, sizeof(unsigned));
   if (e == hipSuccess)
     e = hipMemcpy(c->dftab, g->ftab.data(), g->ftab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !bwin.empty())
+    e = hipMemcpy(c->dbwin, bwin.data(), bwin.size() * sizeof(int64_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     cfv_ctx_destroy(c);
     return hip_fail(e, "uploading grid tables");
@@ -340,6 +352,7 @@ void cfv_ctx_destroy(cfv_ctx* c) {
   if (c->slot) (void)hipFree(c->slot);
   if (c->dflag) (void)hipFree(c->dflag);
   if (c->dftab) (void)hipFree(c->dftab);
+  if (c->dbwin) (void)hipFree(c->dbwin);
   double* kb[] = {c->kry_V, c->kry_w, c->kry_r, c->kry_d, c->kry_s, c->kry_x,
                   c->dir_u, c->dir_g, c->dir_b, c->dir_s, c->st_u, c->st_m};
   for (double* b : kb)
@@ -391,7 +404,8 @@ cfv_status cfv_jvp(cfv_ctx* c, const double* U, const double* v, const double* d
 cfv_status cfv_vjp(cfv_ctx* c, const double* U, const double* w, double* gU, double* gbr, hipStream_t s) {
   if (cfv_status st = check_ctx(c)) return st;
   if (!U || !w || !gU) return fail(CFV_ERR_ARG, "null state, weights or output");
-  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), U, w, gU, gbr, c->W, c->A, c->slot, c->march_chunk(true), c->dbwin, c->nbwin, s,
+                          c->tm()));
   return CFV_OK;
 }
 
@@ -494,7 +508,8 @@ static cfv_status ensure_krylov(cfv_ctx* c, int m) {
 static cfv_status apply_operator(cfv_ctx* c, const double* U, const double* diag, int transpose, const double* x,
                                  double* w, hipStream_t s) {
   if (transpose) {
-    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
+    CFV_HIP(cfv::launch_vjp(c->dev(), U, x, w, nullptr, c->W, c->A, c->slot, c->march_chunk(true), c->dbwin, c->nbwin,
+                            s, c->tm()));
   } else {
     cfv::MarchArgs a{c->dev(), U, x, nullptr, c->W, c->Wd, nullptr, w};
     a.E = c->E;
@@ -765,10 +780,12 @@ cfv_status cfv_vjp_dir(cfv_ctx* c, const double* U, const double* w, const doubl
   // + side into the outputs, - side into the workspace
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, gU2, gbr2, c->W, c->A, c->slot, c->march_chunk(true), c->dbwin,
+                          c->nbwin, s, c->tm()));
   CFV_HIP(hipMemcpyAsync(c->dir_u, U, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
   CFV_HIP(cfv::launch_axpby(n, -h, x, 1.0, c->dir_u, s));
-  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot, c->march_chunk(true), s, c->tm()));
+  CFV_HIP(cfv::launch_vjp(c->dev(), c->dir_u, w, c->dir_g, gbr2 ? gbm : nullptr, c->W, c->A, c->slot,
+                          c->march_chunk(true), c->dbwin, c->nbwin, s, c->tm()));
   const double ih = 0.5 / h;
   CFV_HIP(cfv::launch_axpby(n, -ih, c->dir_g, ih, gU2, s));
   if (gbr2) CFV_HIP(cfv::launch_axpby(nb, -ih, gbm, ih, gbr2, s));

@@ -14,6 +14,17 @@ inline int64_t vjp_workspace_size(const Shape& g) { return int64_t(63 + 54) * g.
 
 constexpr int kVBlock = 256;
 
+// Whether the adjoint's window of cells [c0, c0 + kVBlock) holds a cell of
+// a boundary layer (k = 0 or Nr - 1): cells run through a panel's layers in
+// order, so only the window's first and last cells need looking at.
+__host__ __device__ inline bool adjoint_window_has_boundary(const Shape& g, int64_t c0) {
+  const int64_t c1 = (c0 + kVBlock < g.ncells ? c0 + kVBlock : g.ncells) - 1;
+  const int64_t NN = int64_t(g.N) * g.N, per = NN * g.Nr;
+  const int64_t p0 = c0 / per, p1 = c1 / per;
+  const int k0 = int((c0 - p0 * per) / NN), k1 = int((c1 - p1 * per) / NN);
+  return p0 != p1 || k0 == 0 || k1 == g.Nr - 1;
+}
+
 
 // Adjoint of the ghost law for the ghost of boundary cell (p,k,j,i) across
 // face lf: accumulates (dqG/dqI)^T qGb into qIb and returns (dqG/dbr)^T qGb,
@@ -51,6 +62,9 @@ __host__ __device__ __forceinline__ double ghost_adjoint(const DevGrid& d, int p
 // from global memory.  A neighbour's state on a shared face is its stored
 // face state: 9 values instead of its 36 primitives and gradients.  Most of
 // this pass's time is neighbour loads at one wavefront per SIMD.
+// kBoundary false: the cell is in neither boundary layer (the caller knows),
+// so the ghost states and their code are left out.
+template <bool kBoundary>
 __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __restrict__ w,
                                              const double* __restrict__ W, const double* __restrict__ Q,
                                              double* __restrict__ A, double* __restrict__ Gg, int64_t c,
@@ -58,7 +72,7 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   const int64_t nc = d.g.ncells;
   int p, k, j, i;
   decode(d.g, c, p, k, j, i);
-  const bool bin = k == 0, bout = k == d.g.Nr - 1;
+  const bool bin = kBoundary && k == 0, bout = kBoundary && k == d.g.Nr - 1;
   const V3 xc = cell_centre(d.G, d.g, p, k, j, i);
   // rows of cells in the workgroup's window [c0, c0 + kVBlock) come from LDS
   // (one flat load serves either memory: the select stays a single load)
@@ -90,6 +104,9 @@ __host__ __device__ inline void adjoint_cell(const DevGrid& d, const double* __r
   // this cell's side (and the ghost side); the face loop is unrolled so that
   // per-face arrays are indexed statically and faces can overlap
   double qGin[9], qGout[9];
+  if (!kBoundary)  // no ghost in an interior window: the ghost paths below are never taken
+#pragma unroll
+    for (int v = 0; v < 9; ++v) qGin[v] = qGout[v] = 0.0;
   if (bin) {
     V3 xG;
     ghost_prims(d, p, k, j, i, 0, Pc, xc, brc, qGin, xG);

@@ -25,14 +25,33 @@ namespace cfv {
 
 int64_t vjp_workspace_doubles(const Shape& g) { return vjp_workspace_size(g); }
 
+// the adjoint windows that hold a boundary-layer cell, in order (out: room
+// for all of them, or null to count)
+int64_t adjoint_boundary_windows(const Shape& g, int64_t* out) {
+  int64_t n = 0;
+  for (int64_t b = 0; b * kVBlock < g.ncells; ++b)
+    if (adjoint_window_has_boundary(g, b * kVBlock)) {
+      if (out) out[n] = b;
+      ++n;
+    }
+  return n;
+}
+
+// kBoundary false: every window, those holding a boundary-layer cell left
+// out; true: the windows listed in bw (their windows, each once or more: a
+// window's rows are written, not accumulated, so a repeat writes the same)
+template <bool kBoundary>
 __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double* __restrict__ w,
                                                           const double* __restrict__ W, const double* __restrict__ Q,
-                                                          double* __restrict__ A, double* __restrict__ Gg) {
+                                                          double* __restrict__ A, double* __restrict__ Gg,
+                                                          const int64_t* __restrict__ bw) {
   __shared__ double lW[63 * kVBlock];  // primitives (9 rows), then the face states (54)
   __shared__ double lw[9 * kVBlock];
   const DevGrid& d = first_kernel_arg<DevGrid>();
   const int64_t nc = d.g.ncells;
-  const int64_t c0 = int64_t(blockIdx.x) * kVBlock, c = c0 + threadIdx.x;
+  const int64_t c0 = (kBoundary ? gld(bw, int64_t(blockIdx.x)) : int64_t(blockIdx.x)) * kVBlock;
+  if (!kBoundary && adjoint_window_has_boundary(d.g, c0)) return;  // the same in every lane
+  const int64_t c = c0 + threadIdx.x;
   if (c < nc) {
     // every load of the window issued before the first LDS store (one memory
     // latency for the 72 rows, not one per batch of rows)
@@ -49,7 +68,7 @@ __global__ __launch_bounds__(kVBlock) void adjoint_kernel(DevGrid, const double*
     for (int r = 0; r < 9; ++r) lw[r * kVBlock + threadIdx.x] = t[63 + r];
   }
   __syncthreads();
-  if (c < nc) adjoint_cell(d, w, W, Q, A, Gg, c, lW, lw, c0);
+  if (c < nc) adjoint_cell<kBoundary>(d, w, W, Q, A, Gg, c, lW, lw, c0);
 }
 
 // Per boundary column: the ghost states' adjoints through the boundary laws
@@ -71,7 +90,8 @@ __global__ __launch_bounds__(kVBlock) void gather_kernel(DevGrid d, const double
 }
 
 hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double* gU, double* gbr, double* W,
-                      double* A, MarchArgs* slot, int kc, hipStream_t s, KernelTimer* t) {
+                      double* A, MarchArgs* slot, int kc, const int64_t* bw, int64_t nbw, hipStream_t s,
+                      KernelTimer* t) {
   const int64_t nc = d.g.ncells;
   const dim3 grid(unsigned((nc + kVBlock - 1) / kVBlock));
   // pass 1: the forward gradient march writes the primitives (rows 0..8 of
@@ -83,8 +103,10 @@ hipError_t launch_vjp(const DevGrid& d, const double* U, const double* w, double
   hipError_t e = launch_march_grad(fa, slot, kc, s, t);
   if (e != hipSuccess) return e;
   {
+    // interior windows, then those with boundary-layer cells (bw[nbw])
     TimedScope ts(t, "adjoint", s);
-    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(kVBlock), 0, s, d, w, W, Q, A, Gg);
+    hipLaunchKernelGGL(adjoint_kernel<false>, grid, dim3(kVBlock), 0, s, d, w, W, Q, A, Gg, bw);
+    if (nbw > 0) hipLaunchKernelGGL(adjoint_kernel<true>, dim3(unsigned(nbw)), dim3(kVBlock), 0, s, d, w, W, Q, A, Gg, bw);
   }
   {
     TimedScope ts(t, "adjoint_ghosts", s);

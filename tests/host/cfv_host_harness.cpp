@@ -258,8 +258,15 @@ int host_vjp(int N, int Nr, const double* r, const cfv_params* p, const double* 
       for (int q = 0; q < 54; ++q) lW[(9 + q) * kVBlock + t] = Q[q * nc + c0 + t];
       for (int q = 0; q < 9; ++q) lw[q * kVBlock + t] = w[q * nc + c0 + t];
     }
-    for (int t = 0; t < kVBlock && c0 + t < nc; ++t)
-      adjoint_cell(s.d, w, W.data(), Q, A.data(), Gg, c0 + t, lW.data(), lw.data(), c0);
+    // the variant the device runs for this window (interior windows leave
+    // the ghost code out)
+    const bool bnd = adjoint_window_has_boundary(g, c0);
+    for (int t = 0; t < kVBlock && c0 + t < nc; ++t) {
+      if (bnd)
+        adjoint_cell<true>(s.d, w, W.data(), Q, A.data(), Gg, c0 + t, lW.data(), lw.data(), c0);
+      else
+        adjoint_cell<false>(s.d, w, W.data(), Q, A.data(), Gg, c0 + t, lW.data(), lw.data(), c0);
+    }
   }
   // pass 3: the ghost states' adjoints through the boundary laws
   for (int64_t col = 0; col < g.nb; ++col) ghost_fold_column(s.d, W.data(), Gg, A.data(), gbr, col);
