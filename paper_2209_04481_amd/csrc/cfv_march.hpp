@@ -115,6 +115,17 @@ __host__ __device__ __forceinline__ const MarchArgs& constant_args(const MarchAr
 #endif
 }
 
+#if defined(__HIPCC__)
+// the same descriptor, but a value the compiler cannot follow: reads through
+// it are not hoisted out of the layer loop (the descriptor's fields would
+// otherwise stay in scalar registers across the whole item and spill)
+__device__ __forceinline__ const MarchArgs& per_layer(const MarchArgs& a) {
+  const MarchArgs* p = &a;
+  asm volatile("" : "+s"(p));
+  return constant_args(p);
+}
+#endif
+
 template <class T>
 __host__ __device__ __forceinline__ void load_prims(const MarchArgs& a, int64_t c, T P[9]) {
   const int64_t nc = a.d.g.ncells;

@@ -143,11 +143,6 @@ struct GeomRef {
   int64_t ncol;
 };
 
-// r_k for a layer k that is the same in every lane of the wavefront (the
-// layer of a radial march): a scalar load.  A vector load would be waited for
-// with the vector memory counter, which also counts the loads and stores in
-// flight (a march's prefetch of the next layer, its residual stores), so
-// using the radius would wait for all of them.
 // a 64-bit address from its halves as readfirstlane returns them (signed
 // 32-bit ints): each half taken as unsigned, or the low half's bit 31 would
 // spread over the high half and give an address outside any allocation
@@ -163,6 +158,11 @@ __device__ __forceinline__ uint64_t uniform_address(const void* p) {
 }
 #endif
 
+// r_k for a layer k that is the same in every lane of the wavefront (the
+// layer of a radial march): a scalar load.  A vector load would be waited for
+// with the vector memory counter, which also counts the loads and stores in
+// flight (a march's prefetch of the next layer, its residual stores), so
+// using the radius would wait for all of them.
 __host__ __device__ __forceinline__ double radius_uniform(const GeomRef& G, int k) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return *reinterpret_cast<const __attribute__((address_space(4))) double*>(uniform_address(G.r + k));

@@ -15,15 +15,6 @@
 
 namespace cfv {
 
-// the same descriptor, but a value the compiler cannot follow: reads through
-// it are not hoisted out of the layer loop (the descriptor's fields would
-// otherwise stay in scalar registers across the whole item and spill)
-__device__ __forceinline__ const MarchArgs& per_layer(const MarchArgs& a) {
-  const MarchArgs* p = &a;
-  asm volatile("" : "+s"(p));
-  return constant_args(p);
-}
-
 template <class T>
 __device__ __forceinline__ void fused_march_tile(const MarchArgs& a0, const FTile& tm, double* lds) {
   const MarchArgs& a = a0;

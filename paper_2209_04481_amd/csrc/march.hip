@@ -28,15 +28,6 @@
 namespace cfv {
 
 // --------------------------------------------------------------- device glue
-// the same descriptor, but a value the compiler cannot follow: reads through
-// it are not hoisted out of the layer loop (the descriptor's fields would
-// otherwise stay in scalar registers across the whole item and spill)
-__device__ __forceinline__ const MarchArgs& per_layer(const MarchArgs& a) {
-  const MarchArgs* p = &a;
-  asm volatile("" : "+s"(p));
-  return constant_args(p);
-}
-
 // One (tile, chunk) of each pass; the single-instance kernels run one per
 // workgroup, the ensemble kernels (ensemble.hip) loop over a queue of them.
 template <class T, bool Faces = false>
